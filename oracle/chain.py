@@ -1,0 +1,79 @@
+"""Timestep chain of the method on the CPU oracle (test infrastructure only).
+
+For n = 1..T (Section 2.3: one implicit solve per timestep, dt = 1/T; one linearisation pass,
+m~ = m^{n-1}):
+  seed:    A_s m = b_s solved by restarted GMRES from 0 (or from m^{n-1}); the first cycle's
+           basis V^n and Hessenberg matrix are kept (Section 3, Phase 1).
+  targets: each target is projected onto V^n and the result polished by GMRES to the
+           tolerance (Section 3, Phase 2); "plain" runs the same GMRES from x_base instead,
+           "direct" uses the banded LU.
+  commit:  m^n <- x for every system.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import TARGET_GALERKIN, Operator, banded_solve, gmres, project, residual, rhs
+
+
+@dataclass
+class ChainStats:
+    seed_iters: list = field(default_factory=list)
+    iters: list = field(default_factory=list)          # [step][target] polish / plain iterations
+    restarts: list = field(default_factory=list)
+    status: list = field(default_factory=list)
+    res_true: list = field(default_factory=list)
+    guess_res: list = field(default_factory=list)      # [step][target] ||b-Ax0||/||b||
+    basis_dim: list = field(default_factory=list)
+
+
+def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
+              mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000):
+    """Advance the seed and every target through `steps` (default T) timesteps.
+
+    seed_m0: (n,) initial state of the seed; target_m0: (N, n).  Returns (m_seed, m_targets,
+    stats).  With method "plain" or "direct" the seed chain is not solved.
+    """
+    dt = 1.0 / T
+    ms = np.array(seed_m0, dtype=np.float64).reshape(-1)
+    mt = np.array(target_m0, dtype=np.float64).reshape(len(target_m0), -1)
+    st = ChainStats()
+    for _ in range(T if steps is None else steps):
+        basis = None
+        if method == "project":
+            As = Operator(H, dt, g, ms)
+            bs = rhs(As, ms)
+            sr = gmres(As, bs, x0=ms if warm else None, m=m, tol=tol, keep_basis=True,
+                       max_restarts=max_restarts)
+            basis = sr
+            st.seed_iters.append(sr.iters)
+            st.basis_dim.append(sr.basis_dim)
+        it_row, rs_row, stt_row, res_row, g_row = [], [], [], [], []
+        new = np.empty_like(mt)
+        for t in range(mt.shape[0]):
+            At = Operator(H, dt, g, mt[t])
+            bt = rhs(At, mt[t])
+            xb = mt[t] if warm else None
+            if method == "direct":
+                x, s = banded_solve(At, bt)
+                it_row.append(0); rs_row.append(0); stt_row.append(s)
+                res_row.append(residual(At, bt, x)); g_row.append(np.nan)
+            else:
+                if method == "project":
+                    x0, _, _ = project(At, bt, basis.V, basis.Hbar, mode=mode, x_base=xb)
+                else:
+                    x0 = xb
+                g_row.append(residual(At, bt, x0) if x0 is not None else 1.0)
+                r = gmres(At, bt, x0=x0, m=m, tol=tol, max_restarts=max_restarts)
+                x = r.x
+                it_row.append(r.iters); rs_row.append(r.restarts); stt_row.append(r.status)
+                res_row.append(r.res_true)
+            new[t] = x
+        if basis is not None:
+            ms = basis.x
+        mt = new
+        st.iters.append(it_row); st.restarts.append(rs_row); st.status.append(stt_row)
+        st.res_true.append(res_row); st.guess_res.append(g_row)
+    return ms, mt, st
