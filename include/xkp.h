@@ -1,0 +1,174 @@
+/*
+ * xkp.h -- C ABI of the MI355X (gfx950) cross-matrix Krylov projection library (libxkp.so).
+ *
+ * The library solves, for many images at one timestep, the implicit linearised log-density
+ * Fokker-Planck systems A u = b of Lau, Na and Wan, "Efficient Score Pre-computation for
+ * Diffusion Models via Cross-Matrix Krylov Projection" (arXiv 2511.17634):
+ *   - the operator A is the five-point stencil of Section 2.3 (coefficients C_diag, C_north,
+ *     C_south, C_east, C_west built from the lagged log-density m~ and the drift f), kept
+ *     matrix-free;
+ *   - xkp_seed_build solves a seed system by restarted GMRES and keeps the orthonormal basis of
+ *     its first cycle, which spans the Krylov subspace K_k(A_seed, r0) (Section 3, Phase 1);
+ *   - xkp_target_project_solve projects each target system onto that basis, solves the small
+ *     k x k system and polishes the result with GMRES to the tolerance (Section 3, Phase 2);
+ *   - xkp_residual returns ||b - A x||_2 / ||b||_2 in FP64 for any batch of systems.
+ *
+ * Conventions shared by every call
+ *   - Grids are square: H x H, n = H*H, h = 1/H (Section 2.3 takes dx = dy = h).  Unknown p of
+ *     a grid vector is p = i*H + j, i the x (width) index, j the y (height) index: the y index
+ *     runs fastest, as in the paper's vector definition.  Values outside the grid are zero.
+ *   - Every array pointer inside a descriptor, and every descriptor array passed to a batched
+ *     call, is a DEVICE pointer owned by the caller; the library never frees them.  Scalars and
+ *     xkp_params are host values.
+ *   - Calls are asynchronous on the context's stream: they return after enqueuing work and can
+ *     be captured into a HIP graph.  Argument errors detectable on the host (null pointers,
+ *     sizes beyond the context limits) are returned synchronously before anything is enqueued.
+ *     Per-system outcomes (convergence, breakdown, singular projection, bad descriptor) are
+ *     written to the caller's device xkp_info array.
+ *   - A context is used from one host thread at a time.  Calls on one context run in stream
+ *     order; they share the context's workspace, so two contexts are needed for overlap.
+ *   - All solver arithmetic is FP64 in XKP_FP64 mode.  In XKP_MIXED mode the Krylov vectors
+ *     are still orthogonalised, rotated and checked in FP64; the projection contraction
+ *     V^T (A' V) runs as BF16 matrix-core products with FP32 accumulation.
+ */
+#ifndef XKP_H
+#define XKP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    XKP_OK = 0,            /* success / system converged                                   */
+    XKP_EINVAL = 1,        /* invalid argument or descriptor                              */
+    XKP_ENOMEM = 2,        /* device allocation failed                                    */
+    XKP_EDEVICE = 3,       /* HIP runtime error                                           */
+    XKP_ENOCONV = 4,       /* GMRES hit max_restarts; x holds the last iterate            */
+    XKP_ESINGULAR = 5,     /* projected k x k system had a zero pivot; x0 = x_base used   */
+    XKP_EUNSUPPORTED = 6   /* valid but not supported by this build (e.g. m > 64)        */
+} xkp_status;
+
+typedef enum { XKP_FP64 = 0, XKP_MIXED = 1 } xkp_precision;
+
+/* How a target is projected onto the seed basis V_k (Section 3, Phase 2). */
+typedef enum {
+    XKP_PROJ_TARGET_GALERKIN = 0, /* A_p = V_k^T A' V_k, the target's own operator          */
+    XKP_PROJ_SEED_GALERKIN = 1,   /* A_p = H_k = V_k^T A_seed V_k, the seed operator the
+                                     paper substitutes to avoid forming V^T A_i V per target */
+    XKP_PROJ_SEED_LSQ = 2,        /* alpha minimises ||V_{k+1}^T r_base - Hbar_k alpha||_2    */
+    XKP_PROJ_NONE = 3             /* no projection: plain GMRES from x_base                  */
+} xkp_proj_mode;
+
+/* One linear system of one image channel at one timestep (device-resident array element). */
+typedef struct {
+    int32_t H;            /* grid side; n = H*H unknowns                                    */
+    int32_t basis_id;     /* targets: index into the bases array of the seed basis to use  */
+    double dt;            /* time step (1/T)                                                 */
+    double g;             /* diffusion coefficient g                                         */
+    const double *mt;     /* [n] lagged log-density m~ defining the coefficients            */
+    const double *fx;     /* [n] drift x component, or NULL for f = 0                       */
+    const double *fy;     /* [n] drift y component, or NULL for f = 0                       */
+    const double *b;      /* [n] right-hand side                                            */
+    const double *x0;     /* [n] initial guess (seed) / base vector x_base (target), or NULL */
+    double *x;            /* [n] solution (output); may alias x0                            */
+} xkp_system;
+
+typedef struct {
+    int32_t m;            /* GMRES restart length = seed basis dimension, 1 <= m <= 64      */
+    int32_t max_restarts; /* restarts allowed after the first cycle                         */
+    double tol;           /* converged when ||b - A x||_2 <= tol ||b||_2 (FP64, true residual) */
+    int32_t precision;    /* xkp_precision                                                  */
+    int32_t mode;         /* xkp_proj_mode (targets)                                        */
+    int32_t batch_max_n;  /* largest n among this call's systems, or 0 for the context's
+                             max_n; smaller values select leaner kernels.  A system with more
+                             unknowns than this gets status XKP_EINVAL.                    */
+    int32_t reserved;     /* must be 0                                                      */
+} xkp_params;
+
+/* Per-system outcome, device-resident. */
+typedef struct {
+    int32_t status;       /* xkp_status of this system                                      */
+    int32_t iters;        /* Arnoldi steps (operator applications in the Krylov loop)        */
+    int32_t restarts;     /* restarts after the first cycle                                 */
+    int32_t basis_dim;    /* seed: k kept in the basis; target: k used by the projection    */
+    double res_est;       /* last Givens residual estimate, relative                        */
+    double res_true;      /* final ||b - A x||_2 / ||b||_2 computed in FP64                  */
+    double guess_res;     /* target: relative residual of the projected guess x0           */
+    double pad;
+} xkp_info;
+
+/*
+ * Seed basis buffer, caller-allocated device memory of xkp_basis_bytes(n, m) bytes, 256-byte
+ * aligned.  Layout (all offsets in bytes from the start):
+ *   [0, 256)         xkp_basis_header
+ *   [256, ...)       V: (m+1) columns of n doubles, column c at 256 + 8*c*n (orthonormal
+ *                    Arnoldi vectors v_0..v_k of the seed's first GMRES cycle; column k is
+ *                    zero after a breakdown)
+ *   then             Hbar: m columns of (m+1) doubles (column-major, leading dimension m+1),
+ *                    the unrotated Hessenberg matrix of that cycle
+ *   then             Vb: (m+1) columns of n bf16 values (XKP_MIXED copies of V, 256-aligned)
+ */
+typedef struct {
+    int32_t n, m, k, status;
+    double beta;          /* ||r0|| of the seed's first cycle                               */
+    int32_t pad[58];
+} xkp_basis_header;
+
+typedef struct xkp_ctx xkp_ctx;
+
+/* Create a context on `device` bound to `hip_stream` (a hipStream_t, or NULL for the null
+ * stream).  Workspace for up to `max_batch` concurrently solved systems of at most max_n
+ * unknowns and restart length max_m is allocated here; no later call allocates. */
+xkp_status xkp_ctx_create(xkp_ctx **ctx, int device, void *hip_stream, int32_t max_n,
+                          int32_t max_m, int32_t max_batch);
+xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
+
+/* Size in bytes of one seed basis buffer for n unknowns and restart length m. */
+size_t xkp_basis_bytes(int32_t n, int32_t m);
+
+/*
+ * Phase 1 (Section 3): solve each of the n_seeds seed systems by restarted GMRES(m) from
+ * seeds[i].x0 (NULL: zero) to params->tol, write the solution to seeds[i].x and the first
+ * cycle's basis V, Hessenberg matrix and header into the buffer bases[i].
+ *   seeds: device array of n_seeds descriptors; bases: device array of n_seeds device
+ *   pointers to buffers of xkp_basis_bytes(n, params->m); infos: device array of n_seeds.
+ * In XKP_MIXED mode a BF16 copy of V is also written.
+ */
+xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds,
+                          void *const *bases, const xkp_params *params, xkp_info *infos);
+
+/*
+ * Phase 2 (Section 3): for each target i, r_base = b - A' x_base (x_base = targets[i].x0,
+ * NULL: zero); alpha solves the projected system selected by params->mode on the basis
+ * bases[targets[i].basis_id]; x0 = x_base + V_k alpha; then GMRES(m) from x0 to params->tol.
+ * The result goes to targets[i].x.  Mode XKP_PROJ_NONE skips the projection (plain GMRES from
+ * x_base) and ignores `bases` (may be NULL).  A basis with a different n than the target, or
+ * a basis_id outside [0, n_bases), sets that target's status to XKP_EINVAL.
+ */
+xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                                    int32_t n_bases, const void *const *bases,
+                                    const xkp_params *params, xkp_info *infos);
+
+/* rel_res[i] = ||b_i - A_i x_i||_2 / ||b_i||_2 in FP64 (||r||_2 when b_i = 0), for a device
+ * array of n_sys descriptors; rel_res is a device array of n_sys doubles. */
+xkp_status xkp_residual(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, double *rel_res);
+
+/* Right-hand side of each system at the new timestep (Section 2.3):
+ *   b = m^{n-1}/dt - [(f_x)_{i+1,j} - (f_x)_{i-1,j} + (f_y)_{i,j+1} - (f_y)_{i,j-1}] / (2h)
+ * with m^{n-1} = systems[i].mt (one linearisation pass, m~ = m^{n-1}), written to the memory
+ * that systems[i].b points to (the one call that writes through b). */
+xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems);
+
+/* y_i = A_i u_i for a batch (the stencil operator alone): u = systems[i].x0, y = systems[i].x. */
+xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems);
+
+/* Static description of a status code. */
+const char *xkp_status_string(xkp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XKP_H */

@@ -1,0 +1,45 @@
+// Host-side launch interface between the C ABI (xkp_api.hip) and the kernels (xkp_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "xkp.h"
+
+namespace xkp {
+
+// Per-workgroup workspace, in doubles, for systems of at most nmax unknowns and restart m.
+struct WsLayout {
+    size_t v, ex, ey, w, stride;
+};
+WsLayout ws_layout(int nmax, int mmax);
+
+// Byte offsets inside a seed basis buffer (the layout documented in xkp.h).
+size_t basis_off_v();
+size_t basis_off_h(int n, int m);
+size_t basis_off_vb(int n, int m);
+size_t basis_bytes(int n, int m);
+
+enum GmresFlags {
+    kStartFromX = 1,   // initial guess is the descriptor's x (the projected x0)
+    kKeepBasis = 2,    // seed build: write the first cycle into bases[i]
+    kTarget = 4        // honour a status already written by the projection kernel
+};
+
+// Rows per thread the kernel variant is compiled for; a batch uses the smallest variant whose
+// capacity kNT * rmax covers its largest system.
+int rmax_for(int n);
+
+hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
+                        int nsys, xkp_params P, int flags, void *const *bases, xkp_info *infos,
+                        double *ws, WsLayout L, int nmax);
+hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
+                          int nsys, int n_bases, const void *const *bases, xkp_params P,
+                          xkp_info *infos, double *ws, WsLayout L, int nmax);
+hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
+                           int nsys, double *rel, int nmax);
+hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,
+                      int nmax);
+hipError_t launch_apply(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
+                        int nsys, int nmax);
+
+}  // namespace xkp

@@ -1,0 +1,79 @@
+"""Timestep chain of the method on the GPU, built only from libxkp calls.
+
+Per timestep n (Section 2.3: one implicit solve per image and timestep, dt = 1/T, one
+linearisation pass m~ = m^{n-1}; Section 3: seed phase then target phase):
+  xkp_build_rhs            b = m^{n-1}/dt for the seed and every target
+  xkp_seed_build           seed GMRES, first-cycle basis V^n kept       (projection only)
+  xkp_target_project_solve projection onto V^n + GMRES polish, or plain GMRES
+and the solution buffers become the next step's m^{n-1} (double buffering, no copies).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import xkp
+
+
+class Chain:
+    """Seed and targets of one grid size advanced together through the timesteps."""
+
+    def __init__(self, H, T, m, seed_m0, target_m0, g=0.5, tol=1e-8, method="project",
+                 mode="target_galerkin", warm=False, max_restarts=1000, device=0, ctx=None,
+                 precision=xkp.FP64):
+        import torch
+        self.H, self.T, self.m, self.g, self.tol = H, T, m, g, tol
+        self.n = n = H * H
+        self.method = method
+        self.dev = torch.device(f"cuda:{device}")
+        tgt = np.ascontiguousarray(np.asarray(target_m0, dtype=np.float64).reshape(-1, n))
+        self.N = N = tgt.shape[0]
+        self.ctx = ctx or xkp.Context(n, m, max(N, 1), device=device)
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.ms = [torch.tensor(np.asarray(seed_m0, dtype=np.float64).reshape(1, n), **f64),
+                   torch.empty((1, n), **f64)]
+        self.mt = [torch.tensor(tgt, **f64), torch.empty((N, n), **f64)]
+        self.bs = torch.empty((1, n), **f64)
+        self.bt = torch.empty((N, n), **f64)
+        self.bases = xkp.Bases(1, n, m, device=device)
+        dt = 1.0 / T
+        mode_id = xkp.NONE if method == "plain" else xkp.MODES[mode]
+        self.params = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
+                                         precision=precision, mode=mode_id, batch_max_n=n)
+        self.seed_desc, self.tgt_desc, self.all_desc = [], [], []
+        for par in (0, 1):
+            sd = xkp.pack_batch(H, dt, g, self.ms[par], self.bs, self.ms[1 - par],
+                                x0=self.ms[par] if warm else None)
+            td = xkp.pack_batch(H, dt, g, self.mt[par], self.bt, self.mt[1 - par],
+                                x0=self.mt[par] if warm else None, basis_id=0)
+            self.seed_desc.append(sd)
+            self.tgt_desc.append(td)
+            ad = torch.cat([sd, td])
+            ad._xkp_keep = sd._xkp_keep + td._xkp_keep
+            self.all_desc.append(ad)
+        self.info_s = self.ctx.new_infos(1)
+        self.info_t = self.ctx.new_infos(N)
+        self.step_no = 0
+
+    def step(self):
+        """Enqueue one timestep on the context's stream."""
+        par = self.step_no & 1
+        c = self.ctx
+        if self.method == "project":
+            c.build_rhs(self.all_desc[par], self.N + 1)
+            c.seed_build(self.seed_desc[par], 1, self.bases.ptrs, self.params, self.info_s)
+        else:
+            c.build_rhs(self.tgt_desc[par], self.N)
+        c.target_project_solve(self.tgt_desc[par], self.N, 1, self.bases.ptrs, self.params,
+                               self.info_t)
+        self.step_no += 1
+
+    @property
+    def seed_state(self):
+        return self.ms[self.step_no & 1][0]
+
+    @property
+    def target_state(self):
+        return self.mt[self.step_no & 1]
+
+    def infos(self):
+        return xkp.infos_to_numpy(self.info_s), xkp.infos_to_numpy(self.info_t)

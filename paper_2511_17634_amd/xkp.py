@@ -1,0 +1,236 @@
+"""ctypes binding of libxkp.so (argument marshalling only).
+
+Every step of the method runs in the HIP library; torch provides device memory (tensor data
+pointers) and the stream.  Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxkp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, EUNSUPPORTED = range(7)
+FP64, MIXED = 0, 1
+TARGET_GALERKIN, SEED_GALERKIN, SEED_LSQ, NONE = 0, 1, 2, 3
+MODES = {"target_galerkin": TARGET_GALERKIN, "seed_galerkin": SEED_GALERKIN,
+         "seed_lsq": SEED_LSQ, "none": NONE}
+
+# Device-side structs, byte-compatible with include/xkp.h.
+SYSTEM_DTYPE = np.dtype([("H", "<i4"), ("basis_id", "<i4"), ("dt", "<f8"), ("g", "<f8"),
+                         ("mt", "<u8"), ("fx", "<u8"), ("fy", "<u8"), ("b", "<u8"),
+                         ("x0", "<u8"), ("x", "<u8")])
+INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("restarts", "<i4"),
+                       ("basis_dim", "<i4"), ("res_est", "<f8"), ("res_true", "<f8"),
+                       ("guess_res", "<f8"), ("pad", "<f8")])
+HEADER_BYTES = 256
+
+
+class Params(ct.Structure):
+    _fields_ = [("m", ct.c_int32), ("max_restarts", ct.c_int32), ("tol", ct.c_double),
+                ("precision", ct.c_int32), ("mode", ct.c_int32), ("batch_max_n", ct.c_int32),
+                ("reserved", ct.c_int32)]
+
+
+class XkpError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load():
+    """Load libxkp.so; raises if it is missing (build it with paper_2511_17634_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise XkpError(f"{LIB_PATH} not found: build the HIP library first "
+                           "(python -m paper_2511_17634_amd.build)")
+        try:
+            import torch  # noqa: F401  (load torch's HIP runtime first so libxkp binds to it)
+        except ImportError:
+            pass
+        lib = ct.CDLL(LIB_PATH)
+        P = ct.c_void_p
+        lib.xkp_ctx_create.argtypes = [ct.POINTER(P), ct.c_int, P, ct.c_int32, ct.c_int32,
+                                       ct.c_int32]
+        lib.xkp_ctx_destroy.argtypes = [P]
+        lib.xkp_basis_bytes.argtypes = [ct.c_int32, ct.c_int32]
+        lib.xkp_basis_bytes.restype = ct.c_size_t
+        lib.xkp_seed_build.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P]
+        lib.xkp_target_project_solve.argtypes = [P, ct.c_int32, P, ct.c_int32, P,
+                                                 ct.POINTER(Params), P]
+        lib.xkp_residual.argtypes = [P, ct.c_int32, P, P]
+        lib.xkp_apply.argtypes = [P, ct.c_int32, P]
+        lib.xkp_build_rhs.argtypes = [P, ct.c_int32, P]
+        lib.xkp_status_string.argtypes = [ct.c_int]
+        lib.xkp_status_string.restype = ct.c_char_p
+        for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
+                  "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs"):
+            getattr(lib, f).restype = ct.c_int
+        _lib = lib
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return load().xkp_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise XkpError(f"{what}: {status_string(code)} ({code})")
+
+
+def basis_bytes(n: int, m: int) -> int:
+    return int(load().xkp_basis_bytes(n, m))
+
+
+def _ptr(t):
+    return 0 if t is None else int(t.data_ptr())
+
+
+@dataclass
+class SystemSpec:
+    """Host description of one system; tensors are CUDA float64 of n = H*H elements."""
+    H: int
+    dt: float
+    g: float
+    mt: object
+    b: object
+    x: object
+    x0: object = None
+    fx: object = None
+    fy: object = None
+    basis_id: int = 0
+
+
+def pack_systems(specs, device):
+    """Device array of xkp_system descriptors (uint8 tensor)."""
+    import torch
+    a = np.zeros(len(specs), dtype=SYSTEM_DTYPE)
+    keep = []
+    for i, s in enumerate(specs):
+        a[i] = (s.H, s.basis_id, s.dt, s.g, _ptr(s.mt), _ptr(s.fx), _ptr(s.fy), _ptr(s.b),
+                _ptr(s.x0), _ptr(s.x))
+        keep += [t for t in (s.mt, s.fx, s.fy, s.b, s.x0, s.x) if t is not None]
+    d = torch.from_numpy(a.view(np.uint8).copy()).to(device)
+    d._xkp_keep = keep          # the descriptors hold device addresses: keep their owners alive
+    return d
+
+
+def pack_batch(H, dt, g, mt, b, x, x0=None, basis_id=None, device=None):
+    """Descriptors for a batch stored as (N, n) CUDA float64 tensors (rows are systems)."""
+    import torch
+    N = mt.shape[0]
+    n = H * H
+    a = np.zeros(N, dtype=SYSTEM_DTYPE)
+    a["H"] = H
+    a["dt"] = dt
+    a["g"] = g
+    st = 8 * n
+    for f, t in (("mt", mt), ("b", b), ("x", x), ("x0", x0)):
+        if t is not None:
+            assert t.is_contiguous() and t.dtype == torch.float64 and t.shape[-1] == n
+            a[f] = t.data_ptr() + st * np.arange(N, dtype=np.uint64)
+    if basis_id is not None:
+        a["basis_id"] = basis_id
+    d = torch.from_numpy(a.view(np.uint8).copy()).to(device or mt.device)
+    d._xkp_keep = [t for t in (mt, b, x, x0) if t is not None]
+    return d
+
+
+def infos_to_numpy(t) -> np.ndarray:
+    return t.cpu().numpy().view(INFO_DTYPE)
+
+
+class Context:
+    """A libxkp context bound to one device and stream, with its fixed workspace."""
+
+    def __init__(self, max_n: int, max_m: int, max_batch: int, device: int = 0, stream=None):
+        import torch
+        lib = load()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ct.c_void_p()
+        _check(lib.xkp_ctx_create(ct.byref(h), device, ct.c_void_p(self.stream.cuda_stream),
+                                  max_n, max_m, max_batch), "xkp_ctx_create")
+        self._h = h
+        self.max_n, self.max_m, self.max_batch = max_n, max_m, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().xkp_ctx_destroy(self._h), "xkp_ctx_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def params(m, tol=1e-8, max_restarts=1000, precision=FP64, mode=TARGET_GALERKIN,
+               batch_max_n=0):
+        if isinstance(mode, str):
+            mode = MODES[mode]
+        return Params(m, max_restarts, tol, precision, mode, batch_max_n, 0)
+
+    def new_infos(self, count):
+        import torch
+        return torch.zeros(count * INFO_DTYPE.itemsize, dtype=torch.uint8,
+                           device=f"cuda:{self.device}")
+
+    def seed_build(self, systems, n_sys, bases_ptrs, params, infos):
+        """systems: packed descriptors; bases_ptrs: int64 CUDA tensor of basis buffer addresses."""
+        _check(load().xkp_seed_build(self._h, n_sys, _ptr(systems), _ptr(bases_ptrs),
+                                     ct.byref(params), _ptr(infos)), "xkp_seed_build")
+
+    def target_project_solve(self, systems, n_sys, n_bases, bases_ptrs, params, infos):
+        _check(load().xkp_target_project_solve(self._h, n_sys, _ptr(systems), n_bases,
+                                               _ptr(bases_ptrs), ct.byref(params), _ptr(infos)),
+               "xkp_target_project_solve")
+
+    def residual(self, systems, n_sys, rel_out):
+        _check(load().xkp_residual(self._h, n_sys, _ptr(systems), _ptr(rel_out)), "xkp_residual")
+
+    def build_rhs(self, systems, n_sys):
+        _check(load().xkp_build_rhs(self._h, n_sys, _ptr(systems)), "xkp_build_rhs")
+
+    def apply(self, systems, n_sys):
+        _check(load().xkp_apply(self._h, n_sys, _ptr(systems)), "xkp_apply")
+
+
+class Bases:
+    """Device storage for `count` seed bases of n unknowns and restart length m."""
+
+    def __init__(self, count, n, m, device=0):
+        import torch
+        self.count, self.n, self.m = count, n, m
+        self.stride = basis_bytes(n, m)
+        self.buf = torch.zeros(count * self.stride, dtype=torch.uint8, device=f"cuda:{device}")
+        base = self.buf.data_ptr()
+        assert base % 256 == 0
+        self.ptrs = torch.tensor([base + i * self.stride for i in range(count)],
+                                 dtype=torch.int64, device=f"cuda:{device}")
+
+    def header(self, i):
+        h = self.buf[i * self.stride:i * self.stride + 16].cpu().numpy().view(np.int32)
+        return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3])}
+
+    def V(self, i):
+        """(n, m+1) view of basis i's FP64 columns."""
+        import torch
+        off = i * self.stride + HEADER_BYTES
+        raw = self.buf[off:off + 8 * self.n * (self.m + 1)]
+        return raw.view(torch.float64).view(self.m + 1, self.n).T
+
+    def Hbar(self, i):
+        import torch
+        off = i * self.stride + HEADER_BYTES + 8 * self.n * (self.m + 1)
+        raw = self.buf[off:off + 8 * (self.m + 1) * self.m]
+        return raw.view(torch.float64).view(self.m, self.m + 1).T

@@ -1,0 +1,86 @@
+"""CPU checks of the C ABI: the library loads, exports every function include/xkp.h declares,
+its structs have the layout the binding packs, and host-side argument errors come back without
+touching a GPU."""
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xkp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xkp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2511_17634_amd import xkp
+    if not os.path.exists(xkp.LIB_PATH):
+        from paper_2511_17634_amd import build
+        build.build()
+    return xkp.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"xkp_seed_build", "xkp_target_project_solve", "xkp_residual"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    from paper_2511_17634_amd import xkp
+    probe = tmp_path / "probe.c"
+    probe.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "xkp.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(xkp_system), offsetof(xkp_system, dt),
+         offsetof(xkp_system, mt), offsetof(xkp_system, x), sizeof(xkp_info), sizeof(xkp_params));
+  printf("%zu %zu %zu\n", sizeof(xkp_basis_header), offsetof(xkp_info, res_est),
+         offsetof(xkp_params, tol));
+  return 0;
+}''')
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(probe),
+                           "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    v = list(map(int, out))
+    S, I = xkp.SYSTEM_DTYPE, xkp.INFO_DTYPE
+    assert v[0] == S.itemsize and v[1] == S.fields["dt"][1] and v[2] == S.fields["mt"][1]
+    assert v[3] == S.fields["x"][1] and v[4] == I.itemsize and v[5] == ct.sizeof(xkp.Params)
+    assert v[6] == xkp.HEADER_BYTES and v[7] == I.fields["res_est"][1]
+    assert v[8] == xkp.Params.tol.offset
+
+
+def test_host_side_errors_without_gpu(lib):
+    from paper_2511_17634_amd import xkp
+    h = ct.c_void_p()
+    assert lib.xkp_ctx_create(ct.byref(h), 0, None, 0, 10, 1) == xkp.EINVAL
+    assert lib.xkp_ctx_create(ct.byref(h), 0, None, 4096, 65, 1) == xkp.EUNSUPPORTED
+    assert lib.xkp_ctx_create(ct.byref(h), 0, None, 1 << 20, 10, 1) == xkp.EUNSUPPORTED
+    P = xkp.Context.params(10)
+    assert lib.xkp_seed_build(None, 1, None, None, ct.byref(P), None) == xkp.EINVAL
+    assert lib.xkp_target_project_solve(None, 1, None, 0, None, ct.byref(P), None) == xkp.EINVAL
+    assert lib.xkp_residual(None, 1, None, None) == xkp.EINVAL
+    assert xkp.basis_bytes(0, 10) == 0
+    n, m = 4096, 40
+    assert xkp.basis_bytes(n, m) >= 256 + 8 * n * (m + 1) + 8 * (m + 1) * m + 2 * n * (m + 1)
+    assert xkp.basis_bytes(n, m) % 256 == 0
+    assert xkp.status_string(xkp.ESINGULAR).startswith("projected")
+
+
+def test_single_hip_runtime_in_process(lib):
+    """libxkp binds to the HIP runtime torch already loaded: one libamdhip64 mapping."""
+    import torch  # noqa: F401
+    maps = open("/proc/self/maps").read().splitlines()
+    paths = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(paths) == 1, paths
