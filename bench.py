@@ -1,0 +1,181 @@
+"""Benchmark: target systems solved per second at FP64-verified relative residual 1e-8.
+
+Workload (one GPU): 64x64 grid (4096 unknowns), 1 seed + 63 targets (blob images, seed blobs
+jittered by N(0, 2 px), amplitudes scaled by U[0.9, 1.1]), T = 100 timesteps, seed basis and
+GMRES restart m = 40, tol 1e-8, FP64.  One step = the whole hot path over the batch: for each of
+the 100 timesteps, the right-hand sides, the seed GMRES with its kept basis, and the projection +
+GMRES polish of all 63 targets.  value = 63 * 100 * steps / elapsed seconds for the projection
+path (target-Galerkin mode); the same chain with plain GMRES and with the seed-Galerkin mode is
+timed beside it.  Inputs are resident in device memory before the timed region.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "target systems solved/sec @ rel-residual 1e-8; projected vs plain GMRES"
+HBM_PEAK_GBS = 8000.0
+
+
+def gmres_bytes(n, m, iters, restarts):
+    """Algorithmic HBM bytes of restarted GMRES(m) with two Gram-Schmidt passes, FP64:
+    Arnoldi step j reads v_0..v_j twice (16 n (j+1)), writes v_{j+1} (8 n) and applies the
+    operator (read u and m~, write w: 24 n); each cycle end forms x += V y (8 n k) and the true
+    residual (48 n)."""
+    import numpy as np
+    iters = np.asarray(iters, dtype=np.int64)
+    restarts = np.asarray(restarts, dtype=np.int64)
+    total = 0
+    for it, rs in zip(iters.ravel(), restarts.ravel()):
+        cycles = [m] * int(rs) + [int(it) - int(rs) * m]
+        for k in cycles:
+            if k <= 0:
+                continue
+            total += sum(16 * n * (j + 1) + 8 * n + 24 * n for j in range(k))
+            total += 8 * n * k + 48 * n
+    return total
+
+
+def run_leg(Chain, args, H, T, m, s0, t0, method, mode, torch):
+    ch = Chain(H, T, m, s0, t0, method=method, mode=mode)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(T)]
+    for _ in range(args.warmup):
+        ch.reset()
+        for _ in range(T):
+            ch.step()
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        ch.reset()
+        for t in range(T):
+            ch.step(events=ev[t] if s == args.steps - 1 else None)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
+    seed_inf, tgt_inf = ch.all_infos()
+    ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
+    if method == "project":
+        ok = ok and bool((seed_inf["status"] == 0).all())
+    # independent FP64 check of the last timestep through the residual entry point
+    rel = torch.empty(ch.N, dtype=torch.float64, device=ch.dev)
+    par = ch.step_no & 1
+    import numpy as np
+    from paper_2511_17634_amd import xkp
+    prev = ch.mt[1 - par]   # m^{T-1}: operator and rhs of the last solve
+    bt = torch.empty_like(prev)
+    d = xkp.pack_batch(H, 1.0 / T, 0.5, prev, bt, ch.mt[par])
+    ch.ctx.build_rhs(d, ch.N)
+    ch.ctx.residual(d, ch.N, rel)
+    torch.cuda.synchronize()
+    rel = rel.cpu().numpy()
+    ok = ok and bool((rel <= args.tol * (1 + 1e-6)).all())
+    return {
+        "elapsed": elapsed, "ok": ok, "kernel_ms_last_chain": kernel_ms,
+        "iters_mean": float(tgt_inf["iters"].mean()), "iters_total": int(tgt_inf["iters"].sum()),
+        "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"],
+        "seed_iters_total": int(seed_inf["iters"].sum()) if method == "project" else 0,
+        "guess_res_mean": float(np.mean(tgt_inf["guess_res"])),
+        "max_res": float(max(tgt_inf["res_true"].max(), rel.max())),
+        "N": ch.N,
+    }
+
+
+def cpu_baseline(H, T, m, s0, t0, n_targets, steps):
+    """The oracle (single-threaded C, FP64) on a bounded sample of the same chain."""
+    from oracle.chain import run_chain
+    t = time.perf_counter()
+    _, _, st = run_chain(s0, t0[:n_targets], H, T, m, method="project", steps=steps)
+    el = time.perf_counter() - t
+    return {"value": n_targets * steps / el, "unit": "target systems/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_targets} of 63 targets x {steps} of {T} timesteps of the same "
+                      f"64x64 chain (seed chain included), target-Galerkin projection + "
+                      f"GMRES({m}) polish, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-targets", type=int, default=7)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2511_17634_amd import xkp
+    from paper_2511_17634_amd.driver import Chain
+    from synth import CONFIGS, config_images, initial_state
+
+    xkp.load()
+    cfg = CONFIGS["c2"]
+    H, T, m = cfg.groups[0].H, cfg.T, cfg.m
+    seed, tg = config_images(cfg, 0)
+    s0 = initial_state(seed[0])
+    t0 = np.stack([initial_state(t[0]) for t in tg])
+    n = H * H
+
+    legs = {}
+    for name, method, mode in (("project", "project", "target_galerkin"),
+                               ("project_seed_galerkin", "project", "seed_galerkin"),
+                               ("plain", "plain", "none")):
+        legs[name] = run_leg(Chain, args, H, T, m, s0, t0, method, mode, torch)
+        print(f"# {name}: {legs[name]['elapsed']:.3f} s, ok={legs[name]['ok']}, "
+              f"mean iters {legs[name]['iters_mean']:.1f}", file=sys.stderr, flush=True)
+
+    N = legs["project"]["N"]
+    per_step = {k: v["elapsed"] / args.steps for k, v in legs.items()}
+    value = N * T / per_step["project"]
+    # roofline of the dominant kernel: the batched GMRES kernel, timed alone in the plain leg
+    pl = legs["plain"]
+    byts = gmres_bytes(n, m, pl["iters"], pl["restarts"]) / T          # per launch (timestep)
+    launch_s = pl["kernel_ms_last_chain"] / 1e3 / T
+    achieved = byts / launch_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "target systems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(per_step["project"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg.name, "grid": f"{H}x{H}", "n": n, "targets": N, "seeds": 1,
+                   "timesteps": T, "m": m, "tol": args.tol, "projection": "target_galerkin"},
+        "verified": all(v["ok"] for v in legs.values()),
+        "plain_gmres": {"value": round(N * T / per_step["plain"], 2),
+                        "ms_per_step": round(per_step["plain"] * 1e3, 3),
+                        "mean_iters": round(pl["iters_mean"], 2)},
+        "seed_galerkin": {"value": round(N * T / per_step["project_seed_galerkin"], 2),
+                          "ms_per_step": round(per_step["project_seed_galerkin"] * 1e3, 3),
+                          "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2)},
+        "projection": {"mean_polish_iters": round(legs["project"]["iters_mean"], 2),
+                       "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
+                       "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
+        "roofline": {"kernel": "gmres_kernel (batched restarted GMRES, 63 systems per launch)",
+                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -50,22 +50,55 @@ class Chain:
             ad = torch.cat([sd, td])
             ad._xkp_keep = sd._xkp_keep + td._xkp_keep
             self.all_desc.append(ad)
-        self.info_s = self.ctx.new_infos(1)
-        self.info_t = self.ctx.new_infos(N)
+        # one info record per system and timestep, so that every solve can be verified
+        self.info_s_all = self.ctx.new_infos(T)
+        self.info_t_all = self.ctx.new_infos(T * N)
+        self.m0 = (self.ms[0].clone(), self.mt[0].clone())
         self.step_no = 0
 
-    def step(self):
-        """Enqueue one timestep on the context's stream."""
+    def reset(self):
+        """Back to the initial images (a device-to-device copy of the state)."""
+        self.ms[0].copy_(self.m0[0])
+        self.mt[0].copy_(self.m0[1])
+        self.step_no = 0
+
+    def _info_slices(self, t):
+        w = xkp.INFO_DTYPE.itemsize
+        return (self.info_s_all[t * w:(t + 1) * w],
+                self.info_t_all[t * self.N * w:(t + 1) * self.N * w])
+
+    @property
+    def info_s(self):
+        return self._info_slices((self.step_no - 1) % self.T)[0]
+
+    @property
+    def info_t(self):
+        return self._info_slices((self.step_no - 1) % self.T)[1]
+
+    def step(self, events=None):
+        """Enqueue one timestep on the context's stream.  `events`, if given, is a pair of
+        HIP events recorded around the target call."""
         par = self.step_no & 1
         c = self.ctx
+        inf_s, inf_t = self._info_slices(self.step_no % self.T)
         if self.method == "project":
             c.build_rhs(self.all_desc[par], self.N + 1)
-            c.seed_build(self.seed_desc[par], 1, self.bases.ptrs, self.params, self.info_s)
+            c.seed_build(self.seed_desc[par], 1, self.bases.ptrs, self.params, inf_s)
         else:
             c.build_rhs(self.tgt_desc[par], self.N)
+        if events is not None:
+            events[0].record(c.stream)
         c.target_project_solve(self.tgt_desc[par], self.N, 1, self.bases.ptrs, self.params,
-                               self.info_t)
+                               inf_t)
+        if events is not None:
+            events[1].record(c.stream)
         self.step_no += 1
+
+    def all_infos(self):
+        """(seed infos [T], target infos [T, N]) of the last full chain."""
+        s = xkp.infos_to_numpy(self.info_s_all)
+        t = xkp.infos_to_numpy(self.info_t_all).reshape(self.T, self.N)
+        return s, t
 
     @property
     def seed_state(self):
