@@ -104,17 +104,19 @@ typedef struct {
  * Seed basis buffer, caller-allocated device memory of xkp_basis_bytes(n, m) bytes, 256-byte
  * aligned.  Layout (all offsets in bytes from the start):
  *   [0, 256)         xkp_basis_header
- *   [256, ...)       V: (m+1) columns of n doubles, column c at 256 + 8*c*n (orthonormal
- *                    Arnoldi vectors v_0..v_k of the seed's first GMRES cycle; column k is
+ *   [256, ...)       V: (m+1) columns of ldv = roundup(n + 1, 8) doubles, column c at
+ *                    256 + 8*c*ldv: the orthonormal Arnoldi vectors v_0..v_k of the seed's
+ *                    first GMRES cycle in rows 0..n-1, zeros in rows n..ldv-1 (column k is
  *                    zero after a breakdown)
  *   then             Hbar: m columns of (m+1) doubles (column-major, leading dimension m+1),
  *                    the unrotated Hessenberg matrix of that cycle
- *   then             Vb: (m+1) columns of n bf16 values (XKP_MIXED copies of V, 256-aligned)
+ *   then             Vb: (m+1) columns of ldv bf16 values (XKP_MIXED copies of V, 256-aligned)
  */
 typedef struct {
     int32_t n, m, k, status;
     double beta;          /* ||r0|| of the seed's first cycle                               */
-    int32_t pad[58];
+    int32_t ldv;          /* leading dimension of V in doubles                              */
+    int32_t pad[57];
 } xkp_basis_header;
 
 typedef struct xkp_ctx xkp_ctx;

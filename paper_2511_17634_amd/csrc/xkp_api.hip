@@ -33,7 +33,7 @@ xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const 
     return *rmax ? XKP_OK : XKP_EUNSUPPORTED;
 }
 
-int lds_len(int nmax) { return (nmax + 1) & ~1; }
+int lds_len(int nmax) { return xkp::lds_vec_len(nmax); }
 
 }  // namespace
 

@@ -9,14 +9,23 @@ namespace xkp {
 
 // Per-workgroup workspace, in doubles, for systems of at most nmax unknowns and restart m.
 struct WsLayout {
-    size_t v, ex, ey, w, stride;
+    size_t v, cE, cW, cN, cS, w, stride;
+    int npad;   // rows covered by the kernel variant (kNT * rmax), coefficient array length
 };
 WsLayout ws_layout(int nmax, int mmax);
 
-// Byte offsets inside a seed basis buffer (the layout documented in xkp.h).
+// Byte offsets inside a seed basis buffer (the layout documented in xkp.h): V columns have
+// leading dimension ldv = roundup(n + 1, 8) doubles, element n (and the rest of the column
+// padding) being zero.
 size_t basis_off_v();
-size_t basis_off_h(int n, int m);
-size_t basis_off_vb(int n, int m);
+int basis_ldv(int n);
+__host__ __device__ inline size_t basis_off_h(int n, int m) {
+    return 256 + sizeof(double) * (size_t)((n + 8) & ~7) * (m + 1);
+}
+__host__ __device__ inline size_t basis_off_vb(int n, int m) {
+    const size_t o = basis_off_h(n, m) + sizeof(double) * (size_t)(m + 1) * m;
+    return (o + 255) & ~(size_t)255;
+}
 size_t basis_bytes(int n, int m);
 
 enum GmresFlags {
@@ -28,6 +37,10 @@ enum GmresFlags {
 // Rows per thread the kernel variant is compiled for; a batch uses the smallest variant whose
 // capacity kNT * rmax covers its largest system.
 int rmax_for(int n);
+
+// Length in doubles of the zero-padded LDS copy of a grid vector: the variant's rows plus one
+// grid column (+1) so that the stencil's forward neighbours need no clamp.
+int lds_vec_len(int nmax);
 
 hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
                         int nsys, xkp_params P, int flags, void *const *bases, xkp_info *infos,

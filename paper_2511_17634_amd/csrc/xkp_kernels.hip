@@ -23,22 +23,46 @@ constexpr int kLdA = 81;   // leading dimension of the projected matrix in LDS (
 // ----------------------------------------------------------------------------------------
 // Vector helpers over the rows a thread owns.
 
+// Row accessors on buffer resources: a vector is addressed through a scalar descriptor (base and
+// size in bytes) plus a 32-bit byte offset per row, the same offset register for every vector
+// and basis column.  The hardware range check makes rows past the end read as zero and drops
+// stores past the end, so no access needs a mask or a branch.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;   // raw (untyped) buffer, gfx9-family descriptor
+
+__device__ __forceinline__ rsrc_t mkbuf(const double *base, int count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), (short)0, count * 8,
+                                             kRsrcWord3);
+}
+__device__ __forceinline__ double bld(rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+__device__ __forceinline__ void bst(rsrc_t r, unsigned byte_off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
+}
+__device__ __forceinline__ unsigned row_off(int k) { return (threadIdx.x + k * kNT) * 8u; }
+
+// Plain global accessors (global address space) for the few non-row accesses.
+typedef __attribute__((address_space(1))) const double gcdouble;
+__device__ __forceinline__ double ld(const double *__restrict__ base, unsigned idx) {
+    return *(gcdouble *)((__attribute__((address_space(1))) const char *)base + (idx << 3));
+}
+
+// load_rows / store_rows / load_col / store_col / mkbuf take GLOBAL-memory vectors only; LDS
+// vectors go through store_rows_lds and plain indexing.
 template <int RMAX>
 __device__ __forceinline__ void load_rows(const double *__restrict__ v, int n, double (&r)[RMAX]) {
+    const rsrc_t b = mkbuf(v, n);
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-        const int p = (int)threadIdx.x + k * kNT;
-        r[k] = (p < n) ? v[p] : 0.0;
-    }
+    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, row_off(k));
 }
 
 template <int RMAX>
 __device__ __forceinline__ void store_rows(double *__restrict__ v, int n, const double (&r)[RMAX]) {
+    const rsrc_t b = mkbuf(v, n);
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-        const int p = (int)threadIdx.x + k * kNT;
-        if (p < n) v[p] = r[k];
-    }
+    for (int k = 0; k < RMAX; ++k) bst(b, row_off(k), r[k]);
 }
 
 template <int RMAX>
@@ -49,70 +73,154 @@ __device__ __forceinline__ double dot_rows(const double (&a)[RMAX], const double
     return s;
 }
 
-// ex, ey per row: C_east = -a + ex, C_west = -a - ex, C_north = -a + ey, C_south = -a - ey with
-// ex = f_x/(2h) - g^2/(8h^2) (m~_{i+1,j} - m~_{i-1,j}) and ey likewise along j (Section 2.3).
+// Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), each loaded by the rows'
+// owners, with a ring of D columns in flight: the loads for visit q+D are issued as soon as
+// visit q has consumed its buffer, so global-memory latency overlaps the per-column work (the
+// reductions of modified Gram-Schmidt are sequential in q).  f(q, column) does the work.
+// Basis columns have leading dimension ldv = roundup(n + 1, 8) and zeros in rows n..ldv-1.
+__device__ __forceinline__ int ldv_for(int n) { return (n + 8) & ~7; }
+
 template <int RMAX>
-__device__ void build_coeffs(const xkp_system &s, const OpConst &o, double *__restrict__ ex,
-                             double *__restrict__ ey) {
-    RowIdx ri;
-    ri.init(o.H);
-    int i = ri.i0, j = ri.j0;
+__device__ __forceinline__ void load_col(const double *__restrict__ v, int n, double (&r)[RMAX]) {
+    load_rows<RMAX>(v, n, r);
+}
+
+// Stores rows p < ldv (the rows past n carry zeros), keeping the column's zero padding.
+template <int RMAX>
+__device__ __forceinline__ void store_col(double *__restrict__ v, int ldv, const double (&r)[RMAX]) {
+    store_rows<RMAX>(v, ldv, r);
+}
+
+template <int RMAX>
+__device__ __forceinline__ void load_buf(rsrc_t b, double (&r)[RMAX]) {
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, row_off(k));
+}
+
+// Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), with a ring of D columns
+// in flight: the loads for visit q+D are issued as soon as visit q has consumed its buffer, so
+// memory latency overlaps the per-column work (the reductions of modified Gram-Schmidt are
+// sequential in q).  The refill is issued unconditionally -- past the last visit it goes through
+// a zero-size descriptor, which returns zeros without touching memory -- so every path through
+// the loop has the same loads outstanding and the waits stay partial.  f(q, column) must not
+// access global memory.
+template <int RMAX, int D, typename F>
+__device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int n, int ldv, int ncols,
+                                           int nvisit, F &&f) {
+    double buf[D][RMAX];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int c = d < ncols ? d : d % ncols;
+        load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, d < nvisit ? n : 0), buf[d]);
+    }
+    for (int q0 = 0; q0 < nvisit; q0 += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int q = q0 + d;
+            if (q < nvisit) f(q, buf[d]);
+            const int qn = q + D;
+            const int c = qn < ncols ? qn : (qn < 2 * ncols ? qn - ncols : 0);
+            load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, qn < nvisit ? n : 0), buf[d]);
+        }
+    }
+}
+
+template <int R> struct Depth { static constexpr int value = 4; };
+template <> struct Depth<2> { static constexpr int value = 8; };
+template <> struct Depth<8> { static constexpr int value = 3; };
+template <> struct Depth<32> { static constexpr int value = 1; };
+
+// Per-row off-diagonal coefficients of the operator (Section 2.3), in the workspace:
+//   C_east  = -g^2/(2h^2) + f_x/(2h) - g^2/(8h^2) (m~_{i+1,j} - m~_{i-1,j})
+//   C_west  = -g^2/(2h^2) - f_x/(2h) + g^2/(8h^2) (m~_{i+1,j} - m~_{i-1,j})
+//   C_north = -g^2/(2h^2) + f_y/(2h) - g^2/(8h^2) (m~_{i,j+1} - m~_{i,j-1})
+//   C_south = -g^2/(2h^2) - f_y/(2h) + g^2/(8h^2) (m~_{i,j+1} - m~_{i,j-1})
+// (m~ and f zero outside the grid).  A coefficient whose neighbour lies outside the grid is stored
+// as zero, and rows n <= p < npad are zero, so the stencil needs no boundary branches.  C_diag is
+// the same for every row and stays a scalar.
+struct Coef {
+    double *E, *W, *N, *S;
+};
+
+template <int RMAX>
+__device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &C) {
     const int H = o.H;
     const double *__restrict__ mt = s.mt;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
         const int p = (int)threadIdx.x + k * kNT;
+        double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
         if (p < o.n) {
+            const int i = p / H, j = p - (p / H) * H;
             const double mE = (i + 1 < H) ? mt[p + H] : 0.0;
             const double mW = (i > 0) ? mt[p - H] : 0.0;
             const double mN = (j + 1 < H) ? mt[p + 1] : 0.0;
             const double mS = (j > 0) ? mt[p - 1] : 0.0;
             const double fxp = s.fx ? s.fx[p] : 0.0;
             const double fyp = s.fy ? s.fy[p] : 0.0;
-            ex[p] = fxp * o.inv2h - o.c8 * (mE - mW);
-            ey[p] = fyp * o.inv2h - o.c8 * (mN - mS);
+            const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
+            const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
+            cE = (i + 1 < H) ? -o.a + ex : 0.0;
+            cW = (i > 0) ? -o.a - ex : 0.0;
+            cN = (j + 1 < H) ? -o.a + ey : 0.0;
+            cS = (j > 0) ? -o.a - ey : 0.0;
         }
-        j += ri.dj;
-        i += ri.di;
-        if (j >= H) { j -= H; ++i; }
+        const unsigned off = (unsigned)p * 8u;
+        bst(mkbuf(C.E, kNT * RMAX), off, cE);
+        bst(mkbuf(C.W, kNT * RMAX), off, cW);
+        bst(mkbuf(C.N, kNT * RMAX), off, cN);
+        bst(mkbuf(C.S, kNT * RMAX), off, cS);
     }
 }
 
-// w = A u with u read from `u` (LDS copy or global), zero outside the grid.
+// w = A u with u in LDS, zero-padded by at least one grid column (+1) on both sides: every
+// neighbour read is in bounds and unconditional (the coefficient is 0 where the neighbour lies
+// outside the grid), so each neighbour needs one address register, rows differing by an
+// immediate offset.
 template <int RMAX>
-__device__ __forceinline__ void stencil(const double *u, const double *__restrict__ ex,
-                                        const double *__restrict__ ey, const OpConst &o,
-                                        double (&w)[RMAX]) {
-    RowIdx ri;
-    ri.init(o.H);
-    int i = ri.i0, j = ri.j0;
+__device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, const OpConst &o,
+                                            double (&w)[RMAX]) {
     const int H = o.H;
+    const double *uc = u + threadIdx.x;
+    const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
+    const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        const int p = (int)threadIdx.x + k * kNT;
-        double s = 0.0;
-        if (p < o.n) {
-            const double uc = u[p];
-            const double uE = (i + 1 < H) ? u[p + H] : 0.0;
-            const double uW = (i > 0) ? u[p - H] : 0.0;
-            const double uN = (j + 1 < H) ? u[p + 1] : 0.0;
-            const double uS = (j > 0) ? u[p - 1] : 0.0;
-            s = o.cd * uc - o.a * ((uE + uW) + (uN + uS)) + ex[p] * (uE - uW) + ey[p] * (uN - uS);
-        }
-        w[k] = s;
-        j += ri.dj;
-        i += ri.di;
-        if (j >= H) { j -= H; ++i; }
+        const unsigned off = row_off(k);
+        const double *q = uc + k * kNT;
+        w[k] = o.cd * q[0] + bld(bE, off) * q[H] + bld(bW, off) * q[-H] + bld(bN, off) * q[1]
+               + bld(bS, off) * q[-1];
+        // bound the scheduling region: issuing every row's loads at once needs more registers
+        // than the kernel has while the basis prefetch is in flight
+        if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// Same operator with the coefficients formed on the fly from m~ (no workspace).
+// w = A u with u a length-n global vector: every neighbour index clamped into [0, n), rows past
+// n masked to zero.
+template <int RMAX>
+__device__ __forceinline__ void stencil_glob(const double *__restrict__ u, const Coef &C,
+                                             const OpConst &o, double (&w)[RMAX]) {
+    const unsigned H = o.H, n = o.n;
+    const rsrc_t bu = mkbuf(u, n);
+    const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
+    const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        const unsigned p = threadIdx.x + k * kNT, off = p * 8u;
+        // neighbours outside [0, n) read as zero (range check); their coefficient is 0 anyway
+        const unsigned ow = p >= H ? (p - H) * 8u : 0xFFFFFFF0u;
+        const unsigned os = p >= 1u ? (p - 1u) * 8u : 0xFFFFFFF0u;
+        w[k] = o.cd * bld(bu, off) + bld(bE, off) * bld(bu, off + 8u * H)
+               + bld(bW, off) * bld(bu, ow) + bld(bN, off) * bld(bu, off + 8u)
+               + bld(bS, off) * bld(bu, os);
+    }
+}
+
+// The operator with coefficients formed on the fly from m~ (no workspace; residual and apply).
 template <int RMAX>
 __device__ __forceinline__ void stencil_direct(const double *u, const xkp_system &s,
                                                const OpConst &o, double (&w)[RMAX]) {
-    RowIdx ri;
-    ri.init(o.H);
-    int i = ri.i0, j = ri.j0;
     const int H = o.H;
     const double *__restrict__ mt = s.mt;
 #pragma unroll
@@ -120,23 +228,28 @@ __device__ __forceinline__ void stencil_direct(const double *u, const xkp_system
         const int p = (int)threadIdx.x + k * kNT;
         double r = 0.0;
         if (p < o.n) {
+            const int i = p / H, j = p - (p / H) * H;
             const bool e = i + 1 < H, wv = i > 0, nn = j + 1 < H, ss = j > 0;
             const double ex = (s.fx ? s.fx[p] : 0.0) * o.inv2h
                               - o.c8 * ((e ? mt[p + H] : 0.0) - (wv ? mt[p - H] : 0.0));
             const double ey = (s.fy ? s.fy[p] : 0.0) * o.inv2h
                               - o.c8 * ((nn ? mt[p + 1] : 0.0) - (ss ? mt[p - 1] : 0.0));
-            const double uc = u[p];
             const double uE = e ? u[p + H] : 0.0;
             const double uW = wv ? u[p - H] : 0.0;
             const double uN = nn ? u[p + 1] : 0.0;
             const double uS = ss ? u[p - 1] : 0.0;
-            r = o.cd * uc - o.a * ((uE + uW) + (uN + uS)) + ex * (uE - uW) + ey * (uN - uS);
+            r = o.cd * u[p] + (-o.a + ex) * uE + (-o.a - ex) * uW + (-o.a + ey) * uN
+                + (-o.a - ey) * uS;
         }
         w[k] = r;
-        j += ri.dj;
-        i += ri.di;
-        if (j >= H) { j -= H; ++i; }
     }
+}
+
+// All rows (including the zero rows past n) into the padded LDS vector.
+template <int RMAX>
+__device__ __forceinline__ void store_rows_lds(double *v, const double (&r)[RMAX]) {
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) v[threadIdx.x + k * kNT] = r[k];
 }
 
 __device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
@@ -147,15 +260,16 @@ __device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
 // ----------------------------------------------------------------------------------------
 // LDS layout of the GMRES kernel: vbuf[nlds] | Rp[kMMax*(kMMax+1)/2] | cs | sn | gv | h1 | yv | red
 struct GmresLds {
-    double *vbuf, *Rp, *cs, *sn, *gv, *h1, *yv, *red;
-    __device__ GmresLds(double *base, int nlds) {
-        vbuf = base;
-        Rp = vbuf + nlds;
+    double *vbuf, *Rp, *cs, *sn, *gv, *h1, *h2, *yv, *red;
+    __device__ GmresLds(double *base, int nlds, int npad) {
+        vbuf = base + (nlds - npad) / 2;   // front pad
+        Rp = base + nlds;
         cs = Rp + kMMax * (kMMax + 1) / 2;
         sn = cs + kMMax;
         gv = sn + kMMax;
         h1 = gv + kMMax + 1;
-        yv = h1 + kMMax + 1;
+        h2 = h1 + kMMax + 1;
+        yv = h2 + kMMax + 1;
         red = yv + kMMax;
     }
 };
@@ -165,13 +279,13 @@ __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
 template <int RMAX>
 __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, int prestatus,
                           xkp_basis_header *hdr, double *Vfirst, double *Hb, double *Vws,
-                          double *ex, double *ey, xkp_info *info, GmresLds &L) {
+                          const Coef &C, xkp_info *info, GmresLds &L) {
     const OpConst o = op_const(s);
-    const int n = o.n, m = P.m, tid = threadIdx.x;
+    const int n = o.n, m = P.m, tid = threadIdx.x, ldv = ldv_for(o.n);
     const bool keep = hdr != nullptr;
     BlockRed br{L.red, 0};
 
-    build_coeffs<RMAX>(s, o, ex, ey);
+    build_coeffs<RMAX>(s, o, C);
     if (keep) {
         for (int t = tid; t < (m + 1) * m; t += kNT) Hb[t] = 0.0;
         __syncthreads();   // thread 0 overwrites some of these entries later
@@ -193,10 +307,10 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
         const double *xs = (flags & kStartFromX) ? s.x : s.x0;
         if (xs) {
             load_rows<RMAX>(xs, n, nxt);
-            store_rows<RMAX>(L.vbuf, n, nxt);
+            store_rows_lds<RMAX>(L.vbuf, nxt);
             if (xs != s.x) store_rows<RMAX>(s.x, n, nxt);
             lds_barrier();
-            stencil<RMAX>(L.vbuf, ex, ey, o, w);
+            stencil_lds<RMAX>(L.vbuf, C, o, w);
 #pragma unroll
             for (int k = 0; k < RMAX; ++k) cur[k] -= w[k];
         } else {
@@ -213,60 +327,61 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                 // v_0 = r / beta; the LDS copy feeds the stencil
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) cur[k] = cur[k] / beta;
-                store_rows<RMAX>(V, n, cur);
-                store_rows<RMAX>(L.vbuf, n, cur);
+                store_col<RMAX>(V, ldv, cur);
+                store_rows_lds<RMAX>(L.vbuf, cur);
                 if (first) beta_first = beta;
                 lds_barrier();
                 double gcur = beta;
                 int kk = 0;
                 for (int j = 0; j < m; ++j) {
-                    stencil<RMAX>(L.vbuf, ex, ey, o, w);
+                    stencil_lds<RMAX>(L.vbuf, C, o, w);
                     ++iters;
                     const double wsq = dot_rows<RMAX>(w, w);
                     double wn0 = 0.0, t = 0.0;
-                    for (int pass = 0; pass < 2; ++pass) {
-                        load_rows<RMAX>(V, n, cur);
-                        for (int i = 0; i <= j; ++i) {
-                            if (i < j) load_rows<RMAX>(V + (size_t)(i + 1) * n, n, nxt);
-                            double d;
-                            if (pass == 0 && i == 0) {
-                                double two[2] = {dot_rows<RMAX>(w, cur), wsq};
-                                br.sum_multi<2>(two);
-                                d = two[0];
-                                wn0 = sqrt(two[1]);
-                            } else {
-                                d = br.sum(dot_rows<RMAX>(w, cur));
-                            }
+                    // two modified Gram-Schmidt passes over v_0..v_j as one sweep of 2(j+1)
+                    // column visits; the second pass re-orthogonalises and completes h_{i,j}
+                    const int nc = j + 1;
+                    sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, nc, 2 * nc,
+                        [&](int q, const double(&col)[RMAX]) {
+                        const int i = q < nc ? q : q - nc;
+                        double d;
+                        if (q == 0) {
+                            double two[2] = {dot_rows<RMAX>(w, col), wsq};
+                            br.sum_multi<2>(two);
+                            d = two[0];
+                            wn0 = sqrt(two[1]);
+                        } else {
+                            d = br.sum(dot_rows<RMAX>(w, col));
+                        }
 #pragma unroll
-                            for (int k = 0; k < RMAX; ++k) w[k] -= d * cur[k];
-                            if (pass == 0) {
-                                if (tid == 0) L.h1[i] = d;
+                        for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
+                        if (q < nc) {
+                            if (tid == 0) L.h1[i] = d;
+                        } else {
+                            // final h_{i,j}; fold the Givens rotations in as entries arrive
+                            const double hf = L.h1[i] + d;
+                            if (tid == 0) L.h2[i] = hf;
+                            if (i == 0) {
+                                t = hf;
                             } else {
-                                // final h_{i,j}; fold the Givens rotations in as entries arrive
-                                const double hf = L.h1[i] + d;
-                                if (keep && first && tid == 0) Hb[(size_t)j * (m + 1) + i] = hf;
-                                if (i == 0) {
-                                    t = hf;
-                                } else {
-                                    const double c = L.cs[i - 1], sn = L.sn[i - 1];
-                                    const double rr = c * t + sn * hf;
-                                    t = -sn * t + c * hf;
-                                    if (tid == 0) L.Rp[tri(j) + i - 1] = rr;
-                                }
-                            }
-                            if (i < j) {
-#pragma unroll
-                                for (int k = 0; k < RMAX; ++k) cur[k] = nxt[k];
+                                const double c = L.cs[i - 1], sn = L.sn[i - 1];
+                                const double rr = c * t + sn * hf;
+                                t = -sn * t + c * hf;
+                                if (tid == 0) L.Rp[tri(j) + i - 1] = rr;
                             }
                         }
-                    }
+                    });
                     const double hn = sqrt(br.sum(dot_rows<RMAX>(w, w)));
                     const bool brk = !(hn > 1e-14 * wn0);
 #pragma unroll
                     for (int k = 0; k < RMAX; ++k) w[k] = brk ? 0.0 : w[k] / hn;
-                    store_rows<RMAX>(V + (size_t)(j + 1) * n, n, w);
-                    store_rows<RMAX>(L.vbuf, n, w);
-                    if (keep && first && tid == 0) Hb[(size_t)j * (m + 1) + j + 1] = hn;
+                    store_col<RMAX>(V + (size_t)(j + 1) * ldv, ldv, w);
+                    store_rows_lds<RMAX>(L.vbuf, w);
+                    if (keep && first) {
+                        // unrotated Hessenberg column j of the kept basis
+                        for (int r = tid; r <= m; r += kNT)
+                            Hb[(size_t)j * (m + 1) + r] = r <= j ? L.h2[r] : (r == j + 1 ? hn : 0.0);
+                    }
                     const double den = sqrt(t * t + hn * hn);
                     const double cj = t / den, sj = hn / den;
                     if (tid == 0) {
@@ -293,26 +408,21 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                 lds_barrier();
                 // x += V_k y
                 load_rows<RMAX>(s.x, n, w);
-                load_rows<RMAX>(V, n, cur);
-                for (int c = 0; c < kk; ++c) {
-                    if (c + 1 < kk) load_rows<RMAX>(V + (size_t)(c + 1) * n, n, nxt);
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, kk, kk,
+                    [&](int c, const double(&col)[RMAX]) {
                     const double yc = L.yv[c];
 #pragma unroll
-                    for (int k = 0; k < RMAX; ++k) w[k] += yc * cur[k];
-                    if (c + 1 < kk) {
-#pragma unroll
-                        for (int k = 0; k < RMAX; ++k) cur[k] = nxt[k];
-                    }
-                }
+                    for (int k = 0; k < RMAX; ++k) w[k] += yc * col[k];
+                });
                 store_rows<RMAX>(s.x, n, w);
-                store_rows<RMAX>(L.vbuf, n, w);
+                store_rows_lds<RMAX>(L.vbuf, w);
                 if (first) {
                     kfirst = kk;
                     first = false;
                 }
                 lds_barrier();
                 // true residual in FP64
-                stencil<RMAX>(L.vbuf, ex, ey, o, w);
+                stencil_lds<RMAX>(L.vbuf, C, o, w);
                 load_rows<RMAX>(s.b, n, cur);
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) cur[k] -= w[k];
@@ -334,6 +444,7 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
             hdr->k = kfirst;
             hdr->status = status;
             hdr->beta = beta_first;
+            hdr->ldv = ldv;
         }
         int st = status;
         if (st == XKP_OK && (flags & kTarget) && prestatus == XKP_ESINGULAR) st = XKP_ESINGULAR;
@@ -358,8 +469,11 @@ __global__ __launch_bounds__(kNT) void gmres_kernel(const xkp_system *__restrict
                                                     xkp_info *infos, double *ws, WsLayout Lw,
                                                     int nmax, int nlds) {
     extern __shared__ double lds[];
-    GmresLds L(lds, nlds);
+    GmresLds L(lds, nlds, kNT * RMAX);
+    for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;   // the pads stay zero
+    lds_barrier();
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
+    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
     for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
         const xkp_system s = sys[si];
         xkp_info *info = infos + si;
@@ -376,10 +490,9 @@ __global__ __launch_bounds__(kNT) void gmres_kernel(const xkp_system *__restrict
             char *base = (char *)bases[si];
             hdr = (xkp_basis_header *)base;
             Vfirst = (double *)(base + 256);
-            Hb = (double *)(base + 256 + sizeof(double) * (size_t)s.H * s.H * (P.m + 1));
+            Hb = (double *)(base + basis_off_h(s.H * s.H, P.m));
         }
-        gmres_one<RMAX>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, slot + Lw.ex, slot + Lw.ey,
-                        info, L);
+        gmres_one<RMAX>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, L);
     }
 }
 
@@ -475,14 +588,15 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                                                       WsLayout Lw, int nmax, int nlds) {
     extern __shared__ double lds[];
     // vbuf and the projected matrix share the front of LDS; they are never live together.
-    double *vbuf = lds;
+    double *vbuf = lds + (nlds - kNT * RMAX) / 2;   // after the front pad
     double *Ap = lds;
     double *zv = lds + nlds;           // kMMax + 1
     double *alpha = zv + kMMax + 1;    // kMMax
     int *pivl = (int *)(alpha + kMMax);
     double *red = alpha + kMMax + kMMax / 2;
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
-    double *ex = slot + Lw.ex, *ey = slot + Lw.ey, *W = slot + Lw.w;
+    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
+    double *W = slot + Lw.w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
@@ -507,19 +621,23 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
         }
         const int m = P.m;
         const double *V = (const double *)((const char *)hdr + 256);
-        const double *Hb = V + (size_t)n * (m + 1);
+        const int ldv = ldv_for(n);
+        const double *Hb = (const double *)((const char *)hdr + basis_off_h(n, m));
         const OpConst o = op_const(s);
         BlockRed br{red, 0};
-        build_coeffs<RMAX>(s, o, ex, ey);
+        build_coeffs<RMAX>(s, o, C);
+        // the LDS vector shares space with the projected matrix of the previous system: clear it
+        for (int t = tid; t < nlds; t += kNT) lds[t] = 0.0;
+        lds_barrier();   // the cleared words belong to other threads' rows
 
         // r_base = b - A' x_base
         double rb[RMAX], xr[RMAX], cur[RMAX];
         load_rows<RMAX>(s.b, n, rb);
         if (s.x0) {
             load_rows<RMAX>(s.x0, n, xr);
-            store_rows<RMAX>(vbuf, n, xr);
+            store_rows_lds<RMAX>(vbuf, xr);
             lds_barrier();
-            stencil<RMAX>(vbuf, ex, ey, o, cur);
+            stencil_lds<RMAX>(vbuf, C, o, cur);
 #pragma unroll
             for (int q = 0; q < RMAX; ++q) rb[q] -= cur[q];
         } else {
@@ -532,24 +650,25 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                 // W = [A' V_k | r_base] in the workspace, then [V_k^T A' V_k | V_k^T r_base] by
                 // FP64 matrix-core tiles (16x16 outputs, 4-deep inner steps over the rows).
                 for (int c = 0; c < k; ++c) {
-                    stencil<RMAX>(V + (size_t)c * n, ex, ey, o, cur);
-                    store_rows<RMAX>(W + (size_t)c * n, n, cur);
+                    stencil_glob<RMAX>(V + (size_t)c * ldv, C, o, cur);
+                    store_col<RMAX>(W + (size_t)c * ldv, ldv, cur);
                 }
-                store_rows<RMAX>(W + (size_t)k * n, n, rb);
+                store_col<RMAX>(W + (size_t)k * ldv, ldv, rb);
                 __syncthreads();   // W rows written by other threads are read below
                 const int ktr = (k + 15) / 16, ktc = (k + 16) / 16;
                 for (int tl = wave; tl < ktr * ktc; tl += kNW) {
                     const int ta = tl / ktc, tc = tl % ktc;
                     const int ia = ta * 16 + (lane & 15), jc = tc * 16 + (lane & 15);
                     const int kq = lane >> 4;
-                    const double *Va = V + (size_t)(ia < k ? ia : 0) * n;
-                    const double *Wc = W + (size_t)(jc <= k ? jc : 0) * n;
+                    const double *Va = V + (size_t)(ia < k ? ia : 0) * ldv;
+                    const double *Wc = W + (size_t)(jc <= k ? jc : 0) * ldv;
                     const bool va = ia < k, wb = jc <= k;
+                    const rsrc_t rA = mkbuf(Va, n), rB = mkbuf(Wc, n);
                     double4_t acc = {0.0, 0.0, 0.0, 0.0};
                     for (int p0 = 0; p0 < n; p0 += 4) {
                         const int p = p0 + kq;
-                        const double av = (va && p < n) ? Va[p] : 0.0;
-                        const double bv = (wb && p < n) ? Wc[p] : 0.0;
+                        const double av = va ? bld(rA, (unsigned)p * 8u) : 0.0;
+                        const double bv = wb ? bld(rB, (unsigned)p * 8u) : 0.0;
                         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                     }
                     // FP64 16x16x4 output layout: lane l, register r holds D[4r + l/16][l%16]
@@ -573,7 +692,7 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                     for (int q = 0; q < kRedSlots; ++q) {
                         part[q] = 0.0;
                         if (c0 + q < nz) {
-                            load_rows<RMAX>(V + (size_t)(c0 + q) * n, n, cur);
+                            load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, cur);
                             part[q] = dot_rows<RMAX>(cur, rb);
                         }
                     }
@@ -602,17 +721,12 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
             singular = pivl[kMMax - 1] != 0;
             if (!singular) {
                 // x0 = x_base + V_k alpha
-                load_rows<RMAX>(V, n, cur);
-                for (int c = 0; c < k; ++c) {
-                    if (c + 1 < k) load_rows<RMAX>(V + (size_t)(c + 1) * n, n, rb);
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                    [&](int c, const double(&col)[RMAX]) {
                     const double al = alpha[c];
 #pragma unroll
-                    for (int q = 0; q < RMAX; ++q) xr[q] += al * cur[q];
-                    if (c + 1 < k) {
-#pragma unroll
-                        for (int q = 0; q < RMAX; ++q) cur[q] = rb[q];
-                    }
-                }
+                    for (int q = 0; q < RMAX; ++q) xr[q] += al * col[q];
+                });
             }
         }
         store_rows<RMAX>(s.x, n, xr);
@@ -643,7 +757,7 @@ __global__ __launch_bounds__(kNT) void residual_kernel(const xkp_system *__restr
         double x[RMAX], w[RMAX], b[RMAX];
         load_rows<RMAX>(s.x, o.n, x);
         load_rows<RMAX>(s.b, o.n, b);
-        store_rows<RMAX>(vbuf, o.n, x);
+        store_rows_lds<RMAX>(vbuf, x);
         lds_barrier();
         stencil_direct<RMAX>(vbuf, s, o, w);
 #pragma unroll
@@ -665,7 +779,7 @@ __global__ __launch_bounds__(kNT) void apply_kernel(const xkp_system *__restrict
         const OpConst o = op_const(s);
         double u[RMAX], w[RMAX];
         load_rows<RMAX>(s.x0, o.n, u);
-        store_rows<RMAX>(lds, o.n, u);
+        store_rows_lds<RMAX>(lds, u);
         lds_barrier();
         stencil_direct<RMAX>(lds, s, o, w);
         store_rows<RMAX>(s.x, o.n, w);
@@ -708,22 +822,21 @@ __global__ __launch_bounds__(kNT) void rhs_kernel(const xkp_system *__restrict__
 WsLayout ws_layout(int nmax, int mmax) {
     auto up = [](size_t v) { return (v + 63) & ~(size_t)63; };
     WsLayout L;
+    L.npad = kNT * rmax_for(nmax);
     L.v = 0;
-    L.ex = up((size_t)nmax * (mmax + 1));
-    L.ey = L.ex + up(nmax);
-    L.w = L.ey + up(nmax);
-    L.stride = L.w + up((size_t)nmax * (mmax + 1));
+    L.cE = up((size_t)basis_ldv(nmax) * (mmax + 1));
+    L.cW = L.cE + up(L.npad);
+    L.cN = L.cW + up(L.npad);
+    L.cS = L.cN + up(L.npad);
+    L.w = L.cS + up(L.npad);
+    L.stride = L.w + up((size_t)basis_ldv(nmax) * (mmax + 1));
     return L;
 }
 
 size_t basis_off_v() { return 256; }
-size_t basis_off_h(int n, int m) { return 256 + sizeof(double) * (size_t)n * (m + 1); }
-size_t basis_off_vb(int n, int m) {
-    size_t o = basis_off_h(n, m) + sizeof(double) * (size_t)(m + 1) * m;
-    return (o + 255) & ~(size_t)255;
-}
+int basis_ldv(int n) { return (n + 8) & ~7; }
 size_t basis_bytes(int n, int m) {
-    size_t o = basis_off_vb(n, m) + 2 * (size_t)n * (m + 1);
+    size_t o = basis_off_vb(n, m) + 2 * (size_t)basis_ldv(n) * (m + 1);
     return (o + 255) & ~(size_t)255;
 }
 
@@ -734,8 +847,15 @@ int rmax_for(int n) {
     return 0;
 }
 
+int lds_vec_len(int nmax) {
+    int h = 1;
+    while (h * h < nmax) ++h;
+    const int pad = (h + 2) & ~1;            // >= one grid column + 1, on each side
+    return kNT * rmax_for(nmax) + 2 * pad;
+}
+
 static size_t gmres_lds_bytes(int nlds) {
-    return sizeof(double) * ((size_t)nlds + kMMax * (kMMax + 1) / 2 + 5 * kMMax + 2 +
+    return sizeof(double) * ((size_t)nlds + kMMax * (kMMax + 1) / 2 + 6 * kMMax + 3 +
                              2 * kRedSlots * kNW);
 }
 static size_t project_lds_bytes(int nlds) {

@@ -218,19 +218,29 @@ class Bases:
         self.ptrs = torch.tensor([base + i * self.stride for i in range(count)],
                                  dtype=torch.int64, device=f"cuda:{device}")
 
+    @property
+    def ldv(self):
+        """Leading dimension of V: roundup(n + 1, 8) doubles (zeros past row n)."""
+        return (self.n + 8) & ~7
+
     def header(self, i):
-        h = self.buf[i * self.stride:i * self.stride + 16].cpu().numpy().view(np.int32)
-        return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3])}
+        h = self.buf[i * self.stride:i * self.stride + 32].cpu().numpy().view(np.int32)
+        return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3]),
+                "ldv": int(h[6])}
+
+    def V_padded(self, i):
+        """(ldv, m+1) view of basis i's FP64 columns including the zero rows."""
+        import torch
+        off = i * self.stride + HEADER_BYTES
+        raw = self.buf[off:off + 8 * self.ldv * (self.m + 1)]
+        return raw.view(torch.float64).view(self.m + 1, self.ldv).T
 
     def V(self, i):
         """(n, m+1) view of basis i's FP64 columns."""
-        import torch
-        off = i * self.stride + HEADER_BYTES
-        raw = self.buf[off:off + 8 * self.n * (self.m + 1)]
-        return raw.view(torch.float64).view(self.m + 1, self.n).T
+        return self.V_padded(i)[:self.n]
 
     def Hbar(self, i):
         import torch
-        off = i * self.stride + HEADER_BYTES + 8 * self.n * (self.m + 1)
+        off = i * self.stride + HEADER_BYTES + 8 * self.ldv * (self.m + 1)
         raw = self.buf[off:off + 8 * (self.m + 1) * self.m]
         return raw.view(torch.float64).view(self.m, self.m + 1).T
