@@ -581,16 +581,101 @@ __device__ bool lsq_hessenberg_wave(double *A, int lda, int kk, double *z, doubl
     return false;
 }
 
+// Partial [V_k^T W] over the 4-row groups g = wave, wave + kNW, ... for KTR row tiles and NTC
+// column tiles starting at column tile tc0, FP64 matrix cores (v_mfma_f64_16x16x4: A 16x4 from
+// lane i + 16 kk, B 4x16 from lane j + 16 kk).  Each wave keeps all KTR x NTC accumulators;
+// the operands of the next group are loaded before the current group's products.
+template <int KTR, int NTC>
+__device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, int k, int tc0,
+                                          double *Ap, double *tred) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double4_t acc[KTR][NTC];
+    unsigned offA[KTR], offB[NTC];
+    bool okA[KTR], okB[NTC];
+#pragma unroll
+    for (int t = 0; t < KTR; ++t) {
+        const int a = t * 16 + (lane & 15);
+        okA[t] = a < k;
+        offA[t] = (unsigned)(okA[t] ? a : 0) * (unsigned)ldv * 8u;
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+        const int c = (tc0 + t) * 16 + (lane & 15);
+        okB[t] = c <= k;
+        offB[t] = (unsigned)(okB[t] ? c : 0) * (unsigned)ldv * 8u;
+    }
+#pragma unroll
+    for (int a = 0; a < KTR; ++a)
+#pragma unroll
+        for (int b = 0; b < NTC; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
+    const int ngroups = (n + 3) / 4;
+    double an[KTR], bn[NTC];
+    int g = wave;
+    {
+        const unsigned p = 4u * g + (lane >> 4), po = p * 8u;
+#pragma unroll
+        for (int t = 0; t < KTR; ++t) an[t] = bld(rV, offA[t] + po);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) bn[t] = bld(rW, offB[t] + po);
+    }
+    for (; g < ngroups; g += kNW) {
+        const unsigned p = 4u * g + (lane >> 4);
+        const bool pin = p < (unsigned)n;
+        double av[KTR], bv[NTC];
+#pragma unroll
+        for (int t = 0; t < KTR; ++t) av[t] = (okA[t] && pin) ? an[t] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) bv[t] = (okB[t] && pin) ? bn[t] : 0.0;
+        // next group's operands (past the end: clamped to the last group, never used)
+        const int gn = g + kNW < ngroups ? g + kNW : g;
+        const unsigned pon = (4u * gn + (lane >> 4)) * 8u;
+#pragma unroll
+        for (int t = 0; t < KTR; ++t) an[t] = bld(rV, offA[t] + pon);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) bn[t] = bld(rW, offB[t] + pon);
+#pragma unroll
+        for (int a = 0; a < KTR; ++a)
+#pragma unroll
+            for (int b = 0; b < NTC; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    // reduce each tile over the waves in a fixed order; lane l, register r holds
+    // D[4r + l/16][l%16] of the 16x16 tile
+#pragma unroll
+    for (int ta = 0; ta < KTR; ++ta) {
+#pragma unroll
+        for (int tb = 0; tb < NTC; ++tb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tred[wave * 256 + lane * 4 + r] = acc[ta][tb][r];
+            lds_barrier();
+            if (threadIdx.x < 256) {
+                double sum = 0.0;
+#pragma unroll
+                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + threadIdx.x];
+                const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+                const int a = ta * 16 + 4 * r + (l >> 4);
+                const int c = (tc0 + tb) * 16 + (l & 15);
+                if (a < k && c <= k) Ap[a * kLdA + c] = sum;
+            }
+            lds_barrier();
+        }
+    }
+}
+
 template <int RMAX>
 __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restrict__ sys, int nsys,
                                                       int n_bases, const void *const *bases,
                                                       xkp_params P, xkp_info *infos, double *ws,
-                                                      WsLayout Lw, int nmax, int nlds) {
+                                                      WsLayout Lw, int nmax, int nlds,
+                                                      int nbuf, int nregion) {
     extern __shared__ double lds[];
-    // vbuf and the projected matrix share the front of LDS; they are never live together.
+    // The LDS region holds nbuf zero-padded vector copies (each nlds long) during the operator
+    // applications, then the projected matrix and the tile-reduction scratch: never live
+    // together.
     double *vbuf = lds + (nlds - kNT * RMAX) / 2;   // after the front pad
+    double *vbuf1 = vbuf + nlds;
     double *Ap = lds;
-    double *zv = lds + nlds;           // kMMax + 1
+    double *zv = lds + nregion;        // kMMax + 1
     double *alpha = zv + kMMax + 1;    // kMMax
     int *pivl = (int *)(alpha + kMMax);
     double *red = alpha + kMMax + kMMax / 2;
@@ -627,56 +712,75 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
         BlockRed br{red, 0};
         build_coeffs<RMAX>(s, o, C);
         // the LDS vector shares space with the projected matrix of the previous system: clear it
-        for (int t = tid; t < nlds; t += kNT) lds[t] = 0.0;
+        for (int t = tid; t < nregion; t += kNT) lds[t] = 0.0;
         lds_barrier();   // the cleared words belong to other threads' rows
 
         // r_base = b - A' x_base
-        double rb[RMAX], xr[RMAX], cur[RMAX];
+        double rb[RMAX], cur[RMAX];
         load_rows<RMAX>(s.b, n, rb);
         if (s.x0) {
-            load_rows<RMAX>(s.x0, n, xr);
-            store_rows_lds<RMAX>(vbuf, xr);
+            load_rows<RMAX>(s.x0, n, cur);
+            store_rows_lds<RMAX>(vbuf, cur);
             lds_barrier();
             stencil_lds<RMAX>(vbuf, C, o, cur);
 #pragma unroll
             for (int q = 0; q < RMAX; ++q) rb[q] -= cur[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < RMAX; ++q) xr[q] = 0.0;
         }
         bool singular = false;
         if (k > 0) {
             if (P.mode == XKP_PROJ_TARGET_GALERKIN) {
-                // W = [A' V_k | r_base] in the workspace, then [V_k^T A' V_k | V_k^T r_base] by
-                // FP64 matrix-core tiles (16x16 outputs, 4-deep inner steps over the rows).
-                for (int c = 0; c < k; ++c) {
-                    stencil_glob<RMAX>(V + (size_t)c * ldv, C, o, cur);
-                    store_col<RMAX>(W + (size_t)c * ldv, ldv, cur);
-                }
-                store_col<RMAX>(W + (size_t)k * ldv, ldv, rb);
-                __syncthreads();   // W rows written by other threads are read below
-                const int ktr = (k + 15) / 16, ktc = (k + 16) / 16;
-                for (int tl = wave; tl < ktr * ktc; tl += kNW) {
-                    const int ta = tl / ktc, tc = tl % ktc;
-                    const int ia = ta * 16 + (lane & 15), jc = tc * 16 + (lane & 15);
-                    const int kq = lane >> 4;
-                    const double *Va = V + (size_t)(ia < k ? ia : 0) * ldv;
-                    const double *Wc = W + (size_t)(jc <= k ? jc : 0) * ldv;
-                    const bool va = ia < k, wb = jc <= k;
-                    const rsrc_t rA = mkbuf(Va, n), rB = mkbuf(Wc, n);
-                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
-                    for (int p0 = 0; p0 < n; p0 += 4) {
-                        const int p = p0 + kq;
-                        const double av = va ? bld(rA, (unsigned)p * 8u) : 0.0;
-                        const double bv = wb ? bld(rB, (unsigned)p * 8u) : 0.0;
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-                    }
-                    // FP64 16x16x4 output layout: lane l, register r holds D[4r + l/16][l%16]
+                // W = [A' V_k | r_base] in the workspace.  Each thread keeps its rows'
+                // coefficients in registers; the basis columns stream through the prefetch ring
+                // and, for the neighbours, through one of two zero-padded LDS copies.
+                double cEr[RMAX], cWr[RMAX], cNr[RMAX], cSr[RMAX];
+                {
+                    const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
+                    const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int a = ta * 16 + 4 * r + (lane >> 4), c = tc * 16 + (lane & 15);
-                        if (a < k && c <= k) Ap[a * kLdA + c] = acc[r];
+                    for (int q = 0; q < RMAX; ++q) {
+                        cEr[q] = bld(bE, row_off(q));
+                        cWr[q] = bld(bW, row_off(q));
+                        cNr[q] = bld(bN, row_off(q));
+                        cSr[q] = bld(bS, row_off(q));
                     }
+                }
+                const int H = o.H;
+                store_col<RMAX>(W + (size_t)k * ldv, ldv, rb);
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                    [&](int c, const double(&col)[RMAX]) {
+                    double *vb = (nbuf == 2 && (c & 1)) ? vbuf1 : vbuf;
+                    if (nbuf == 1 && c > 0) lds_barrier();   // readers of the previous column
+                    store_rows_lds<RMAX>(vb, col);
+                    lds_barrier();
+                    double y[RMAX];
+#pragma unroll
+                    for (int q = 0; q < RMAX; ++q) {
+                        const double *u = vb + threadIdx.x + q * kNT;
+                        y[q] = o.cd * u[0] + cEr[q] * u[H] + cWr[q] * u[-H] + cNr[q] * u[1]
+                               + cSr[q] * u[-1];
+                    }
+                    store_col<RMAX>(W + (size_t)c * ldv, ldv, y);
+                });
+                __syncthreads();   // W rows written by other threads are read below
+                // [V_k^T A' V_k | V_k^T r_base]: rows split over the waves, all tiles per wave,
+                // column tiles two at a time; partial tiles reduced across waves in a fixed order.
+                const int ktr = (k + 15) / 16, ktc = (k + 16) / 16;
+                const rsrc_t rV = mkbuf(V, ldv * (k + 1)), rW = mkbuf(W, ldv * (k + 1));
+                double *tred = Ap + (kMMax + 1) * kLdA;   // kNW x 256 partial tile
+                for (int tc0 = 0; tc0 < ktc; tc0 += 2) {
+                    const int ntc = ktc - tc0 < 2 ? ktc - tc0 : 2;
+#define XKP_VTW(R_, C_) vtw_chunk<R_, C_>(rV, rW, n, ldv, k, tc0, Ap, tred)
+                    switch (ktr * 2 + ntc - 1) {
+                    case 2: XKP_VTW(1, 1); break;
+                    case 3: XKP_VTW(1, 2); break;
+                    case 4: XKP_VTW(2, 1); break;
+                    case 5: XKP_VTW(2, 2); break;
+                    case 6: XKP_VTW(3, 1); break;
+                    case 7: XKP_VTW(3, 2); break;
+                    case 8: XKP_VTW(4, 1); break;
+                    default: XKP_VTW(4, 2); break;
+                    }
+#undef XKP_VTW
                 }
                 lds_barrier();
                 if (wave == 0) {
@@ -719,15 +823,22 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
             if (tid == 0) pivl[kMMax - 1] = singular ? 1 : 0;
             lds_barrier();
             singular = pivl[kMMax - 1] != 0;
-            if (!singular) {
-                // x0 = x_base + V_k alpha
-                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
-                    [&](int c, const double(&col)[RMAX]) {
-                    const double al = alpha[c];
+        }
+        // x0 = x_base + V_k alpha (x_base reloaded: not kept live through the projection)
+        double xr[RMAX];
+        if (s.x0) {
+            load_rows<RMAX>(s.x0, n, xr);
+        } else {
 #pragma unroll
-                    for (int q = 0; q < RMAX; ++q) xr[q] += al * col[q];
-                });
-            }
+            for (int q = 0; q < RMAX; ++q) xr[q] = 0.0;
+        }
+        if (k > 0 && !singular) {
+            sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                [&](int c, const double(&col)[RMAX]) {
+                const double al = alpha[c];
+#pragma unroll
+                for (int q = 0; q < RMAX; ++q) xr[q] += al * col[q];
+            });
         }
         store_rows<RMAX>(s.x, n, xr);
         if (tid == 0) {
@@ -895,13 +1006,17 @@ hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_
 hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
                           int nsys, int n_bases, const void *const *bases, xkp_params P,
                           xkp_info *infos, double *ws, WsLayout L, int nmax) {
-    const int nl = nlds > (kMMax + 1) * kLdA ? nlds : (kMMax + 1) * kLdA;
-    const size_t lds = project_lds_bytes(nl);
+    // two vector copies when they fit next to the rest, else one (two barriers per column)
+    const int small = (kMMax + 1) * kLdA + kNW * 256;
+    int nbuf = 2;
+    if (project_lds_bytes(2 * nlds > small ? 2 * nlds : small) > 150 * 1024) nbuf = 1;
+    const int nregion = nbuf * nlds > small ? nbuf * nlds : small;
+    const size_t lds = project_lds_bytes(nregion);
     XKP_DISPATCH(rmax, {
         hipError_t e = set_lds(project_kernel<R>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(project_kernel<R>, dim3(grid), dim3(kNT), lds, st, sys, nsys, n_bases,
-                           bases, P, infos, ws, L, nmax, nl);
+                           bases, P, infos, ws, L, nmax, nlds, nbuf, nregion);
     });
     return hipGetLastError();
 }
