@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-targets", type=int, default=7)
+    ap.add_argument("--cpu-targets", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -19,7 +19,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libxkp.so")
-SOURCES = ["xkp_kernels.hip", "xkp_api.hip"]
+# (source, object, extra flags): the kernel file is compiled once per workgroup size
+UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIANT=v512"]),
+         ("xkp_common.hip", "xkp_common.o", []),
+         ("xkp_api.hip", "xkp_api.o", [])]
 ARCH = os.environ.get("XKP_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
@@ -43,11 +46,21 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OUT, exist_ok=True)
     hipcc = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(OUT, src.replace(".hip", ".o"))
-        _run([hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
-              os.path.join(CSRC, src), "-o", obj], verbose)
+    procs = []
+    for src, objname, extra in UNITS:
+        obj = os.path.join(OUT, objname)
+        cmd = [hipcc, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                            text=True)))
         objs.append(obj)
+    for cmd, pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out + err)
+            raise RuntimeError("build step failed: " + " ".join(cmd[:3]))
     # link-time stub: every HIP runtime symbol the objects use, no SONAME
     undef = set()
     for o in objs:

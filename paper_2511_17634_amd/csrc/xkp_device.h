@@ -5,9 +5,17 @@
 
 #include "xkp.h"
 
-namespace xkp {
+#ifndef XKP_NT
+#define XKP_NT 512
+#endif
+#ifndef XKP_VARIANT
+#define XKP_VARIANT v512
+#endif
 
-constexpr int kNT = 512;            // threads per workgroup
+namespace xkp {
+namespace XKP_VARIANT {
+
+constexpr int kNT = XKP_NT;         // threads per workgroup
 constexpr int kNW = kNT / 64;       // wavefronts per workgroup
 constexpr int kMMax = 64;           // largest restart length / basis dimension
 constexpr int kRedSlots = 8;        // values reduced together by block_sum_multi
@@ -130,4 +138,5 @@ struct RowIdx {
     }
 };
 
+}  // namespace XKP_VARIANT
 }  // namespace xkp

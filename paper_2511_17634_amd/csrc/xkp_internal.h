@@ -7,12 +7,13 @@
 
 namespace xkp {
 
-// Per-workgroup workspace, in doubles, for systems of at most nmax unknowns and restart m.
+// Per-workgroup workspace, in doubles, for systems of at most nmax unknowns and restart m;
+// npad is the padded row count (threads x rows per thread) of the kernel variant used.
 struct WsLayout {
     size_t v, cE, cW, cN, cS, w, stride;
-    int npad;   // rows covered by the kernel variant (kNT * rmax), coefficient array length
+    int npad;   // rows covered by the kernel variant, coefficient array length
 };
-WsLayout ws_layout(int nmax, int mmax);
+WsLayout ws_layout(int nmax, int mmax, int npad);
 
 // Byte offsets inside a seed basis buffer (the layout documented in xkp.h): V columns have
 // leading dimension ldv = roundup(n + 1, 8) doubles, element n (and the rest of the column
@@ -34,25 +35,29 @@ enum GmresFlags {
     kTarget = 4        // honour a status already written by the projection kernel
 };
 
-// Rows per thread the kernel variant is compiled for; a batch uses the smallest variant whose
-// capacity kNT * rmax covers its largest system.
-int rmax_for(int n);
+// The kernel file can be compiled once per workgroup size into its own namespace; the build
+// uses v512 (512 threads; 2, 8 or 32 rows per thread).  A variant reports the rows per thread
+// it would use for n unknowns (0: too large), and the zero-padded LDS vector length.
+#define XKP_DECLARE_VARIANT(NS)                                                                  \
+    namespace NS {                                                                               \
+    int threads();                                                                               \
+    int rmax_for(int n);                                                                         \
+    int lds_vec_len(int nmax);                                                                   \
+    hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys, \
+                            int nsys, xkp_params P, int flags, void *const *bases,               \
+                            xkp_info *infos, double *ws, WsLayout L, int nmax);                  \
+    hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds,                      \
+                              const xkp_system *sys, int nsys, int n_bases,                      \
+                              const void *const *bases, xkp_params P, xkp_info *infos,           \
+                              double *ws, WsLayout L, int nmax);                                 \
+    hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds,                     \
+                               const xkp_system *sys, int nsys, double *rel, int nmax);          \
+    hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,   \
+                          int nmax);                                                             \
+    hipError_t launch_apply(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys, \
+                            int nsys, int nmax);                                                 \
+    }
 
-// Length in doubles of the zero-padded LDS copy of a grid vector: the variant's rows plus one
-// grid column (+1) so that the stencil's forward neighbours need no clamp.
-int lds_vec_len(int nmax);
-
-hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                        int nsys, xkp_params P, int flags, void *const *bases, xkp_info *infos,
-                        double *ws, WsLayout L, int nmax);
-hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                          int nsys, int n_bases, const void *const *bases, xkp_params P,
-                          xkp_info *infos, double *ws, WsLayout L, int nmax);
-hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                           int nsys, double *rel, int nmax);
-hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,
-                      int nmax);
-hipError_t launch_apply(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                        int nsys, int nmax);
+XKP_DECLARE_VARIANT(v512)
 
 }  // namespace xkp

@@ -16,7 +16,18 @@
 #include "xkp_device.h"
 #include "xkp_internal.h"
 
+#ifndef XKP_DEPTH4
+#define XKP_DEPTH4 4
+#endif
+#ifndef XKP_DEPTH16
+#define XKP_DEPTH16 1
+#endif
+#ifndef XKP_DEPTH32
+#define XKP_DEPTH32 2
+#endif
+
 namespace xkp {
+namespace XKP_VARIANT {
 
 constexpr int kLdA = 81;   // leading dimension of the projected matrix in LDS (<= 80 columns)
 
@@ -35,13 +46,16 @@ __device__ __forceinline__ rsrc_t mkbuf(const double *base, int count) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), (short)0, count * 8,
                                              kRsrcWord3);
 }
-__device__ __forceinline__ double bld(rsrc_t r, unsigned byte_off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+__device__ __forceinline__ double bld(rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, soff, 0));
 }
-__device__ __forceinline__ void bst(rsrc_t r, unsigned byte_off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, 0, 0);
+__device__ __forceinline__ void bst(rsrc_t r, unsigned byte_off, double v, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, soff, 0);
 }
 __device__ __forceinline__ unsigned row_off(int k) { return (threadIdx.x + k * kNT) * 8u; }
+// Row k of this thread = lane offset (one register) + scalar offset k * kNT * 8.
+__device__ __forceinline__ unsigned lane_off() { return threadIdx.x * 8u; }
+__device__ __forceinline__ unsigned row_soff(int k) { return (unsigned)(k * kNT * 8); }
 
 // Plain global accessors (global address space) for the few non-row accesses.
 typedef __attribute__((address_space(1))) const double gcdouble;
@@ -54,15 +68,17 @@ __device__ __forceinline__ double ld(const double *__restrict__ base, unsigned i
 template <int RMAX>
 __device__ __forceinline__ void load_rows(const double *__restrict__ v, int n, double (&r)[RMAX]) {
     const rsrc_t b = mkbuf(v, n);
+    const unsigned lo = lane_off();
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, row_off(k));
+    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, lo, row_soff(k));
 }
 
 template <int RMAX>
 __device__ __forceinline__ void store_rows(double *__restrict__ v, int n, const double (&r)[RMAX]) {
     const rsrc_t b = mkbuf(v, n);
+    const unsigned lo = lane_off();
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) bst(b, row_off(k), r[k]);
+    for (int k = 0; k < RMAX; ++k) bst(b, lo, r[k], row_soff(k));
 }
 
 template <int RMAX>
@@ -93,8 +109,9 @@ __device__ __forceinline__ void store_col(double *__restrict__ v, int ldv, const
 
 template <int RMAX>
 __device__ __forceinline__ void load_buf(rsrc_t b, double (&r)[RMAX]) {
+    const unsigned lo = lane_off();
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, row_off(k));
+    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, lo, row_soff(k));
 }
 
 // Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), with a ring of D columns
@@ -125,10 +142,13 @@ __device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int n, 
     }
 }
 
-template <int R> struct Depth { static constexpr int value = 4; };
+// Prefetch depth per rows-per-thread, bounded by the register budget of the variant.
+template <int R> struct Depth { static constexpr int value = 2; };
 template <> struct Depth<2> { static constexpr int value = 8; };
+template <> struct Depth<4> { static constexpr int value = XKP_DEPTH4; };
 template <> struct Depth<8> { static constexpr int value = 3; };
-template <> struct Depth<32> { static constexpr int value = 1; };
+template <> struct Depth<16> { static constexpr int value = XKP_DEPTH16; };
+template <> struct Depth<32> { static constexpr int value = XKP_DEPTH32; };
 
 // Per-row off-diagonal coefficients of the operator (Section 2.3), in the workspace:
 //   C_east  = -g^2/(2h^2) + f_x/(2h) - g^2/(8h^2) (m~_{i+1,j} - m~_{i-1,j})
@@ -184,12 +204,13 @@ __device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, cons
     const double *uc = u + threadIdx.x;
     const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
     const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
+    const unsigned lo = lane_off();
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        const unsigned off = row_off(k);
+        const unsigned so = row_soff(k);
         const double *q = uc + k * kNT;
-        w[k] = o.cd * q[0] + bld(bE, off) * q[H] + bld(bW, off) * q[-H] + bld(bN, off) * q[1]
-               + bld(bS, off) * q[-1];
+        w[k] = o.cd * q[0] + bld(bE, lo, so) * q[H] + bld(bW, lo, so) * q[-H]
+               + bld(bN, lo, so) * q[1] + bld(bS, lo, so) * q[-1];
         // bound the scheduling region: issuing every row's loads at once needs more registers
         // than the kernel has while the basis prefetch is in flight
         if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
@@ -334,9 +355,18 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                 double gcur = beta;
                 int kk = 0;
                 for (int j = 0; j < m; ++j) {
+                    // With many rows per thread the Krylov vector w lives in the LDS copy of
+                    // v_j (free once the operator has read it) instead of registers.
+                    constexpr bool kWL = RMAX >= 32;
+                    double *wl = L.vbuf + tid;
                     stencil_lds<RMAX>(L.vbuf, C, o, w);
                     ++iters;
                     const double wsq = dot_rows<RMAX>(w, w);
+                    if constexpr (kWL) {
+                        lds_barrier();   // every thread has read its neighbours of v_j
+#pragma unroll
+                        for (int k = 0; k < RMAX; ++k) wl[k * kNT] = w[k];
+                    }
                     double wn0 = 0.0, t = 0.0;
                     // two modified Gram-Schmidt passes over v_0..v_j as one sweep of 2(j+1)
                     // column visits; the second pass re-orthogonalises and completes h_{i,j}
@@ -344,17 +374,29 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                     sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, nc, 2 * nc,
                         [&](int q, const double(&col)[RMAX]) {
                         const int i = q < nc ? q : q - nc;
+                        double part = 0.0;
+                        if constexpr (kWL) {
+#pragma unroll
+                            for (int k = 0; k < RMAX; ++k) part += wl[k * kNT] * col[k];
+                        } else {
+                            part = dot_rows<RMAX>(w, col);
+                        }
                         double d;
                         if (q == 0) {
-                            double two[2] = {dot_rows<RMAX>(w, col), wsq};
+                            double two[2] = {part, wsq};
                             br.sum_multi<2>(two);
                             d = two[0];
                             wn0 = sqrt(two[1]);
                         } else {
-                            d = br.sum(dot_rows<RMAX>(w, col));
+                            d = br.sum(part);
                         }
+                        if constexpr (kWL) {
 #pragma unroll
-                        for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
+                            for (int k = 0; k < RMAX; ++k) wl[k * kNT] -= d * col[k];
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
+                        }
                         if (q < nc) {
                             if (tid == 0) L.h1[i] = d;
                         } else {
@@ -371,6 +413,10 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                             }
                         }
                     });
+                    if constexpr (kWL) {
+#pragma unroll
+                        for (int k = 0; k < RMAX; ++k) w[k] = wl[k * kNT];
+                    }
                     const double hn = sqrt(br.sum(dot_rows<RMAX>(w, w)));
                     const bool brk = !(hn > 1e-14 * wn0);
 #pragma unroll
@@ -732,8 +778,11 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                 // W = [A' V_k | r_base] in the workspace.  Each thread keeps its rows'
                 // coefficients in registers; the basis columns stream through the prefetch ring
                 // and, for the neighbours, through one of two zero-padded LDS copies.
-                double cEr[RMAX], cWr[RMAX], cNr[RMAX], cSr[RMAX];
-                {
+                // (with 32 rows per thread the coefficients are re-read from the workspace
+                // instead: four register arrays of 32 would not fit)
+                constexpr int RC = RMAX >= 32 ? 1 : RMAX;
+                double cEr[RC], cWr[RC], cNr[RC], cSr[RC];
+                if constexpr (RMAX < 32) {
                     const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
                     const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
 #pragma unroll
@@ -753,11 +802,15 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                     store_rows_lds<RMAX>(vb, col);
                     lds_barrier();
                     double y[RMAX];
+                    if constexpr (RMAX < 32) {
 #pragma unroll
-                    for (int q = 0; q < RMAX; ++q) {
-                        const double *u = vb + threadIdx.x + q * kNT;
-                        y[q] = o.cd * u[0] + cEr[q] * u[H] + cWr[q] * u[-H] + cNr[q] * u[1]
-                               + cSr[q] * u[-1];
+                        for (int q = 0; q < RMAX; ++q) {
+                            const double *u = vb + threadIdx.x + q * kNT;
+                            y[q] = o.cd * u[0] + cEr[q] * u[H] + cWr[q] * u[-H] + cNr[q] * u[1]
+                                   + cSr[q] * u[-1];
+                        }
+                    } else {
+                        stencil_lds<RMAX>(vb, C, o, y);
                     }
                     store_col<RMAX>(W + (size_t)c * ldv, ldv, y);
                 });
@@ -930,33 +983,35 @@ __global__ __launch_bounds__(kNT) void rhs_kernel(const xkp_system *__restrict__
 // ----------------------------------------------------------------------------------------
 // Host launchers
 
-WsLayout ws_layout(int nmax, int mmax) {
-    auto up = [](size_t v) { return (v + 63) & ~(size_t)63; };
-    WsLayout L;
-    L.npad = kNT * rmax_for(nmax);
-    L.v = 0;
-    L.cE = up((size_t)basis_ldv(nmax) * (mmax + 1));
-    L.cW = L.cE + up(L.npad);
-    L.cN = L.cW + up(L.npad);
-    L.cS = L.cN + up(L.npad);
-    L.w = L.cS + up(L.npad);
-    L.stride = L.w + up((size_t)basis_ldv(nmax) * (mmax + 1));
-    return L;
-}
+int threads() { return kNT; }
 
-size_t basis_off_v() { return 256; }
-int basis_ldv(int n) { return (n + 8) & ~7; }
-size_t basis_bytes(int n, int m) {
-    size_t o = basis_off_vb(n, m) + 2 * (size_t)basis_ldv(n) * (m + 1);
-    return (o + 255) & ~(size_t)255;
-}
-
+#if XKP_NT == 512
 int rmax_for(int n) {
     if (n <= kNT * 2) return 2;
     if (n <= kNT * 8) return 8;
     if (n <= kNT * 32) return 32;
     return 0;
 }
+#define XKP_DISPATCH(RM, CALL)                       \
+    switch (RM) {                                    \
+    case 2: { constexpr int R = 2; CALL; } break;    \
+    case 8: { constexpr int R = 8; CALL; } break;    \
+    case 32: { constexpr int R = 32; CALL; } break;  \
+    default: return hipErrorInvalidValue;            \
+    }
+#else
+int rmax_for(int n) {
+    if (n <= kNT * 4) return 4;
+    if (n <= kNT * 16) return 16;
+    return 0;
+}
+#define XKP_DISPATCH(RM, CALL)                       \
+    switch (RM) {                                    \
+    case 4: { constexpr int R = 4; CALL; } break;    \
+    case 16: { constexpr int R = 16; CALL; } break;  \
+    default: return hipErrorInvalidValue;            \
+    }
+#endif
 
 int lds_vec_len(int nmax) {
     int h = 1;
@@ -982,13 +1037,6 @@ static hipError_t set_lds(K kern, size_t bytes) {
                                (int)bytes);
 }
 
-#define XKP_DISPATCH(RM, CALL)                     \
-    switch (RM) {                                  \
-    case 2: { constexpr int R = 2; CALL; } break;  \
-    case 8: { constexpr int R = 8; CALL; } break;  \
-    case 32: { constexpr int R = 32; CALL; } break; \
-    default: return hipErrorInvalidValue;          \
-    }
 
 hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
                         int nsys, xkp_params P, int flags, void *const *bases, xkp_info *infos,
@@ -1052,4 +1100,5 @@ hipError_t launch_apply(hipStream_t st, int grid, int rmax, int nlds, const xkp_
     return hipGetLastError();
 }
 
+}  // namespace XKP_VARIANT
 }  // namespace xkp
