@@ -63,21 +63,12 @@ def run_leg(Chain, args, H, T, m, s0, t0, method, mode, torch):
     elapsed = time.perf_counter() - t_start
     kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
     seed_inf, tgt_inf = ch.all_infos()
+    import numpy as np
     ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
     if method == "project":
         ok = ok and bool((seed_inf["status"] == 0).all())
     # independent FP64 check of the last timestep through the residual entry point
-    rel = torch.empty(ch.N, dtype=torch.float64, device=ch.dev)
-    par = ch.step_no & 1
-    import numpy as np
-    from paper_2511_17634_amd import xkp
-    prev = ch.mt[1 - par]   # m^{T-1}: operator and rhs of the last solve
-    bt = torch.empty_like(prev)
-    d = xkp.pack_batch(H, 1.0 / T, 0.5, prev, bt, ch.mt[par])
-    ch.ctx.build_rhs(d, ch.N)
-    ch.ctx.residual(d, ch.N, rel)
-    torch.cuda.synchronize()
-    rel = rel.cpu().numpy()
+    rel = ch.verify_last()
     ok = ok and bool((rel <= args.tol * (1 + 1e-6)).all())
     return {
         "elapsed": elapsed, "ok": ok, "kernel_ms_last_chain": kernel_ms,

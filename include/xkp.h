@@ -85,7 +85,8 @@ typedef struct {
     int32_t batch_max_n;  /* largest n among this call's systems, or 0 for the context's
                              max_n; smaller values select leaner kernels.  A system with more
                              unknowns than this gets status XKP_EINVAL.                    */
-    int32_t reserved;     /* must be 0                                                      */
+    int32_t polish_m;     /* targets: restart length of the polish (and of plain GMRES),
+                             1..64, or 0 for m.  The seed basis dimension stays m.          */
 } xkp_params;
 
 /* Per-system outcome, device-resident. */
@@ -132,6 +133,18 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
 size_t xkp_basis_bytes(int32_t n, int32_t m);
 
 /*
+ * Batches.  Each of xkp_seed_build and xkp_target_project_solve is ONE persistent kernel launch
+ * over its whole batch.  Systems of different sizes may share a batch (params->batch_max_n, or
+ * the context's max_n, bounds them); each runs the code path compiled for its own size.
+ * Workgroups take systems from a work queue in array order, so ordering a batch largest first
+ * balances it (longest-processing-time first).  Results do not depend on the order or on which
+ * workgroup solved a system.  Calls enqueue work on the context's stream without host
+ * synchronisation and allocate nothing, so a sequence of them can be captured in a HIP graph
+ * and replayed; calls on one context must not run concurrently (they share its workspace and
+ * work-queue counters).
+ */
+
+/*
  * Phase 1 (Section 3): solve each of the n_seeds seed systems by restarted GMRES(m) from
  * seeds[i].x0 (NULL: zero) to params->tol, write the solution to seeds[i].x and the first
  * cycle's basis V, Hessenberg matrix and header into the buffer bases[i].
@@ -166,6 +179,31 @@ xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems)
 
 /* y_i = A_i u_i for a batch (the stencil operator alone): u = systems[i].x0, y = systems[i].x. */
 xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems);
+
+/* Outcome of xkp_autotune. */
+typedef struct {
+    int32_t polish_m;     /* fastest restart length of the polish (for params->polish_m)    */
+    int32_t wg_per_cu;    /* fastest workgroups per compute unit (now set in the context)    */
+    float ms_best;        /* time of one call with the chosen values, milliseconds           */
+    float ms_default;     /* time with polish_m = m and the most workgroups per compute unit */
+    int32_t n_tried;      /* candidates timed                                               */
+    int32_t pad;
+} xkp_tuning;
+
+/*
+ * Launch autotuner for target calls: times xkp_target_project_solve on the given batch (one
+ * representative timestep) for each candidate restart length of the polish (m/2, 3m/4 and m,
+ * at least 8) and each workgroup count per compute unit the kernels can hold (1..occupancy),
+ * two timed calls each after one untimed call, and keeps the fastest candidate whose every
+ * target converged.  The chosen workgroup count is stored in the context and applies to its
+ * later seed and target calls; the chosen restart length is returned for the caller's params.
+ * Side effects: targets[i].x and infos hold the last candidate's results.  Unlike the other
+ * calls this one synchronises the stream (it reads timings and statuses back), so it must not
+ * be captured in a graph.  Returns XKP_ENOCONV if no candidate converged everywhere.
+ */
+xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                        int32_t n_bases, const void *const *bases, const xkp_params *params,
+                        xkp_info *infos, xkp_tuning *out);
 
 /* Static description of a status code. */
 const char *xkp_status_string(xkp_status s);

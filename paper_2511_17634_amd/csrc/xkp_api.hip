@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <new>
+#include <vector>
 
 #include "xkp.h"
 #include "xkp_internal.h"
@@ -10,9 +11,12 @@ struct xkp_ctx {
     int device;
     hipStream_t stream;
     int max_n, max_m, max_batch;
-    int slots;          // workgroups that own a workspace slot
+    int slots;          // workgroups that own a workspace slot (the largest grid launched)
     xkp::WsLayout L;
     double *ws;
+    unsigned *queue;    // work-queue counters of the solve kernels (reset by each launch)
+    int cus;            // compute units of the device
+    int per_cu;         // workgroups per compute unit used for the grid (autotuned)
 };
 
 namespace {
@@ -24,16 +28,16 @@ struct Variant {
     int (*threads)();
     int (*rmax_for)(int);
     int (*lds_vec_len)(int);
-    decltype(&xkp::v512::launch_gmres) gmres;
-    decltype(&xkp::v512::launch_project) project;
+    int (*solve_per_cu)(int);
+    decltype(&xkp::v512::launch_solve) solve;
     decltype(&xkp::v512::launch_residual) residual;
     decltype(&xkp::v512::launch_rhs) rhs;
     decltype(&xkp::v512::launch_apply) apply;
 };
 #define XKP_VARIANT_TABLE(NS)                                                          \
     Variant {                                                                          \
-        xkp::NS::threads, xkp::NS::rmax_for, xkp::NS::lds_vec_len, xkp::NS::launch_gmres, \
-            xkp::NS::launch_project, xkp::NS::launch_residual, xkp::NS::launch_rhs,    \
+        xkp::NS::threads, xkp::NS::rmax_for, xkp::NS::lds_vec_len, xkp::NS::solve_per_cu, \
+            xkp::NS::launch_solve, xkp::NS::launch_residual, xkp::NS::launch_rhs,      \
             xkp::NS::launch_apply                                                      \
     }
 const Variant kV512 = XKP_VARIANT_TABLE(v512);
@@ -49,7 +53,7 @@ xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const 
                       int *nmax, int *rmax, const Variant **var) {
     if (!ctx || count < 0 || (count > 0 && !arr) || !P) return XKP_EINVAL;
     if (P->m < 1 || P->m > ctx->max_m || !(P->tol >= 0.0) || P->max_restarts < 0 ||
-        P->reserved != 0 || P->batch_max_n < 0 || P->batch_max_n > ctx->max_n)
+        P->polish_m < 0 || P->polish_m > ctx->max_m || P->batch_max_n < 0 || P->batch_max_n > ctx->max_n)
         return XKP_EINVAL;
     if (P->precision != XKP_FP64 && P->precision != XKP_MIXED) return XKP_EINVAL;
     if (P->mode < XKP_PROJ_TARGET_GALERKIN || P->mode > XKP_PROJ_NONE) return XKP_EINVAL;
@@ -58,6 +62,13 @@ xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const 
     if (!*var) return XKP_EUNSUPPORTED;
     *rmax = (*var)->rmax_for(*nmax);
     return XKP_OK;
+}
+
+// Workgroups of a solve launch over `count` systems.
+int solve_grid(const xkp_ctx *ctx, int count) {
+    int g = ctx->per_cu * ctx->cus;
+    if (g > ctx->slots) g = ctx->slots;
+    return count < g ? count : g;
 }
 
 }  // namespace
@@ -80,11 +91,32 @@ xkp_status xkp_ctx_create(xkp_ctx **out, int device, void *hip_stream, int32_t m
     c->max_n = max_n;
     c->max_m = max_m;
     c->max_batch = max_batch;
-    c->slots = max_batch < 4 * cus ? max_batch : 4 * cus;
+    // one workspace slot per workgroup that can be resident at once: a larger grid would only
+    // add workgroups that find the work queue empty
+    const int per_cu = choose(max_n)->solve_per_cu(max_n);
+    if (per_cu < 1) {
+        delete c;
+        return XKP_EDEVICE;
+    }
+    c->slots = max_batch < per_cu * cus ? max_batch : per_cu * cus;
+    c->cus = cus;
+    c->per_cu = per_cu;
     c->L = xkp::ws_layout(max_n, max_m, npad_for(max_n));
     if (hipMalloc((void **)&c->ws, sizeof(double) * c->L.stride * (size_t)c->slots) != hipSuccess) {
         delete c;
         return XKP_ENOMEM;
+    }
+    if (hipMalloc((void **)&c->queue, 2 * sizeof(unsigned)) != hipSuccess) {
+        hipFree(c->ws);
+        delete c;
+        return XKP_ENOMEM;
+    }
+    if (hipMemset(c->queue, 0, 2 * sizeof(unsigned)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        hipFree(c->queue);
+        hipFree(c->ws);
+        delete c;
+        return XKP_EDEVICE;
     }
     *out = c;
     return XKP_OK;
@@ -94,8 +126,9 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     if (!ctx) return XKP_EINVAL;
     hipError_t e = hipStreamSynchronize(ctx->stream);
     hipError_t f = hipFree(ctx->ws);
+    hipError_t q = hipFree(ctx->queue);
     delete ctx;
-    return (e == hipSuccess && f == hipSuccess) ? XKP_OK : XKP_EDEVICE;
+    return (e == hipSuccess && f == hipSuccess && q == hipSuccess) ? XKP_OK : XKP_EDEVICE;
 }
 
 size_t xkp_basis_bytes(int32_t n, int32_t m) {
@@ -112,9 +145,10 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     if (n_seeds > 0 && (!bases || !infos)) return XKP_EINVAL;
     if (n_seeds == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    const int grid = n_seeds < ctx->slots ? n_seeds : ctx->slots;
-    return from_hip(v->gmres(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
-                             *params, xkp::kKeepBasis, bases, infos, ctx->ws, ctx->L, nmax));
+    const int grid = solve_grid(ctx, n_seeds);
+    return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
+                             *params, xkp::kKeepBasis, 0, nullptr, bases, infos, ctx->ws, ctx->L,
+                             nmax, ctx->queue));
 }
 
 xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
@@ -129,17 +163,11 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
         return XKP_EINVAL;
     if (n_targets == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    const int grid = n_targets < ctx->slots ? n_targets : ctx->slots;
-    int flags = 0;
-    if (params->mode != XKP_PROJ_NONE) {
-        hipError_t e = v->project(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets,
-                                  n_targets, n_bases, bases, *params, infos, ctx->ws, ctx->L,
-                                  nmax);
-        if (e != hipSuccess) return XKP_EDEVICE;
-        flags = xkp::kStartFromX | xkp::kTarget;
-    }
-    return from_hip(v->gmres(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
-                             *params, flags, nullptr, infos, ctx->ws, ctx->L, nmax));
+    const int grid = solve_grid(ctx, n_targets);
+    const int flags = params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0;
+    return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
+                             *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
+                             nmax, ctx->queue));
 }
 
 xkp_status xkp_residual(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, double *rel_res) {
@@ -170,6 +198,88 @@ xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {
     const Variant *v = choose(ctx->max_n);
     return from_hip(v->apply(ctx->stream, grid, v->rmax_for(ctx->max_n),
                              v->lds_vec_len(ctx->max_n), systems, n_sys, ctx->max_n));
+}
+
+xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                        int32_t n_bases, const void *const *bases, const xkp_params *params,
+                        xkp_info *infos, xkp_tuning *out) {
+    if (!ctx || !params || !out || n_targets < 1 || !targets || !infos) return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int m = params->m;
+    int cand_m[3] = {m / 2, (3 * m) / 4, m};
+    for (int &c : cand_m) {
+        if (c < 8) c = 8;
+        if (c > m) c = m;
+    }
+    int nb = 0;
+    {
+        int nmax = 0, rmax = 0;
+        const Variant *v = nullptr;
+        xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
+        if (st != XKP_OK) return st;
+        nb = v->solve_per_cu(nmax);
+        if (nb < 1) return XKP_EDEVICE;
+        if (nb * ctx->cus > ctx->slots) nb = (ctx->slots + ctx->cus - 1) / ctx->cus;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return XKP_EDEVICE;
+    }
+    std::vector<xkp_info> host(n_targets);
+    const int saved = ctx->per_cu;
+    xkp_status result = XKP_OK;
+    float best = -1.f, def = -1.f;
+    int best_m = m, best_w = saved, tried = 0;
+    for (int ci = 0; ci < 3 && result == XKP_OK; ++ci) {
+        if (ci > 0 && cand_m[ci] == cand_m[ci - 1]) continue;
+        for (int w = 1; w <= nb && result == XKP_OK; ++w) {
+            xkp_params P = *params;
+            P.polish_m = cand_m[ci];
+            ctx->per_cu = w;
+            float ms = 0.f;
+            for (int rep = 0; rep < 3 && result == XKP_OK; ++rep) {
+                if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess) result = XKP_EDEVICE;
+                xkp_status st = xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
+                                                         &P, infos);
+                if (st != XKP_OK) result = st;
+            }
+            if (result != XKP_OK) break;
+            if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+                hipMemcpy(host.data(), infos, sizeof(xkp_info) * n_targets,
+                          hipMemcpyDeviceToHost) != hipSuccess) {
+                result = XKP_EDEVICE;
+                break;
+            }
+            ms *= 0.5f;
+            ++tried;
+            bool ok = true;
+            for (const xkp_info &i : host) ok = ok && (i.status == XKP_OK || i.status == XKP_ESINGULAR);
+            if (cand_m[ci] == m && w == nb) def = ms;
+            if (ok && (best < 0.f || ms < best)) {
+                best = ms;
+                best_m = cand_m[ci];
+                best_w = w;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (result != XKP_OK) {
+        ctx->per_cu = saved;
+        return result;
+    }
+    out->polish_m = best_m;
+    out->wg_per_cu = best_w;
+    out->ms_best = best;
+    out->ms_default = def;
+    out->n_tried = tried;
+    out->pad = 0;
+    ctx->per_cu = best < 0.f ? saved : best_w;
+    return best < 0.f ? XKP_ENOCONV : XKP_OK;
 }
 
 const char *xkp_status_string(xkp_status s) {

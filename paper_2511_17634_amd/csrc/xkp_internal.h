@@ -32,7 +32,7 @@ size_t basis_bytes(int n, int m);
 enum GmresFlags {
     kStartFromX = 1,   // initial guess is the descriptor's x (the projected x0)
     kKeepBasis = 2,    // seed build: write the first cycle into bases[i]
-    kTarget = 4        // honour a status already written by the projection kernel
+    kTarget = 4        // project onto the seed basis first, then polish from the projection
 };
 
 // The kernel file can be compiled once per workgroup size into its own namespace; the build
@@ -43,13 +43,12 @@ enum GmresFlags {
     int threads();                                                                               \
     int rmax_for(int n);                                                                         \
     int lds_vec_len(int nmax);                                                                   \
-    hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys, \
-                            int nsys, xkp_params P, int flags, void *const *bases,               \
-                            xkp_info *infos, double *ws, WsLayout L, int nmax);                  \
-    hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds,                      \
-                              const xkp_system *sys, int nsys, int n_bases,                      \
-                              const void *const *bases, xkp_params P, xkp_info *infos,           \
-                              double *ws, WsLayout L, int nmax);                                 \
+    int solve_per_cu(int nmax);                                                                  \
+    hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys, \
+                            int nsys, xkp_params P, int flags, int n_bases,                      \
+                            const void *const *bases, void *const *keep_bases,                   \
+                            xkp_info *infos, double *ws, WsLayout L, int nmax,                   \
+                            unsigned *queue);                                                    \
     hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds,                     \
                                const xkp_system *sys, int nsys, double *rel, int nmax);          \
     hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,   \

@@ -5,14 +5,18 @@
 // read and written only by the thread owning the row, so global memory needs no cross-thread
 // ordering; the stencil's neighbour values come from an LDS copy of the vector.
 //
-//   gmres_kernel    restarted GMRES(m): stencil operator (Section 2.3), Arnoldi with modified
+//   solve_kernel    one persistent launch per batch, systems taken from a work queue:
+//     gmres_one     restarted GMRES(m): stencil operator (Section 2.3), Arnoldi with modified
 //                   Gram-Schmidt done twice, Givens rotations, restart on the FP64 true
 //                   residual; optionally keeps the first cycle as the seed basis (Section 3,
 //                   Phase 1) or starts from the projected guess (Phase 2 polish).
-//   project_kernel  Phase 2 projection of each target onto its seed basis: the k x k system
+//     project_one   Phase 2 projection of a target onto its seed basis: the k x k system
 //                   V^T A' V (FP64 matrix cores), H_k, or the least-squares Hessenberg problem,
 //                   solved by one wavefront; x0 = x_base + V alpha.
 //   residual_kernel ||b - A x|| / ||b|| in FP64;  apply_kernel y = A u.
+#include <mutex>
+#include <vector>
+
 #include "xkp_device.h"
 #include "xkp_internal.h"
 
@@ -302,8 +306,10 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
                           xkp_basis_header *hdr, double *Vfirst, double *Hb, double *Vws,
                           const Coef &C, xkp_info *info, GmresLds &L) {
     const OpConst o = op_const(s);
-    const int n = o.n, m = P.m, tid = threadIdx.x, ldv = ldv_for(o.n);
     const bool keep = hdr != nullptr;
+    // restart length: the kept seed cycle has m steps; targets may polish with another length
+    const int n = o.n, m = (keep || P.polish_m <= 0) ? P.m : P.polish_m;
+    const int tid = threadIdx.x, ldv = ldv_for(o.n);
     BlockRed br{L.red, 0};
 
     build_coeffs<RMAX>(s, o, C);
@@ -509,39 +515,6 @@ __device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, i
     __syncthreads();
 }
 
-template <int RMAX>
-__global__ __launch_bounds__(kNT) void gmres_kernel(const xkp_system *__restrict__ sys, int nsys,
-                                                    xkp_params P, int flags, void *const *bases,
-                                                    xkp_info *infos, double *ws, WsLayout Lw,
-                                                    int nmax, int nlds) {
-    extern __shared__ double lds[];
-    GmresLds L(lds, nlds, kNT * RMAX);
-    for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;   // the pads stay zero
-    lds_barrier();
-    double *slot = ws + (size_t)blockIdx.x * Lw.stride;
-    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
-    for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
-        const xkp_system s = sys[si];
-        xkp_info *info = infos + si;
-        int pre = XKP_OK;
-        if (flags & kTarget) pre = info->status;
-        if (!desc_ok(s, nmax) || P.m < 1 || P.m > kMMax) {
-            if (threadIdx.x == 0) info->status = XKP_EINVAL;
-            continue;
-        }
-        if (pre == XKP_EINVAL) continue;
-        xkp_basis_header *hdr = nullptr;
-        double *Vfirst = slot + Lw.v, *Hb = nullptr;
-        if (flags & kKeepBasis) {
-            char *base = (char *)bases[si];
-            hdr = (xkp_basis_header *)base;
-            Vfirst = (double *)(base + 256);
-            Hb = (double *)(base + basis_off_h(s.H * s.H, P.m));
-        }
-        gmres_one<RMAX>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, L);
-    }
-}
-
 // ----------------------------------------------------------------------------------------
 // Projection (Section 3, Phase 2)
 
@@ -708,16 +681,15 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
     }
 }
 
+// Projection of one target onto its seed basis (Section 3, Phase 2): writes x0 = x_base + V alpha
+// into s.x and returns XKP_OK, XKP_ESINGULAR (the projected system was singular: x0 = x_base)
+// or XKP_EINVAL (no usable basis: s.x untouched, info->status set).  The LDS holds nbuf
+// zero-padded vector copies (each nlds long) during the operator applications, then the
+// projected matrix and the tile-reduction scratch: never live together.
 template <int RMAX>
-__global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restrict__ sys, int nsys,
-                                                      int n_bases, const void *const *bases,
-                                                      xkp_params P, xkp_info *infos, double *ws,
-                                                      WsLayout Lw, int nmax, int nlds,
-                                                      int nbuf, int nregion) {
-    extern __shared__ double lds[];
-    // The LDS region holds nbuf zero-padded vector copies (each nlds long) during the operator
-    // applications, then the projected matrix and the tile-reduction scratch: never live
-    // together.
+__device__ int project_one(const xkp_system &s, xkp_info *info, int n_bases,
+                           const void *const *bases, const xkp_params &P, const Coef &C,
+                           double *W, double *lds, int nlds, int nbuf, int nregion) {
     double *vbuf = lds + (nlds - kNT * RMAX) / 2;   // after the front pad
     double *vbuf1 = vbuf + nlds;
     double *Ap = lds;
@@ -725,19 +697,12 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
     double *alpha = zv + kMMax + 1;    // kMMax
     int *pivl = (int *)(alpha + kMMax);
     double *red = alpha + kMMax + kMMax / 2;
-    double *slot = ws + (size_t)blockIdx.x * Lw.stride;
-    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
-    double *W = slot + Lw.w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
-        const xkp_system s = sys[si];
-        xkp_info *info = infos + si;
+    {
         const int n = s.H * s.H;
         const xkp_basis_header *hdr = nullptr;
         int k = 0;
-        bool ok = desc_ok(s, nmax) && P.m >= 1 && P.m <= kMMax && s.basis_id >= 0 &&
-                  s.basis_id < n_bases;
+        bool ok = s.basis_id >= 0 && s.basis_id < n_bases;
         if (ok) {
             hdr = (const xkp_basis_header *)bases[s.basis_id];
             ok = hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m;
@@ -748,7 +713,7 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
                 info->status = XKP_EINVAL;
                 info->basis_dim = 0;
             }
-            continue;
+            return XKP_EINVAL;
         }
         const int m = P.m;
         const double *V = (const double *)((const char *)hdr + 256);
@@ -894,11 +859,110 @@ __global__ __launch_bounds__(kNT) void project_kernel(const xkp_system *__restri
             });
         }
         store_rows<RMAX>(s.x, n, xr);
-        if (tid == 0) {
-            info->status = singular ? XKP_ESINGULAR : XKP_OK;
-            info->basis_dim = k;
-        }
+        if (tid == 0) info->basis_dim = k;
+        // the polish reads x0 rows written by other threads, and reuses the LDS
         __syncthreads();
+        return singular ? XKP_ESINGULAR : XKP_OK;
+    }
+}
+
+// ----------------------------------------------------------------------------------------
+// The batched solve: one persistent launch over a batch of systems of possibly different sizes.
+// Workgroups take systems from a work queue (an atomic counter) in descriptor order, so a batch
+// ordered largest first is balanced as in longest-processing-time-first scheduling.  Each system
+// runs the code path compiled for the smallest rows-per-thread count that covers it.
+//   seeds   (kKeepBasis): restarted GMRES from x0 = 0, first cycle kept (Section 3, Phase 1)
+//   targets (kTarget):    projection onto the seed basis, then GMRES polish from the projected
+//                         guess (Phase 2)
+//   plain   (no flag):    restarted GMRES from x_base
+// queue[0] counts the systems handed out and queue[1] the workgroups that have finished; the last
+// workgroup to finish sets both back to zero, so consecutive launches on the stream, and replays
+// of a captured graph, need no reset.
+
+#if XKP_NT == 512
+constexpr int kRClass0 = 2, kRClass1 = 8;
+#else
+constexpr int kRClass0 = 4, kRClass1 = 16;
+#endif
+
+template <int R, bool PROJ>
+__device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
+                                          const xkp_params &P, int flags, int n_bases,
+                                          const void *const *bases, void *keep_base,
+                                          const Coef &C, double *slot, const WsLayout &Lw,
+                                          double *lds, int nlds, int nbuf, int nregion) {
+    int pre = XKP_OK;
+    if constexpr (PROJ) {
+        pre = project_one<R>(s, info, n_bases, bases, P, C, slot + Lw.w, lds, nlds, nbuf,
+                             nregion);
+        if (pre == XKP_EINVAL) return;
+        flags |= kStartFromX;
+    }
+    // the GMRES vector copy needs zero pads: clear what the previous system or the projection
+    // left in the LDS
+    for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;
+    lds_barrier();
+    GmresLds L(lds, nlds, kNT * R);
+    xkp_basis_header *hdr = nullptr;
+    double *Vfirst = slot + Lw.v, *Hb = nullptr;
+    if (keep_base) {
+        hdr = (xkp_basis_header *)keep_base;
+        Vfirst = (double *)((char *)keep_base + 256);
+        Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
+    }
+    gmres_one<R>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, L);
+}
+
+template <int RMAX, bool PROJ>
+__global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict__ sys, int nsys,
+                                                    xkp_params P, int flags, int n_bases,
+                                                    const void *const *bases,
+                                                    void *const *keep_bases, xkp_info *infos,
+                                                    double *ws, WsLayout Lw, int nmax, int nlds,
+                                                    int nbuf, int nregion, unsigned *queue) {
+    extern __shared__ double lds[];
+    __shared__ int next[2];
+    double *slot = ws + (size_t)blockIdx.x * Lw.stride;
+    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
+    for (int it = 0;; ++it) {
+        // alternating broadcast slots: a fast thread 0 can fetch the next index before slow
+        // waves have read this one without overwriting it
+        if (threadIdx.x == 0) next[it & 1] = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int si = next[it & 1];
+        if (si >= nsys) break;
+        const xkp_system s = sys[si];
+        xkp_info *info = infos + si;
+        if (!desc_ok(s, nmax) || P.m < 1 || P.m > kMMax || P.polish_m < 0 || P.polish_m > kMMax) {
+            if (threadIdx.x == 0) info->status = XKP_EINVAL;
+            continue;
+        }
+        void *kb = (flags & kKeepBasis) ? keep_bases[si] : nullptr;
+        const int n = s.H * s.H;
+#define XKP_SOLVE(R_) \
+    solve_one<R_, PROJ>(s, info, P, flags, n_bases, bases, kb, C, slot, Lw, lds, nlds, nbuf, nregion)
+        if constexpr (RMAX > kRClass0) {
+            if (n <= kNT * kRClass0) {
+                XKP_SOLVE(kRClass0);
+                continue;
+            }
+        }
+        if constexpr (RMAX > kRClass1) {
+            if (n <= kNT * kRClass1) {
+                XKP_SOLVE(kRClass1);
+                continue;
+            }
+        }
+        XKP_SOLVE(RMAX);
+#undef XKP_SOLVE
+    }
+    if (threadIdx.x == 0) {
+        // every workgroup's last fetch precedes its increment here (the fetched value decided
+        // the exit), so the last one to arrive may reset the queue
+        if (atomicAdd(queue + 1, 1u) == gridDim.x - 1) {
+            atomicExch(queue, 0u);
+            atomicExch(queue + 1, 0u);
+        }
     }
 }
 
@@ -1031,42 +1095,105 @@ static size_t small_lds_bytes(int nlds) {
     return sizeof(double) * ((size_t)nlds + 2 * kRedSlots * kNW);
 }
 
+// Raises a kernel's dynamic-LDS limit once per kernel and device (to the largest size asked
+// for): a launch enqueued later, for instance inside a graph capture, makes no attribute call.
+static hipError_t set_lds_ptr(const void *kern, size_t bytes) {
+    struct Entry {
+        const void *kern;
+        int dev;
+        size_t bytes;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    for (Entry &d : done)
+        if (d.kern == kern && d.dev == dev) {
+            if (d.bytes >= bytes) return hipSuccess;
+            e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e == hipSuccess) d.bytes = bytes;
+            return e;
+        }
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done.push_back({kern, dev, bytes});
+    return e;
+}
 template <typename K>
 static hipError_t set_lds(K kern, size_t bytes) {
-    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    return set_lds_ptr((const void *)kern, bytes);
 }
 
 
-hipError_t launch_gmres(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                        int nsys, xkp_params P, int flags, void *const *bases, xkp_info *infos,
-                        double *ws, WsLayout L, int nmax) {
-    const size_t lds = gmres_lds_bytes(nlds);
+// LDS plan of a solve launch: the GMRES layout, and for projected targets the projection's
+// vector copies (two when they fit next to the rest, else one: two barriers per column).
+struct SolvePlan {
+    int nbuf, nregion;
+    size_t lds;
+};
+static SolvePlan solve_plan(int nlds, bool proj) {
+    SolvePlan sp{1, nlds, gmres_lds_bytes(nlds)};
+    if (proj) {
+        const int small = (kMMax + 1) * kLdA + kNW * 256;
+        sp.nbuf = 2;
+        if (project_lds_bytes(2 * nlds > small ? 2 * nlds : small) > 150 * 1024) sp.nbuf = 1;
+        sp.nregion = sp.nbuf * nlds > small ? sp.nbuf * nlds : small;
+        const size_t pl = project_lds_bytes(sp.nregion);
+        if (pl > sp.lds) sp.lds = pl;
+    }
+    return sp;
+}
+
+hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
+                        int nsys, xkp_params P, int flags, int n_bases, const void *const *bases,
+                        void *const *keep_bases, xkp_info *infos, double *ws, WsLayout L,
+                        int nmax, unsigned *queue) {
+    const bool proj = (flags & kTarget) != 0;
+    const SolvePlan sp = solve_plan(nlds, proj);
+#define XKP_LAUNCH_SOLVE(PJ)                                                                   \
+    {                                                                                          \
+        hipError_t e = set_lds(solve_kernel<R, PJ>, sp.lds);                                   \
+        if (e != hipSuccess) return e;                                                         \
+        hipLaunchKernelGGL((solve_kernel<R, PJ>), dim3(grid), dim3(kNT), sp.lds, st, sys, nsys, \
+                           P, flags, n_bases, bases, keep_bases, infos, ws, L, nmax, nlds,     \
+                           sp.nbuf, sp.nregion, queue);                                        \
+    }
     XKP_DISPATCH(rmax, {
-        hipError_t e = set_lds(gmres_kernel<R>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gmres_kernel<R>, dim3(grid), dim3(kNT), lds, st, sys, nsys, P, flags,
-                           bases, infos, ws, L, nmax, nlds);
+        if (proj) XKP_LAUNCH_SOLVE(true) else XKP_LAUNCH_SOLVE(false)
     });
+#undef XKP_LAUNCH_SOLVE
     return hipGetLastError();
 }
 
-hipError_t launch_project(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
-                          int nsys, int n_bases, const void *const *bases, xkp_params P,
-                          xkp_info *infos, double *ws, WsLayout L, int nmax) {
-    // two vector copies when they fit next to the rest, else one (two barriers per column)
-    const int small = (kMMax + 1) * kLdA + kNW * 256;
-    int nbuf = 2;
-    if (project_lds_bytes(2 * nlds > small ? 2 * nlds : small) > 150 * 1024) nbuf = 1;
-    const int nregion = nbuf * nlds > small ? nbuf * nlds : small;
-    const size_t lds = project_lds_bytes(nregion);
-    XKP_DISPATCH(rmax, {
-        hipError_t e = set_lds(project_kernel<R>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(project_kernel<R>, dim3(grid), dim3(kNT), lds, st, sys, nsys, n_bases,
-                           bases, P, infos, ws, L, nmax, nlds, nbuf, nregion);
-    });
-    return hipGetLastError();
+// Workgroups of the solve kernels for systems of up to nmax unknowns that can be resident on one
+// compute unit at once (the larger of the projected and plain kernels), 0 on error.
+int solve_per_cu(int nmax) {
+    const int rmax = rmax_for(nmax), nlds = lds_vec_len(nmax);
+    int best = 0;
+    for (int pj = 0; pj < 2; ++pj) {
+        const SolvePlan sp = solve_plan(nlds, pj != 0);
+        int nb = 0;
+        hipError_t e = hipSuccess;
+        auto occ = [&](const void *k) {
+            e = set_lds_ptr(k, sp.lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kNT, sp.lds);
+        };
+        switch (rmax) {
+#if XKP_NT == 512
+        case 2: occ(pj ? (const void *)solve_kernel<2, true> : (const void *)solve_kernel<2, false>); break;
+        case 8: occ(pj ? (const void *)solve_kernel<8, true> : (const void *)solve_kernel<8, false>); break;
+        case 32: occ(pj ? (const void *)solve_kernel<32, true> : (const void *)solve_kernel<32, false>); break;
+#else
+        case 4: occ(pj ? (const void *)solve_kernel<4, true> : (const void *)solve_kernel<4, false>); break;
+        case 16: occ(pj ? (const void *)solve_kernel<16, true> : (const void *)solve_kernel<16, false>); break;
+#endif
+        default: return 0;
+        }
+        if (e != hipSuccess) return 0;
+        if (nb > best) best = nb;
+    }
+    return best;
 }
 
 hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,

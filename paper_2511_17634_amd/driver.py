@@ -1,11 +1,17 @@
 """Timestep chain of the method on the GPU, built only from libxkp calls.
 
-Per timestep n (Section 2.3: one implicit solve per image and timestep, dt = 1/T, one
+Per timestep n (Section 2.3: one implicit solve per image, channel and timestep, dt = 1/T, one
 linearisation pass m~ = m^{n-1}; Section 3: seed phase then target phase):
-  xkp_build_rhs            b = m^{n-1}/dt for the seed and every target
-  xkp_seed_build           seed GMRES, first-cycle basis V^n kept       (projection only)
-  xkp_target_project_solve projection onto V^n + GMRES polish, or plain GMRES
+  xkp_build_rhs            b = m^{n-1}/dt for every seed and every target
+  xkp_seed_build           all seeds in one launch, first-cycle bases V^n kept (projection only)
+  xkp_target_project_solve all targets in one launch: projection onto their seed's V^n + GMRES
+                           polish, or plain GMRES
 and the solution buffers become the next step's m^{n-1} (double buffering, no copies).
+
+A batch holds one or more groups; a group is one grid size with C channels, one seed image and
+N target images.  Every channel of every image is its own system (C seeds and N*C targets per
+group); a target uses the basis of its own group's seed in the same channel.  Targets are laid
+out largest grid first, the order in which the work queue hands them out.
 """
 from __future__ import annotations
 
@@ -14,125 +20,273 @@ import numpy as np
 from . import xkp
 
 
-class Chain:
-    """Seed and targets of one grid size advanced together through the timesteps.
+class Group:
+    """One grid size: seed_m0 (C, n) and target_m0 (N, C, n) initial states, n = H*H."""
 
-    With `pipeline` (projection only) the seed runs on its own stream and context one timestep
-    ahead of the targets: the seed of step n+1 overlaps the targets of step n.  The seed basis is
-    double-buffered; events order seed n before targets n, and targets n before seed n+2 (which
-    overwrites the basis targets n read).  All streams keep the default priority.
+    def __init__(self, H, seed_m0, target_m0):
+        n = H * H
+        self.H, self.n = H, n
+        s = np.asarray(seed_m0, dtype=np.float64)
+        self.C = s.size // n
+        self.seed_m0 = np.ascontiguousarray(s.reshape(self.C, n))
+        t = np.asarray(target_m0, dtype=np.float64)
+        self.target_m0 = np.ascontiguousarray(t.reshape(-1, self.C, n))
+        self.N = self.target_m0.shape[0]
+
+
+class Batch:
+    """Seeds and targets of several grid sizes advanced together through the timesteps.
+
+    With `pipeline` (projection only) the seeds run on their own stream and context one timestep
+    ahead of the targets: the seeds of step n+1 overlap the targets of step n.  The bases are
+    double-buffered; events order seeds n before targets n, and targets n before seeds n+2
+    (which overwrite the bases targets n read).  All streams keep the default priority.
+
+    The work of one full chain (reset + T steps) can be captured once in a HIP graph
+    (`capture`) and replayed (`replay`); the eager `run` enqueues the same calls.
     """
 
-    def __init__(self, H, T, m, seed_m0, target_m0, g=0.5, tol=1e-8, method="project",
-                 mode="target_galerkin", warm=False, max_restarts=1000, device=0, ctx=None,
-                 precision=xkp.FP64, pipeline=True):
+    def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
+                 mode="target_galerkin", warm=False, max_restarts=1000, device=0,
+                 precision=xkp.FP64, pipeline=True, polish_m=0):
         import torch
-        self.H, self.T, self.m, self.g, self.tol = H, T, m, g, tol
-        self.n = n = H * H
+        self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
+        self.T, self.m, self.g, self.tol = T, m, g, tol
         self.method = method
         self.dev = torch.device(f"cuda:{device}")
-        tgt = np.ascontiguousarray(np.asarray(target_m0, dtype=np.float64).reshape(-1, n))
-        self.N = N = tgt.shape[0]
-        self.ctx = ctx or xkp.Context(n, m, max(N, 1), device=device)
+        self.nmax = max(gr.n for gr in self.groups)
+        self.S = sum(gr.C for gr in self.groups)
+        self.N = sum(gr.N * gr.C for gr in self.groups)
+        self.s_main = torch.cuda.Stream(device=self.dev)
+        self.ctx = xkp.Context(self.nmax, m, max(self.N, 1), device=device, stream=self.s_main)
         self.pipeline = pipeline and method == "project"
         if self.pipeline:
             self.s_seed = torch.cuda.Stream(device=self.dev)
-            self.ctx_seed = xkp.Context(n, m, 1, device=device, stream=self.s_seed)
+            self.ctx_seed = xkp.Context(self.nmax, m, self.S, device=device, stream=self.s_seed)
             self.ev_seed = [torch.cuda.Event(), torch.cuda.Event()]
             self.ev_tgt = [torch.cuda.Event(), torch.cuda.Event()]
             self.ev_reset = torch.cuda.Event()
         else:
             self.ctx_seed = self.ctx
+        # flat storage: seed systems (group, channel) then target systems (group, target, channel)
+        so = to = 0
+        self.seed_sys, self.tgt_sys = [], []       # (H, offset, basis id)
+        for gr in self.groups:
+            base_id = len(self.seed_sys)
+            for c in range(gr.C):
+                self.seed_sys.append((gr.H, so, base_id + c))
+                so += gr.n
+            for t in range(gr.N):
+                for c in range(gr.C):
+                    self.tgt_sys.append((gr.H, to, base_id + c))
+                    to += gr.n
         f64 = dict(dtype=torch.float64, device=self.dev)
-        self.ms = [torch.tensor(np.asarray(seed_m0, dtype=np.float64).reshape(1, n), **f64),
-                   torch.empty((1, n), **f64)]
-        self.mt = [torch.tensor(tgt, **f64), torch.empty((N, n), **f64)]
-        self.bs = torch.empty((1, n), **f64)
-        self.bt = torch.empty((N, n), **f64)
-        self.bases = xkp.Bases(2, n, m, device=device)
-        dt = 1.0 / T
+        s0 = np.concatenate([gr.seed_m0.reshape(-1) for gr in self.groups])
+        t0 = np.concatenate([gr.target_m0.reshape(-1) for gr in self.groups])
+        self.m0 = (torch.tensor(s0, **f64), torch.tensor(t0, **f64))
+        self.ms = [self.m0[0].clone(), torch.empty_like(self.m0[0])]
+        self.mt = [self.m0[1].clone(), torch.empty_like(self.m0[1])]
+        self.bs = torch.empty_like(self.m0[0])
+        self.bt = torch.empty_like(self.m0[1])
+        ns = [H * H for H, _, _ in self.seed_sys]
+        self.bases = xkp.Bases(2 * self.S, ns * 2, m, device=device)
+        self.dt = 1.0 / T
         mode_id = xkp.NONE if method == "plain" else xkp.MODES[mode]
         self.params = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
-                                         precision=precision, mode=mode_id, batch_max_n=n)
-        self.seed_desc, self.tgt_desc = [], []
-        for par in (0, 1):
-            sd = xkp.pack_batch(H, dt, g, self.ms[par], self.bs, self.ms[1 - par],
-                                x0=self.ms[par] if warm else None)
-            td = xkp.pack_batch(H, dt, g, self.mt[par], self.bt, self.mt[1 - par],
-                                x0=self.mt[par] if warm else None, basis_id=0)
-            self.seed_desc.append(sd)
-            self.tgt_desc.append(td)
+                                         precision=precision, mode=mode_id,
+                                         batch_max_n=self.nmax, polish_m=polish_m)
+        self.warm = warm
+        self.seed_desc = [self._desc(self.seed_sys, self.ms, self.bs, par) for par in (0, 1)]
+        self.tgt_desc = [self._desc(self.tgt_sys, self.mt, self.bt, par) for par in (0, 1)]
         # one info record per system and timestep, so that every solve can be verified
-        self.info_s_all = self.ctx.new_infos(T)
-        self.info_t_all = self.ctx.new_infos(T * N)
-        self.m0 = (self.ms[0].clone(), self.mt[0].clone())
+        self.info_s_all = self.ctx.new_infos(T * self.S)
+        self.info_t_all = self.ctx.new_infos(T * self.N)
         self.step_no = 0
+        self.graph = None
+        torch.cuda.synchronize(self.dev)     # inputs copied on the current stream are in place
 
-    def reset(self):
-        """Back to the initial images (a device-to-device copy of the state)."""
+    def _desc(self, systems, state, b, par, x_from=None):
+        """Descriptors of `systems` at a step of parity par: m~ = state[par], solution into
+        state[1 - par] (or x_from)."""
         import torch
-        if self.pipeline:
-            # the seed stream may still be a step ahead: let the copies wait for it
-            torch.cuda.current_stream(self.dev).wait_stream(self.s_seed)
-        self.ms[0].copy_(self.m0[0])
-        self.mt[0].copy_(self.m0[1])
-        if self.pipeline:
-            self.ev_reset.record(torch.cuda.current_stream(self.dev))
-            self.s_seed.wait_event(self.ev_reset)
+        a = np.zeros(len(systems), dtype=xkp.SYSTEM_DTYPE)
+        mt = state[par].data_ptr()
+        x = (x_from if x_from is not None else state[1 - par]).data_ptr()
+        bp = b.data_ptr()
+        for i, (H, off, bid) in enumerate(systems):
+            o = 8 * off
+            a[i] = (H, bid, self.dt, self.g, mt + o, 0, 0, bp + o,
+                    (mt + o) if self.warm else 0, x + o)
+        d = torch.from_numpy(a.view(np.uint8).copy()).to(self.dev)
+        d._xkp_keep = [state[0], state[1], b]
+        return d
+
+    # -- eager enqueue --------------------------------------------------------------------
+
+    def reset(self, join_seed=True):
+        """Back to the initial images (device-to-device copies on the main stream)."""
+        import torch
+        with torch.cuda.stream(self.s_main):
+            if self.pipeline and join_seed:
+                # the seed stream may still be a step ahead: let the copies wait for it
+                self.s_main.wait_stream(self.s_seed)
+            self.ms[0].copy_(self.m0[0])
+            self.mt[0].copy_(self.m0[1])
+            if self.pipeline:
+                self.ev_reset.record(self.s_main)
+                self.s_seed.wait_event(self.ev_reset)
         self.step_no = 0
 
     def _info_slices(self, t):
         w = xkp.INFO_DTYPE.itemsize
-        return (self.info_s_all[t * w:(t + 1) * w],
+        return (self.info_s_all[t * self.S * w:(t + 1) * self.S * w],
                 self.info_t_all[t * self.N * w:(t + 1) * self.N * w])
 
-    @property
-    def info_s(self):
-        return self._info_slices((self.step_no - 1) % self.T)[0]
-
-    @property
-    def info_t(self):
-        return self._info_slices((self.step_no - 1) % self.T)[1]
-
     def step(self, events=None):
-        """Enqueue one timestep on the context's stream.  `events`, if given, is a pair of
-        HIP events recorded around the target call."""
+        """Enqueue one timestep.  `events`, if given, is a pair of HIP events recorded on the
+        main stream around the target call."""
         par = self.step_no & 1
         c = self.ctx
         inf_s, inf_t = self._info_slices(self.step_no % self.T)
-        basis = self.bases.ptrs[par:par + 1]
+        bases = self.bases.ptrs[par * self.S:(par + 1) * self.S]
         if self.method == "project":
             cs = self.ctx_seed
             if self.pipeline and self.step_no >= 2:
-                self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with this basis
-            cs.build_rhs(self.seed_desc[par], 1)
-            cs.seed_build(self.seed_desc[par], 1, basis, self.params, inf_s)
+                self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
+            cs.build_rhs(self.seed_desc[par], self.S)
+            cs.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
             if self.pipeline:
                 self.ev_seed[par].record(self.s_seed)
                 c.stream.wait_event(self.ev_seed[par])
         c.build_rhs(self.tgt_desc[par], self.N)
         if events is not None:
             events[0].record(c.stream)
-        c.target_project_solve(self.tgt_desc[par], self.N, 1, basis, self.params, inf_t)
+        c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         if events is not None:
             events[1].record(c.stream)
         if self.pipeline:
             self.ev_tgt[par].record(c.stream)
         self.step_no += 1
 
+    def run(self):
+        """One full chain, eagerly enqueued."""
+        self.reset()
+        for _ in range(self.T):
+            self.step()
+
+    # -- graph ----------------------------------------------------------------------------
+
+    def capture(self):
+        """Capture reset + T steps as one HIP graph (run the chain eagerly once before, so that
+        every kernel attribute is set outside the capture)."""
+        import torch
+        torch.cuda.synchronize(self.dev)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=self.s_main):
+            self.reset(join_seed=False)
+            for _ in range(self.T):
+                self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        """Replay the captured chain on the main stream."""
+        import torch
+        self.s_main.wait_stream(torch.cuda.current_stream(self.dev))
+        with torch.cuda.stream(self.s_main):
+            self.graph.replay()
+        self.step_no = self.T
+
+    # -- tuning and results -----------------------------------------------------------------
+
+    def autotune(self, steps=2):
+        """Advance `steps` timesteps eagerly, then time the target call of the next timestep
+        over the candidates of xkp_autotune on its real inputs; the chosen polish restart length
+        goes into the params, the workgroup count into the context.  Resets the chain."""
+        import torch
+        self.reset()
+        for _ in range(steps):
+            self.step()
+        par = self.step_no & 1
+        bases = self.bases.ptrs[par * self.S:(par + 1) * self.S]
+        inf_s, inf_t = self._info_slices(self.step_no % self.T)
+        if self.method == "project":
+            self.ctx_seed.build_rhs(self.seed_desc[par], self.S)
+            self.ctx_seed.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
+        self.ctx.build_rhs(self.tgt_desc[par], self.N)
+        torch.cuda.synchronize(self.dev)
+        t = self.ctx.autotune(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
+        self.params.polish_m = t.polish_m
+        self.reset()
+        torch.cuda.synchronize(self.dev)
+        return t
+
+    def _join(self):
+        """Order the current stream after everything enqueued on the chain's streams."""
+        import torch
+        cur = torch.cuda.current_stream(self.dev)
+        cur.wait_stream(self.s_main)
+        if self.pipeline:
+            cur.wait_stream(self.s_seed)
+
     def all_infos(self):
-        """(seed infos [T], target infos [T, N]) of the last full chain."""
-        s = xkp.infos_to_numpy(self.info_s_all)
+        """(seed infos [T, S], target infos [T, N]) of the last full chain."""
+        self._join()
+        s = xkp.infos_to_numpy(self.info_s_all).reshape(self.T, self.S)
         t = xkp.infos_to_numpy(self.info_t_all).reshape(self.T, self.N)
         return s, t
 
+    def infos(self):
+        """(seed infos [S], target infos [N]) of the last step."""
+        self._join()
+        s, t = self._info_slices((self.step_no - 1) % self.T)
+        return xkp.infos_to_numpy(s), xkp.infos_to_numpy(t)
+
+    def state(self, par=None):
+        """(seed states [S*n...], target states) flat tensors after the last step."""
+        self._join()
+        p = (self.step_no & 1) if par is None else par
+        return self.ms[p], self.mt[p]
+
+    def group_states(self, gi):
+        """(seed (C, n), targets (N, C, n)) views of group gi's current state."""
+        gr = self.groups[gi]
+        ms, mt = self.state()
+        so = sum(g.C * g.n for g in self.groups[:gi])
+        to = sum(g.N * g.C * g.n for g in self.groups[:gi])
+        return (ms[so:so + gr.C * gr.n].view(gr.C, gr.n),
+                mt[to:to + gr.N * gr.C * gr.n].view(gr.N, gr.C, gr.n))
+
+    def verify_last(self):
+        """FP64 relative residual of every target's last solution (operator and right-hand side
+        of the last timestep rebuilt through the library)."""
+        import torch
+        par = self.step_no & 1
+        prev = 1 - par                       # m^{T-1} defined the last solve
+        bt = torch.empty_like(self.bt)
+        d = self._desc(self.tgt_sys, self.mt, bt, prev)
+        rel = torch.empty(self.N, dtype=torch.float64, device=self.dev)
+        self.s_main.wait_stream(torch.cuda.current_stream(self.dev))   # the descriptors' copy
+        with torch.cuda.stream(self.s_main):
+            self.ctx.build_rhs(d, self.N)
+            self.ctx.residual(d, self.N, rel)
+        self.s_main.synchronize()
+        return rel.cpu().numpy()
+
+
+class Chain(Batch):
+    """One grid size, one channel: seed_m0 (n,), target_m0 (N, n)."""
+
+    def __init__(self, H, T, m, seed_m0, target_m0, **kw):
+        n = H * H
+        t = np.asarray(target_m0, dtype=np.float64).reshape(-1, 1, n)
+        super().__init__([Group(H, np.asarray(seed_m0).reshape(1, n), t)], T, m, **kw)
+        self.H, self.n = H, n
+
     @property
     def seed_state(self):
-        return self.ms[self.step_no & 1][0]
+        return self.state()[0]
 
     @property
     def target_state(self):
-        return self.mt[self.step_no & 1]
-
-    def infos(self):
-        return xkp.infos_to_numpy(self.info_s), xkp.infos_to_numpy(self.info_t)
+        return self.state()[1].view(self.N, self.n)

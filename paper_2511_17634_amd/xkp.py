@@ -34,7 +34,12 @@ HEADER_BYTES = 256
 class Params(ct.Structure):
     _fields_ = [("m", ct.c_int32), ("max_restarts", ct.c_int32), ("tol", ct.c_double),
                 ("precision", ct.c_int32), ("mode", ct.c_int32), ("batch_max_n", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("polish_m", ct.c_int32)]
+
+
+class Tuning(ct.Structure):
+    _fields_ = [("polish_m", ct.c_int32), ("wg_per_cu", ct.c_int32), ("ms_best", ct.c_float),
+                ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("pad", ct.c_int32)]
 
 
 class XkpError(RuntimeError):
@@ -68,10 +73,13 @@ def load():
         lib.xkp_residual.argtypes = [P, ct.c_int32, P, P]
         lib.xkp_apply.argtypes = [P, ct.c_int32, P]
         lib.xkp_build_rhs.argtypes = [P, ct.c_int32, P]
+        lib.xkp_autotune.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(Params), P,
+                                     ct.POINTER(Tuning)]
         lib.xkp_status_string.argtypes = [ct.c_int]
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
-                  "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs"):
+                  "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
+                  "xkp_autotune"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -175,10 +183,10 @@ class Context:
 
     @staticmethod
     def params(m, tol=1e-8, max_restarts=1000, precision=FP64, mode=TARGET_GALERKIN,
-               batch_max_n=0):
+               batch_max_n=0, polish_m=0):
         if isinstance(mode, str):
             mode = MODES[mode]
-        return Params(m, max_restarts, tol, precision, mode, batch_max_n, 0)
+        return Params(m, max_restarts, tol, precision, mode, batch_max_n, polish_m)
 
     def new_infos(self, count):
         import torch
@@ -195,6 +203,15 @@ class Context:
                                                _ptr(bases_ptrs), ct.byref(params), _ptr(infos)),
                "xkp_target_project_solve")
 
+    def autotune(self, systems, n_sys, n_bases, bases_ptrs, params, infos) -> Tuning:
+        """Times candidate polish restart lengths and workgroups per compute unit on this batch
+        (host-synchronous); the workgroup count is kept by the context, the returned
+        polish_m goes into later params."""
+        t = Tuning()
+        _check(load().xkp_autotune(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
+                                   ct.byref(params), _ptr(infos), ct.byref(t)), "xkp_autotune")
+        return t
+
     def residual(self, systems, n_sys, rel_out):
         _check(load().xkp_residual(self._h, n_sys, _ptr(systems), _ptr(rel_out)), "xkp_residual")
 
@@ -206,41 +223,50 @@ class Context:
 
 
 class Bases:
-    """Device storage for `count` seed bases of n unknowns and restart length m."""
+    """Device storage for `count` seed bases of restart length m; n is the number of unknowns of
+    every basis, or a sequence giving each basis its own (batches of uneven sizes)."""
 
     def __init__(self, count, n, m, device=0):
         import torch
-        self.count, self.n, self.m = count, n, m
-        self.stride = basis_bytes(n, m)
-        self.buf = torch.zeros(count * self.stride, dtype=torch.uint8, device=f"cuda:{device}")
+        ns = [int(n)] * count if np.isscalar(n) else [int(v) for v in n]
+        assert len(ns) == count
+        self.count, self.m, self.ns = count, m, ns
+        self.n = ns[0] if len(set(ns)) == 1 else None
+        self.offsets = []
+        off = 0
+        for v in ns:
+            self.offsets.append(off)
+            off += (basis_bytes(v, m) + 255) & ~255
+        self.buf = torch.zeros(max(off, 256), dtype=torch.uint8, device=f"cuda:{device}")
         base = self.buf.data_ptr()
         assert base % 256 == 0
-        self.ptrs = torch.tensor([base + i * self.stride for i in range(count)],
-                                 dtype=torch.int64, device=f"cuda:{device}")
+        self.ptrs = torch.tensor([base + o for o in self.offsets], dtype=torch.int64,
+                                 device=f"cuda:{device}")
 
-    @property
-    def ldv(self):
-        """Leading dimension of V: roundup(n + 1, 8) doubles (zeros past row n)."""
-        return (self.n + 8) & ~7
+    def ldv(self, i=0):
+        """Leading dimension of basis i's V: roundup(n + 1, 8) doubles (zeros past row n)."""
+        return (self.ns[i] + 8) & ~7
 
     def header(self, i):
-        h = self.buf[i * self.stride:i * self.stride + 32].cpu().numpy().view(np.int32)
+        o = self.offsets[i]
+        h = self.buf[o:o + 32].cpu().numpy().view(np.int32)
         return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3]),
                 "ldv": int(h[6])}
 
     def V_padded(self, i):
         """(ldv, m+1) view of basis i's FP64 columns including the zero rows."""
         import torch
-        off = i * self.stride + HEADER_BYTES
-        raw = self.buf[off:off + 8 * self.ldv * (self.m + 1)]
-        return raw.view(torch.float64).view(self.m + 1, self.ldv).T
+        off = self.offsets[i] + HEADER_BYTES
+        ldv = self.ldv(i)
+        raw = self.buf[off:off + 8 * ldv * (self.m + 1)]
+        return raw.view(torch.float64).view(self.m + 1, ldv).T
 
     def V(self, i):
         """(n, m+1) view of basis i's FP64 columns."""
-        return self.V_padded(i)[:self.n]
+        return self.V_padded(i)[:self.ns[i]]
 
     def Hbar(self, i):
         import torch
-        off = i * self.stride + HEADER_BYTES + 8 * self.ldv * (self.m + 1)
+        off = self.offsets[i] + HEADER_BYTES + 8 * self.ldv(i) * (self.m + 1)
         raw = self.buf[off:off + 8 * (self.m + 1) * self.m]
         return raw.view(torch.float64).view(self.m, self.m + 1).T

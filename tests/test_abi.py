@@ -47,6 +47,8 @@ int main(void) {
          offsetof(xkp_system, mt), offsetof(xkp_system, x), sizeof(xkp_info), sizeof(xkp_params));
   printf("%zu %zu %zu\n", sizeof(xkp_basis_header), offsetof(xkp_info, res_est),
          offsetof(xkp_params, tol));
+  printf("%zu %zu %zu\n", offsetof(xkp_params, polish_m), sizeof(xkp_tuning),
+         offsetof(xkp_tuning, ms_default));
   return 0;
 }''')
     exe = tmp_path / "probe"
@@ -59,6 +61,8 @@ int main(void) {
     assert v[3] == S.fields["x"][1] and v[4] == I.itemsize and v[5] == ct.sizeof(xkp.Params)
     assert v[6] == xkp.HEADER_BYTES and v[7] == I.fields["res_est"][1]
     assert v[8] == xkp.Params.tol.offset
+    assert v[9] == xkp.Params.polish_m.offset and v[10] == ct.sizeof(xkp.Tuning)
+    assert v[11] == xkp.Tuning.ms_default.offset
 
 
 def test_host_side_errors_without_gpu(lib):
@@ -71,6 +75,8 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.xkp_seed_build(None, 1, None, None, ct.byref(P), None) == xkp.EINVAL
     assert lib.xkp_target_project_solve(None, 1, None, 0, None, ct.byref(P), None) == xkp.EINVAL
     assert lib.xkp_residual(None, 1, None, None) == xkp.EINVAL
+    t = xkp.Tuning()
+    assert lib.xkp_autotune(None, 1, None, 0, None, ct.byref(P), None, ct.byref(t)) == xkp.EINVAL
     assert xkp.basis_bytes(0, 10) == 0
     n, m = 4096, 40
     assert xkp.basis_bytes(n, m) >= 256 + 8 * n * (m + 1) + 8 * (m + 1) * m + 2 * n * (m + 1)
