@@ -1,12 +1,18 @@
 """Benchmark: target systems solved per second at FP64-verified relative residual 1e-8.
 
 Workload (one GPU): 64x64 grid (4096 unknowns), 1 seed + 63 targets (blob images, seed blobs
-jittered by N(0, 2 px), amplitudes scaled by U[0.9, 1.1]), T = 100 timesteps, seed basis and
-GMRES restart m = 40, tol 1e-8, FP64.  One step = the whole hot path over the batch: for each of
-the 100 timesteps, the right-hand sides, the seed GMRES with its kept basis, and the projection +
-GMRES polish of all 63 targets.  value = 63 * 100 * steps / elapsed seconds for the projection
-path (target-Galerkin mode); the same chain with plain GMRES and with the seed-Galerkin mode is
-timed beside it.  Inputs are resident in device memory before the timed region.
+jittered by N(0, 2 px), amplitudes scaled by U[0.9, 1.1]), T = 100 timesteps, seed basis
+dimension m = 40, tol 1e-8, FP64.  One step = the whole hot path over the batch: for each of the
+100 timesteps, the right-hand sides, the seed GMRES with its kept basis, and the projection +
+GMRES polish of all 63 targets, one persistent launch each.  value = 63 * 100 * steps / elapsed
+seconds for the projection path (target-Galerkin mode); the same chain with plain GMRES and with
+the seed-Galerkin mode is timed beside it.  Each chain is captured once as a HIP graph and
+replayed (--eager: enqueued call by call); the polish restart length and workgroups per compute
+unit come from the library's autotuner, run on the chain's own inputs before the timed region
+(--no-tune: restart length m).  Inputs are resident in device memory before the timed region.
+
+Also timed (--no-uneven skips it): the uneven batch, 32x32 / 64x64 / 128x128 grids with 3
+channels each (3072 target systems, 9 seeds) in one launch per timestep.
 
 Prints one JSON line.
 """
@@ -17,6 +23,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -30,7 +38,6 @@ def gmres_bytes(n, m, iters, restarts):
     Arnoldi step j reads v_0..v_j twice (16 n (j+1)), writes v_{j+1} (8 n) and applies the
     operator (read u and m~, write w: 24 n); each cycle end forms x += V y (8 n k) and the true
     residual (48 n)."""
-    import numpy as np
     iters = np.asarray(iters, dtype=np.int64)
     restarts = np.asarray(restarts, dtype=np.int64)
     total = 0
@@ -44,41 +51,74 @@ def gmres_bytes(n, m, iters, restarts):
     return total
 
 
-def run_leg(Chain, args, H, T, m, s0, t0, method, mode, torch):
-    ch = Chain(H, T, m, s0, t0, method=method, mode=mode)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(T)]
-    for _ in range(args.warmup):
-        ch.reset()
-        for _ in range(T):
-            ch.step()
+def build_c2():
+    from synth import CONFIGS, config_images, initial_state
+    cfg = CONFIGS["c2"]
+    seed, tg = config_images(cfg, 0)
+    s0 = initial_state(seed[0])
+    t0 = np.stack([initial_state(t[0]) for t in tg])
+    return cfg, s0, t0
+
+
+def build_c4():
+    """Groups of the uneven workload: 32x32, 64x64 and 128x128, 3 channels each."""
+    from paper_2511_17634_amd.driver import Group
+    from synth import CONFIGS, config_images
+    cfg = CONFIGS["c4"]
+    groups = []
+    for gi, gr in enumerate(cfg.groups):
+        seed, tg = config_images(cfg, gi)
+        groups.append(Group(gr.H, seed.reshape(cfg.channels, -1),
+                            tg.reshape(tg.shape[0], cfg.channels, -1)))
+    return cfg, groups
+
+
+def time_chain(b, args, steps, warmup, graph=True):
+    """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
+    captured graph (or enqueued eagerly), then verify every solve of the last chain."""
+    import torch
+    for _ in range(warmup):
+        b.run()
     torch.cuda.synchronize()
-    kernel_ms = 0.0
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        ch.reset()
-        for t in range(T):
-            ch.step(events=ev[t] if s == args.steps - 1 else None)
+    if graph:
+        b.capture()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        if graph:
+            b.replay()
+        else:
+            b.run()
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
-    seed_inf, tgt_inf = ch.all_infos()
-    import numpy as np
+    elapsed = time.perf_counter() - t0
+    seed_inf, tgt_inf = b.all_infos()
     ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
-    if method == "project":
+    if b.method == "project":
         ok = ok and bool((seed_inf["status"] == 0).all())
     # independent FP64 check of the last timestep through the residual entry point
-    rel = ch.verify_last()
+    rel = b.verify_last()
     ok = ok and bool((rel <= args.tol * (1 + 1e-6)).all())
     return {
-        "elapsed": elapsed, "ok": ok, "kernel_ms_last_chain": kernel_ms,
-        "iters_mean": float(tgt_inf["iters"].mean()), "iters_total": int(tgt_inf["iters"].sum()),
+        "elapsed": elapsed, "ok": ok, "per_chain_s": elapsed / steps,
+        "iters_mean": float(tgt_inf["iters"].mean()),
         "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"],
-        "seed_iters_total": int(seed_inf["iters"].sum()) if method == "project" else 0,
+        "seed_iters_total": int(seed_inf["iters"].sum()) if b.method == "project" else 0,
         "guess_res_mean": float(np.mean(tgt_inf["guess_res"])),
         "max_res": float(max(tgt_inf["res_true"].max(), rel.max())),
-        "N": ch.N,
+        "N": b.N, "polish_m": int(b.params.polish_m) or b.m,
     }
+
+
+def target_call_ms(b):
+    """Per-timestep duration of the target launch (HIP events on the launch's stream) over one
+    eager chain."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(b.T)]
+    b.reset()
+    for t in range(b.T):
+        b.step(events=ev[t])
+    torch.cuda.synchronize()
+    return [a.elapsed_time(e) for a, e in ev]
 
 
 def cpu_baseline(H, T, m, s0, t0, n_targets, steps):
@@ -101,6 +141,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size batch")
+    ap.add_argument("--no-tune", action="store_true", help="default launch parameters")
+    ap.add_argument("--eager", action="store_true", help="enqueue eagerly instead of a graph")
+    ap.add_argument("--uneven-steps", type=int, default=1)
     ap.add_argument("--cpu-targets", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     args = ap.parse_args()
@@ -109,36 +153,38 @@ def main():
               "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
     from paper_2511_17634_amd import xkp
-    from paper_2511_17634_amd.driver import Chain
-    from synth import CONFIGS, config_images, initial_state
+    from paper_2511_17634_amd.driver import Batch, Chain
 
     xkp.load()
-    cfg = CONFIGS["c2"]
+    cfg, s0, t0 = build_c2()
     H, T, m = cfg.groups[0].H, cfg.T, cfg.m
-    seed, tg = config_images(cfg, 0)
-    s0 = initial_state(seed[0])
-    t0 = np.stack([initial_state(t[0]) for t in tg])
     n = H * H
+    graph = not args.eager
 
-    legs = {}
+    legs, tunings = {}, {}
     for name, method, mode in (("project", "project", "target_galerkin"),
                                ("project_seed_galerkin", "project", "seed_galerkin"),
                                ("plain", "plain", "none")):
-        legs[name] = run_leg(Chain, args, H, T, m, s0, t0, method, mode, torch)
-        print(f"# {name}: {legs[name]['elapsed']:.3f} s, ok={legs[name]['ok']}, "
-              f"mean iters {legs[name]['iters_mean']:.1f}", file=sys.stderr, flush=True)
+        ch = Chain(H, T, m, s0, t0, method=method, mode=mode)
+        if not args.no_tune:
+            tunings[name] = ch.autotune()
+        legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
+        if name == "plain":
+            launch_ms = target_call_ms(ch)
+            plain_chain = ch
+        print(f"# {name}: {legs[name]['per_chain_s'] * 1e3:.1f} ms/chain, ok={legs[name]['ok']}, "
+              f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
+              file=sys.stderr, flush=True)
 
     N = legs["project"]["N"]
-    per_step = {k: v["elapsed"] / args.steps for k, v in legs.items()}
+    per_step = {k: v["per_chain_s"] for k, v in legs.items()}
     value = N * T / per_step["project"]
-    # roofline of the dominant kernel: the batched GMRES kernel, timed alone in the plain leg
+    # roofline of the dominant kernel: the batched solve kernel in the plain leg (GMRES only),
+    # one launch per timestep, timed by HIP events on its stream
     pl = legs["plain"]
-    byts = gmres_bytes(n, m, pl["iters"], pl["restarts"]) / T          # per launch (timestep)
-    launch_s = pl["kernel_ms_last_chain"] / 1e3 / T
+    byts = gmres_bytes(n, pl["polish_m"], pl["iters"], pl["restarts"]) / T   # per launch
+    launch_s = sum(launch_ms) / 1e3 / T
     achieved = byts / launch_s / 1e9
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "target systems/s",
@@ -147,22 +193,47 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg.name, "grid": f"{H}x{H}", "n": n, "targets": N, "seeds": 1,
-                   "timesteps": T, "m": m, "tol": args.tol, "projection": "target_galerkin"},
+                   "timesteps": T, "m": m, "tol": args.tol, "projection": "target_galerkin",
+                   "polish_m": legs["project"]["polish_m"], "graph": graph},
         "verified": all(v["ok"] for v in legs.values()),
         "plain_gmres": {"value": round(N * T / per_step["plain"], 2),
                         "ms_per_step": round(per_step["plain"] * 1e3, 3),
-                        "mean_iters": round(pl["iters_mean"], 2)},
+                        "mean_iters": round(pl["iters_mean"], 2), "restart": pl["polish_m"]},
         "seed_galerkin": {"value": round(N * T / per_step["project_seed_galerkin"], 2),
                           "ms_per_step": round(per_step["project_seed_galerkin"] * 1e3, 3),
-                          "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2)},
+                          "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2),
+                          "polish_m": legs["project_seed_galerkin"]["polish_m"]},
         "projection": {"mean_polish_iters": round(legs["project"]["iters_mean"], 2),
                        "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
                        "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
-        "roofline": {"kernel": "gmres_kernel (batched restarted GMRES, 63 systems per launch)",
+        "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu,
+                         "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4)}
+                     for k, t in tunings.items()},
+        "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
+    del plain_chain
+    if not args.no_uneven:
+        cfg4, groups = build_c4()
+        un = {}
+        for name, method in (("project", "project"), ("plain", "plain")):
+            b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin")
+            tu = None if args.no_tune else b.autotune()
+            r = time_chain(b, args, args.uneven_steps, 1, graph)
+            un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
+                        "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                        "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
+                        "polish_m": r["polish_m"],
+                        "wg_per_cu": None if tu is None else tu.wg_per_cu}
+            print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
+                  file=sys.stderr, flush=True)
+            del b
+        out["uneven"] = {"workload": cfg4.name, "targets": sum(g.N * g.C for g in groups),
+                         "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": cfg4.m,
+                         "unit": "target systems/s", **un}
+        out["verified"] = out["verified"] and all(v["verified"] for v in un.values())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -176,12 +176,12 @@ __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &
         double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
         if (p < o.n) {
             const int i = p / H, j = p - (p / H) * H;
-            const double mE = (i + 1 < H) ? mt[p + H] : 0.0;
-            const double mW = (i > 0) ? mt[p - H] : 0.0;
-            const double mN = (j + 1 < H) ? mt[p + 1] : 0.0;
-            const double mS = (j > 0) ? mt[p - 1] : 0.0;
-            const double fxp = s.fx ? s.fx[p] : 0.0;
-            const double fyp = s.fy ? s.fy[p] : 0.0;
+            const double mE = (i + 1 < H) ? ld(mt, p + H) : 0.0;
+            const double mW = (i > 0) ? ld(mt, p - H) : 0.0;
+            const double mN = (j + 1 < H) ? ld(mt, p + 1) : 0.0;
+            const double mS = (j > 0) ? ld(mt, p - 1) : 0.0;
+            const double fxp = s.fx ? ld(s.fx, p) : 0.0;
+            const double fyp = s.fy ? ld(s.fy, p) : 0.0;
             const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
             const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
             cE = (i + 1 < H) ? -o.a + ex : 0.0;
@@ -255,10 +255,10 @@ __device__ __forceinline__ void stencil_direct(const double *u, const xkp_system
         if (p < o.n) {
             const int i = p / H, j = p - (p / H) * H;
             const bool e = i + 1 < H, wv = i > 0, nn = j + 1 < H, ss = j > 0;
-            const double ex = (s.fx ? s.fx[p] : 0.0) * o.inv2h
-                              - o.c8 * ((e ? mt[p + H] : 0.0) - (wv ? mt[p - H] : 0.0));
-            const double ey = (s.fy ? s.fy[p] : 0.0) * o.inv2h
-                              - o.c8 * ((nn ? mt[p + 1] : 0.0) - (ss ? mt[p - 1] : 0.0));
+            const double ex = (s.fx ? ld(s.fx, p) : 0.0) * o.inv2h
+                              - o.c8 * ((e ? ld(mt, p + H) : 0.0) - (wv ? ld(mt, p - H) : 0.0));
+            const double ey = (s.fy ? ld(s.fy, p) : 0.0) * o.inv2h
+                              - o.c8 * ((nn ? ld(mt, p + 1) : 0.0) - (ss ? ld(mt, p - 1) : 0.0));
             const double uE = e ? u[p + H] : 0.0;
             const double uW = wv ? u[p - H] : 0.0;
             const double uN = nn ? u[p + 1] : 0.0;
@@ -302,7 +302,7 @@ struct GmresLds {
 __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
 
 template <int RMAX>
-__device__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, int prestatus,
+__device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, int prestatus,
                           xkp_basis_header *hdr, double *Vfirst, double *Hb, double *Vws,
                           const Coef &C, xkp_info *info, GmresLds &L) {
     const OpConst o = op_const(s);
@@ -687,7 +687,7 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
 // zero-padded vector copies (each nlds long) during the operator applications, then the
 // projected matrix and the tile-reduction scratch: never live together.
 template <int RMAX>
-__device__ int project_one(const xkp_system &s, xkp_info *info, int n_bases,
+__device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, int n_bases,
                            const void *const *bases, const xkp_params &P, const Coef &C,
                            double *W, double *lds, int nlds, int nbuf, int nregion) {
     double *vbuf = lds + (nlds - kNT * RMAX) / 2;   // after the front pad
@@ -885,6 +885,67 @@ constexpr int kRClass0 = 2, kRClass1 = 8;
 constexpr int kRClass0 = 4, kRClass1 = 16;
 #endif
 
+// Each size class's projection and GMRES are compiled as functions of their own, so that the
+// register allocation of one (MFMA accumulators, prefetch rings of other row counts) cannot make
+// another spill inside its loops.  Their arguments arrive in vector registers; every one is
+// the same across the workgroup, and readfirstlane says so to the compiler (buffer descriptors
+// and loop bounds must be scalar).  The LDS is addressed through the dynamic-LDS symbol itself.
+extern __shared__ double xkp_dyn_lds[];
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+template <typename T>
+__device__ __forceinline__ T *uni(T *p) {
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ xkp_system uni(xkp_system s) {
+    s.H = uni(s.H);
+    s.basis_id = uni(s.basis_id);
+    s.dt = uni(s.dt);
+    s.g = uni(s.g);
+    s.mt = uni(s.mt);
+    s.fx = uni(s.fx);
+    s.fy = uni(s.fy);
+    s.b = uni(s.b);
+    s.x0 = uni(s.x0);
+    s.x = uni(s.x);
+    return s;
+}
+__device__ __forceinline__ xkp_params uni(xkp_params P) {
+    P.m = uni(P.m);
+    P.max_restarts = uni(P.max_restarts);
+    P.tol = uni(P.tol);
+    P.precision = uni(P.precision);
+    P.mode = uni(P.mode);
+    P.batch_max_n = uni(P.batch_max_n);
+    P.polish_m = uni(P.polish_m);
+    return P;
+}
+__device__ __forceinline__ Coef uni(Coef C) { return Coef{uni(C.E), uni(C.W), uni(C.N), uni(C.S)}; }
+
+template <int R>
+__device__ __noinline__ int project_call(xkp_system s, xkp_info *info, int n_bases,
+                                         const void *const *bases, xkp_params P, Coef C,
+                                         double *W, int nlds, int nbuf, int nregion) {
+    return project_one<R>(uni(s), uni(info), uni(n_bases), uni(bases), uni(P), uni(C), uni(W),
+                          xkp_dyn_lds, uni(nlds), uni(nbuf), uni(nregion));
+}
+
+template <int R>
+__device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, int pre,
+                                        xkp_basis_header *hdr, double *Vfirst, double *Hb,
+                                        double *Vws, Coef C, xkp_info *info, int nlds) {
+    GmresLds L(xkp_dyn_lds, uni(nlds), kNT * R);
+    gmres_one<R>(uni(s), uni(P), uni(flags), uni(pre), uni(hdr), uni(Vfirst), uni(Hb), uni(Vws),
+                 uni(C), uni(info), L);
+}
+
 template <int R, bool PROJ>
 __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           const xkp_params &P, int flags, int n_bases,
@@ -893,8 +954,7 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           double *lds, int nlds, int nbuf, int nregion) {
     int pre = XKP_OK;
     if constexpr (PROJ) {
-        pre = project_one<R>(s, info, n_bases, bases, P, C, slot + Lw.w, lds, nlds, nbuf,
-                             nregion);
+        pre = project_call<R>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds, nbuf, nregion);
         if (pre == XKP_EINVAL) return;
         flags |= kStartFromX;
     }
@@ -902,7 +962,6 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
     // left in the LDS
     for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;
     lds_barrier();
-    GmresLds L(lds, nlds, kNT * R);
     xkp_basis_header *hdr = nullptr;
     double *Vfirst = slot + Lw.v, *Hb = nullptr;
     if (keep_base) {
@@ -910,7 +969,7 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         Vfirst = (double *)((char *)keep_base + 256);
         Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
     }
-    gmres_one<R>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, L);
+    gmres_call<R>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
 }
 
 template <int RMAX, bool PROJ>
@@ -920,7 +979,7 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
                                                     void *const *keep_bases, xkp_info *infos,
                                                     double *ws, WsLayout Lw, int nmax, int nlds,
                                                     int nbuf, int nregion, unsigned *queue) {
-    extern __shared__ double lds[];
+    double *lds = xkp_dyn_lds;
     __shared__ int next[2];
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
     const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
@@ -1033,9 +1092,9 @@ __global__ __launch_bounds__(kNT) void rhs_kernel(const xkp_system *__restrict__
             const int p = (int)threadIdx.x + k * kNT;
             if (p < o.n) {
                 double div = 0.0;
-                if (s.fx) div += ((i + 1 < H) ? s.fx[p + H] : 0.0) - ((i > 0) ? s.fx[p - H] : 0.0);
-                if (s.fy) div += ((j + 1 < H) ? s.fy[p + 1] : 0.0) - ((j > 0) ? s.fy[p - 1] : 0.0);
-                b[p] = s.mt[p] / s.dt - div * o.inv2h;
+                if (s.fx) div += ((i + 1 < H) ? ld(s.fx, p + H) : 0.0) - ((i > 0) ? ld(s.fx, p - H) : 0.0);
+                if (s.fy) div += ((j + 1 < H) ? ld(s.fy, p + 1) : 0.0) - ((j > 0) ? ld(s.fy, p - 1) : 0.0);
+                b[p] = ld(s.mt, p) / s.dt - div * o.inv2h;
             }
             j += ri.dj;
             i += ri.di;
