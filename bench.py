@@ -32,6 +32,34 @@ sys.path.insert(0, ROOT)
 METRIC = "target systems solved/sec @ rel-residual 1e-8; projected vs plain GMRES"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the roofline kernel (solve_kernel, plain leg, polish restart 20, 63 systems per
+# launch), from two rocprofv3 --pmc runs of this file (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch averaged over the 200 target launches).  FETCH_SIZE read 131087 KiB for a 262144 KiB
+# device copy in the same runs (WRITE_SIZE read 262144 KiB): fetch figures are scaled by
+# 262144 / 131087.  Valid only for the kernel sources they were taken with (digest below).
+TRAFFIC = {"csrc_digest": "627ebc87b981748e", "fetch_kib": 326101.1, "write_kib": 84809.2,
+           "fetch_scale": 262144.0 / 131086.6, "write_scale": 1.0}
+
+
+def csrc_digest():
+    """Digest of the HIP sources, to tell whether stored counter figures still apply."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2511_17634_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes():
+    """HBM bytes per launch of the roofline kernel, or None if the sources have changed."""
+    if csrc_digest() != TRAFFIC["csrc_digest"]:
+        return None
+    return int(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
+                       + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
+
 
 def gmres_bytes(n, m, iters, restarts):
     """Algorithmic HBM bytes of restarted GMRES(m) with two Gram-Schmidt passes, FP64:
@@ -144,7 +172,13 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-size batch")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters")
     ap.add_argument("--eager", action="store_true", help="enqueue eagerly instead of a graph")
+    ap.add_argument("--polish-m", type=int, default=0,
+                    help="fixed polish restart length (implies --no-tune)")
     ap.add_argument("--uneven-steps", type=int, default=1)
+    ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
+                    help="comma list of the 64x64 legs to run (profiling runs take one)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--cpu-targets", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     args = ap.parse_args()
@@ -162,12 +196,24 @@ def main():
     n = H * H
     graph = not args.eager
 
+    if args.copy_probe:
+        import torch
+        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 copies of {args.copy_probe} MiB", file=sys.stderr, flush=True)
+        del src, dst
+    wanted = args.legs.split(",")
     legs, tunings = {}, {}
     for name, method, mode in (("project", "project", "target_galerkin"),
                                ("project_seed_galerkin", "project", "seed_galerkin"),
                                ("plain", "plain", "none")):
-        ch = Chain(H, T, m, s0, t0, method=method, mode=mode)
-        if not args.no_tune:
+        if name not in wanted:
+            continue
+        ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m)
+        if not args.no_tune and not args.polish_m:
             tunings[name] = ch.autotune()
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name == "plain":
@@ -177,6 +223,12 @@ def main():
               f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
               file=sys.stderr, flush=True)
 
+    if "project" not in legs or "plain" not in legs:
+        # a partial run (profiling): one line per leg, not the benchmark record
+        for k, v in legs.items():
+            print(json.dumps({"leg": k, "ms_per_chain": round(v["per_chain_s"] * 1e3, 3),
+                              "verified": v["ok"], "mean_iters": round(v["iters_mean"], 2)}))
+        return
     N = legs["project"]["N"]
     per_step = {k: v["per_chain_s"] for k, v in legs.items()}
     value = N * T / per_step["project"]
@@ -199,10 +251,11 @@ def main():
         "plain_gmres": {"value": round(N * T / per_step["plain"], 2),
                         "ms_per_step": round(per_step["plain"] * 1e3, 3),
                         "mean_iters": round(pl["iters_mean"], 2), "restart": pl["polish_m"]},
-        "seed_galerkin": {"value": round(N * T / per_step["project_seed_galerkin"], 2),
-                          "ms_per_step": round(per_step["project_seed_galerkin"] * 1e3, 3),
-                          "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2),
-                          "polish_m": legs["project_seed_galerkin"]["polish_m"]},
+        "seed_galerkin": None if "project_seed_galerkin" not in legs else {
+            "value": round(N * T / per_step["project_seed_galerkin"], 2),
+            "ms_per_step": round(per_step["project_seed_galerkin"] * 1e3, 3),
+            "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2),
+            "polish_m": legs["project_seed_galerkin"]["polish_m"]},
         "projection": {"mean_polish_iters": round(legs["project"]["iters_mean"], 2),
                        "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
                        "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
@@ -211,7 +264,8 @@ def main():
                      for k, t in tunings.items()},
         "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_bytes(),
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
     del plain_chain
