@@ -27,9 +27,16 @@
  *     written to the caller's device xkp_info array.
  *   - A context is used from one host thread at a time.  Calls on one context run in stream
  *     order; they share the context's workspace, so two contexts are needed for overlap.
- *   - All solver arithmetic is FP64 in XKP_FP64 mode.  In XKP_MIXED mode the Krylov vectors
- *     are still orthogonalised, rotated and checked in FP64; the projection contraction
- *     V^T (A' V) runs as BF16 matrix-core products with FP32 accumulation.
+ *   - All solver arithmetic is FP64 in XKP_FP64 mode.  In XKP_MIXED mode the operator inside
+ *     the GMRES cycles is applied in FP32 (FP32 coefficients, operands rounded to FP32, FP32
+ *     row sums); the Krylov vectors are still orthogonalised, rotated and updated in FP64, every
+ *     restart recomputes the true residual b - A x with the FP64 operator, and convergence is
+ *     judged on it, so results meet params->tol in FP64.  A cycle ends early once its residual
+ *     estimate has fallen by 1e-5 (the reduction the FP32 operator can deliver; a seed's kept
+ *     first cycle is exempt).  Seeds also write a BF16 copy of the kept basis, and the
+ *     target-Galerkin projection forms A'V_k with the FP32 operator, rounds it to BF16 and
+ *     contracts V_k^T (A'V_k) on BF16 matrix cores with FP32 accumulation; V_k^T r_base, the
+ *     k x k solve and x0 = x_base + V_k alpha stay FP64.
  */
 #ifndef XKP_H
 #define XKP_H
@@ -111,13 +118,16 @@ typedef struct {
  *                    zero after a breakdown)
  *   then             Hbar: m columns of (m+1) doubles (column-major, leading dimension m+1),
  *                    the unrotated Hessenberg matrix of that cycle
- *   then             Vb: (m+1) columns of ldv bf16 values (XKP_MIXED copies of V, 256-aligned)
+ *   then             Vb: (m+1) columns of ldv bf16 values (XKP_MIXED copies of V, 256-aligned;
+ *                    header field bf16 = 1 when written).  A mixed-precision target-Galerkin
+ *                    projection on a basis without it gives that target XKP_EINVAL.
  */
 typedef struct {
     int32_t n, m, k, status;
     double beta;          /* ||r0|| of the seed's first cycle                               */
     int32_t ldv;          /* leading dimension of V in doubles                              */
-    int32_t pad[57];
+    int32_t bf16;         /* 1 if the BF16 copy Vb was written (seed built with XKP_MIXED)  */
+    int32_t pad[56];
 } xkp_basis_header;
 
 typedef struct xkp_ctx xkp_ctx;

@@ -12,7 +12,8 @@ WsLayout ws_layout(int nmax, int mmax, int npad) {
     L.cW = L.cE + up(L.npad);
     L.cN = L.cW + up(L.npad);
     L.cS = L.cN + up(L.npad);
-    L.w = L.cS + up(L.npad);
+    L.c32 = L.cS + up(L.npad);
+    L.w = L.c32 + up(2 * (size_t)L.npad);
     L.stride = L.w + up((size_t)basis_ldv(nmax) * (mmax + 1));
     return L;
 }

@@ -10,7 +10,7 @@ namespace xkp {
 // Per-workgroup workspace, in doubles, for systems of at most nmax unknowns and restart m;
 // npad is the padded row count (threads x rows per thread) of the kernel variant used.
 struct WsLayout {
-    size_t v, cE, cW, cN, cS, w, stride;
+    size_t v, cE, cW, cN, cS, c32, w, stride;   // c32: four FP32 coefficient arrays of npad
     int npad;   // rows covered by the kernel variant, coefficient array length
 };
 WsLayout ws_layout(int nmax, int mmax, int npad);

@@ -34,6 +34,10 @@ namespace xkp {
 namespace XKP_VARIANT {
 
 constexpr int kLdA = 81;   // leading dimension of the projected matrix in LDS (<= 80 columns)
+// Mixed precision: a GMRES cycle with the FP32 operator stops once its residual estimate has
+// dropped by this factor (about 170 FP32 unit roundoffs, the attainable reduction for operators
+// of condition number up to a few hundred); the FP64 true residual then restarts it.
+constexpr double kMixedCycleDrop = 1e-5;
 
 // ----------------------------------------------------------------------------------------
 // Vector helpers over the rows a thread owns.
@@ -57,6 +61,33 @@ __device__ __forceinline__ void bst(rsrc_t r, unsigned byte_off, double v, unsig
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, soff, 0);
 }
 __device__ __forceinline__ unsigned row_off(int k) { return (threadIdx.x + k * kNT) * 8u; }
+
+// FP32 / BF16 views: the same resources with 4- and 2-byte elements.
+__device__ __forceinline__ rsrc_t mkbuf32(const float *base, int count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), (short)0, count * 4,
+                                             kRsrcWord3);
+}
+__device__ __forceinline__ rsrc_t mkbuf16(const unsigned short *base, int count) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned short *>(base), (short)0,
+                                             count * 2, kRsrcWord3);
+}
+__device__ __forceinline__ float bldf(rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, soff, 0));
+}
+__device__ __forceinline__ void bstf(rsrc_t r, unsigned byte_off, float v, unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, soff, 0);
+}
+__device__ __forceinline__ void bst16(rsrc_t r, unsigned byte_off, unsigned short v,
+                                      unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, byte_off, soff, 0);
+}
+
+// BF16 bits of a double: rounded to FP32, then to the nearest BF16 (ties to even); finite
+// values only.
+__device__ __forceinline__ unsigned short to_bf16(double d) {
+    const unsigned u = __builtin_bit_cast(unsigned, (float)d);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
 // Row k of this thread = lane offset (one register) + scalar offset k * kNT * 8.
 __device__ __forceinline__ unsigned lane_off() { return threadIdx.x * 8u; }
 __device__ __forceinline__ unsigned row_soff(int k) { return (unsigned)(k * kNT * 8); }
@@ -164,10 +195,11 @@ template <> struct Depth<32> { static constexpr int value = XKP_DEPTH32; };
 // the same for every row and stays a scalar.
 struct Coef {
     double *E, *W, *N, *S;
+    float *E32, *W32, *N32, *S32;   // FP32 copies (mixed precision)
 };
 
 template <int RMAX>
-__device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &C) {
+__device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &C, bool mixed) {
     const int H = o.H;
     const double *__restrict__ mt = s.mt;
 #pragma unroll
@@ -194,6 +226,13 @@ __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &
         bst(mkbuf(C.W, kNT * RMAX), off, cW);
         bst(mkbuf(C.N, kNT * RMAX), off, cN);
         bst(mkbuf(C.S, kNT * RMAX), off, cS);
+        if (mixed) {
+            const unsigned o4 = (unsigned)p * 4u;
+            bstf(mkbuf32(C.E32, kNT * RMAX), o4, (float)cE);
+            bstf(mkbuf32(C.W32, kNT * RMAX), o4, (float)cW);
+            bstf(mkbuf32(C.N32, kNT * RMAX), o4, (float)cN);
+            bstf(mkbuf32(C.S32, kNT * RMAX), o4, (float)cS);
+        }
     }
 }
 
@@ -219,6 +258,38 @@ __device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, cons
         // than the kernel has while the basis prefetch is in flight
         if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+// The same operator in FP32 (mixed precision): coefficients and the five values of u rounded to
+// FP32, the row's sum formed in FP32, the result widened to FP64.
+template <int RMAX>
+__device__ __forceinline__ void stencil_lds_f32(const double *u, const Coef &C, const OpConst &o,
+                                                double (&w)[RMAX]) {
+    const int H = o.H;
+    const float cd = (float)o.cd;
+    const double *uc = u + threadIdx.x;
+    const rsrc_t bE = mkbuf32(C.E32, kNT * RMAX), bW = mkbuf32(C.W32, kNT * RMAX);
+    const rsrc_t bN = mkbuf32(C.N32, kNT * RMAX), bS = mkbuf32(C.S32, kNT * RMAX);
+    const unsigned lo = threadIdx.x * 4u;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) {
+        const unsigned so = (unsigned)(k * kNT * 4);
+        const double *q = uc + k * kNT;
+        const float y = cd * (float)q[0] + bldf(bE, lo, so) * (float)q[H]
+                        + bldf(bW, lo, so) * (float)q[-H] + bldf(bN, lo, so) * (float)q[1]
+                        + bldf(bS, lo, so) * (float)q[-1];
+        w[k] = (double)y;
+        if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// BF16 copy of a column (rows p < ldv), 2-byte elements.
+template <int RMAX>
+__device__ __forceinline__ void store_col_bf16(unsigned short *v, int ldv, const double (&r)[RMAX]) {
+    const rsrc_t b = mkbuf16(v, ldv);
+    const unsigned lo = threadIdx.x * 2u;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) bst16(b, lo, to_bf16(r[k]), (unsigned)(k * kNT * 2));
 }
 
 // w = A u with u a length-n global vector: every neighbour index clamped into [0, n), rows past
@@ -301,7 +372,7 @@ struct GmresLds {
 
 __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
 
-template <int RMAX>
+template <int RMAX, bool MIXED>
 __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, int prestatus,
                           xkp_basis_header *hdr, double *Vfirst, double *Hb, double *Vws,
                           const Coef &C, xkp_info *info, GmresLds &L) {
@@ -311,8 +382,12 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
     const int n = o.n, m = (keep || P.polish_m <= 0) ? P.m : P.polish_m;
     const int tid = threadIdx.x, ldv = ldv_for(o.n);
     BlockRed br{L.red, 0};
+    // mixed precision: FP32 operator inside the Krylov cycles, FP64 everywhere else
+    constexpr bool mixed = MIXED;
+    unsigned short *Vb = (keep && mixed) ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
+                                         : nullptr;
 
-    build_coeffs<RMAX>(s, o, C);
+    build_coeffs<RMAX>(s, o, C, mixed);
     if (keep) {
         for (int t = tid; t < (m + 1) * m; t += kNT) Hb[t] = 0.0;
         __syncthreads();   // thread 0 overwrites some of these entries later
@@ -355,17 +430,26 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) cur[k] = cur[k] / beta;
                 store_col<RMAX>(V, ldv, cur);
+                if (Vb && first) store_col_bf16<RMAX>(Vb, ldv, cur);
                 store_rows_lds<RMAX>(L.vbuf, cur);
                 if (first) beta_first = beta;
                 lds_barrier();
                 double gcur = beta;
+                // With the FP32 operator a cycle cannot lower the true residual much below
+                // kMixedCycleDrop times its start; the cycle ends there and the FP64 restart
+                // takes over (the kept first cycle of a seed runs to m or the tolerance).
+                const double gfloor =
+                    (mixed && !(keep && first)) ? kMixedCycleDrop * beta : 0.0;
                 int kk = 0;
                 for (int j = 0; j < m; ++j) {
                     // With many rows per thread the Krylov vector w lives in the LDS copy of
                     // v_j (free once the operator has read it) instead of registers.
                     constexpr bool kWL = RMAX >= 32;
                     double *wl = L.vbuf + tid;
-                    stencil_lds<RMAX>(L.vbuf, C, o, w);
+                    if constexpr (mixed)
+                        stencil_lds_f32<RMAX>(L.vbuf, C, o, w);
+                    else
+                        stencil_lds<RMAX>(L.vbuf, C, o, w);
                     ++iters;
                     const double wsq = dot_rows<RMAX>(w, w);
                     if constexpr (kWL) {
@@ -428,6 +512,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
 #pragma unroll
                     for (int k = 0; k < RMAX; ++k) w[k] = brk ? 0.0 : w[k] / hn;
                     store_col<RMAX>(V + (size_t)(j + 1) * ldv, ldv, w);
+                    if (Vb && first) store_col_bf16<RMAX>(Vb + (size_t)(j + 1) * ldv, ldv, w);
                     store_rows_lds<RMAX>(L.vbuf, w);
                     if (keep && first) {
                         // unrotated Hessenberg column j of the kept basis
@@ -446,7 +531,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     kk = j + 1;
                     res_est = fabs(gcur) / bnorm;
                     lds_barrier();
-                    if (fabs(gcur) <= P.tol * bnorm || brk) break;
+                    if (fabs(gcur) <= fmax(P.tol * bnorm, gfloor) || brk) break;
                 }
                 // y = R^{-1} g by one wavefront (lane c holds g_c), column-oriented
                 if (tid < 64) {
@@ -497,6 +582,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
             hdr->status = status;
             hdr->beta = beta_first;
             hdr->ldv = ldv;
+            hdr->bf16 = mixed ? 1 : 0;
         }
         int st = status;
         if (st == XKP_OK && (flags & kTarget) && prestatus == XKP_ESINGULAR) st = XKP_ESINGULAR;
@@ -681,12 +767,102 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
     }
 }
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+
+// Mixed-precision counterpart of vtw_chunk: partial Vb^T Wb of the BF16 copies of V_k and
+// A'V_k (k columns each, leading dimension ldv elements), over 32-row chunks
+// g = wave, wave + kNW, ..., on BF16 matrix cores with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] as eight
+// consecutive rows of one column, one 16-byte load; output register r of lane l is
+// D[4(l/16) + r][l%16]).  Chunks are zero past row n; the tiles are summed over the waves in a
+// fixed order in FP64.
+template <int KTR, int NTC>
+__device__ __forceinline__ void vtw_bf16(rsrc_t rV, rsrc_t rW, int n, int ldv, int k, int tc0,
+                                         double *Ap, double *tred) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    f32x4_t acc[KTR][NTC];
+    unsigned offA[KTR], offB[NTC];
+    bool okA[KTR], okB[NTC];
+#pragma unroll
+    for (int t = 0; t < KTR; ++t) {
+        const int a = t * 16 + (lane & 15);
+        okA[t] = a < k;
+        offA[t] = (unsigned)(okA[t] ? a : 0) * (unsigned)ldv * 2u;
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+        const int c = (tc0 + t) * 16 + (lane & 15);
+        okB[t] = c < k;
+        offB[t] = (unsigned)(okB[t] ? c : 0) * (unsigned)ldv * 2u;
+    }
+#pragma unroll
+    for (int a = 0; a < KTR; ++a)
+#pragma unroll
+        for (int b = 0; b < NTC; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int nchunks = (n + 31) / 32;
+    u32x4_t an[KTR], bn[NTC];
+    int g = wave;
+    {
+        const unsigned po = (32u * g + 8u * (lane >> 4)) * 2u;
+#pragma unroll
+        for (int t = 0; t < KTR; ++t) an[t] = __builtin_amdgcn_raw_buffer_load_b128(rV, offA[t] + po, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) bn[t] = __builtin_amdgcn_raw_buffer_load_b128(rW, offB[t] + po, 0, 0);
+    }
+    const u32x4_t zero4 = {0u, 0u, 0u, 0u};
+    for (; g < nchunks; g += kNW) {
+        // rows p..p+7 of a column lie inside it (ldv is a multiple of 8 above n); groups at or
+        // past n are zeroed
+        const unsigned p = 32u * g + 8u * (lane >> 4);
+        const bool pin = p < (unsigned)n;
+        bf16x8_t av[KTR], bv[NTC];
+#pragma unroll
+        for (int t = 0; t < KTR; ++t)
+            av[t] = __builtin_bit_cast(bf16x8_t, (okA[t] && pin) ? an[t] : zero4);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+            bv[t] = __builtin_bit_cast(bf16x8_t, (okB[t] && pin) ? bn[t] : zero4);
+        const int gn = g + kNW < nchunks ? g + kNW : g;
+        const unsigned pon = (32u * gn + 8u * (lane >> 4)) * 2u;
+#pragma unroll
+        for (int t = 0; t < KTR; ++t) an[t] = __builtin_amdgcn_raw_buffer_load_b128(rV, offA[t] + pon, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) bn[t] = __builtin_amdgcn_raw_buffer_load_b128(rW, offB[t] + pon, 0, 0);
+#pragma unroll
+        for (int a = 0; a < KTR; ++a)
+#pragma unroll
+            for (int b = 0; b < NTC; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int ta = 0; ta < KTR; ++ta) {
+#pragma unroll
+        for (int tb = 0; tb < NTC; ++tb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tred[wave * 256 + lane * 4 + r] = (double)acc[ta][tb][r];
+            lds_barrier();
+            if (threadIdx.x < 256) {
+                double sum = 0.0;
+#pragma unroll
+                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + threadIdx.x];
+                const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+                const int a = ta * 16 + 4 * (l >> 4) + r;
+                const int c = (tc0 + tb) * 16 + (l & 15);
+                if (a < k && c < k) Ap[a * kLdA + c] = sum;
+            }
+            lds_barrier();
+        }
+    }
+}
+
 // Projection of one target onto its seed basis (Section 3, Phase 2): writes x0 = x_base + V alpha
 // into s.x and returns XKP_OK, XKP_ESINGULAR (the projected system was singular: x0 = x_base)
 // or XKP_EINVAL (no usable basis: s.x untouched, info->status set).  The LDS holds nbuf
 // zero-padded vector copies (each nlds long) during the operator applications, then the
 // projected matrix and the tile-reduction scratch: never live together.
-template <int RMAX>
+template <int RMAX, bool MIXED>
 __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, int n_bases,
                            const void *const *bases, const xkp_params &P, const Coef &C,
                            double *W, double *lds, int nlds, int nbuf, int nregion) {
@@ -706,6 +882,9 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
         if (ok) {
             hdr = (const xkp_basis_header *)bases[s.basis_id];
             ok = hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m;
+            // the mixed target-Galerkin contraction needs the seed's BF16 basis copy
+            if (ok && P.precision == XKP_MIXED && P.mode == XKP_PROJ_TARGET_GALERKIN)
+                ok = hdr->bf16 == 1;
             if (ok) k = hdr->k;
         }
         if (!ok) {
@@ -721,7 +900,8 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
         const double *Hb = (const double *)((const char *)hdr + basis_off_h(n, m));
         const OpConst o = op_const(s);
         BlockRed br{red, 0};
-        build_coeffs<RMAX>(s, o, C);
+        constexpr bool mixed = MIXED;
+        build_coeffs<RMAX>(s, o, C, mixed);
         // the LDS vector shares space with the projected matrix of the previous system: clear it
         for (int t = tid; t < nregion; t += kNT) lds[t] = 0.0;
         lds_barrier();   // the cleared words belong to other threads' rows
@@ -738,8 +918,66 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
             for (int q = 0; q < RMAX; ++q) rb[q] -= cur[q];
         }
         bool singular = false;
+        // zv = V_{nz}^T r_base in FP64, eight columns per reduction
+        auto vt_rbase = [&](int nz) {
+            for (int c0 = 0; c0 < nz; c0 += kRedSlots) {
+                double part[kRedSlots];
+#pragma unroll
+                for (int q = 0; q < kRedSlots; ++q) {
+                    part[q] = 0.0;
+                    if (c0 + q < nz) {
+                        load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, cur);
+                        part[q] = dot_rows<RMAX>(cur, rb);
+                    }
+                }
+                br.sum_multi<kRedSlots>(part);
+                if (tid == 0)
+                    for (int q = 0; q < kRedSlots && c0 + q < nz; ++q) zv[c0 + q] = part[q];
+            }
+        };
         if (k > 0) {
-            if (P.mode == XKP_PROJ_TARGET_GALERKIN) {
+            if (mixed && P.mode == XKP_PROJ_TARGET_GALERKIN) {
+                // A' V_k with the FP32 operator, rounded to BF16 into the workspace;
+                // V_k^T (A' V_k) on BF16 matrix cores with FP32 accumulation; V_k^T r_base and
+                // the k x k solve in FP64
+                unsigned short *Wb = (unsigned short *)W;
+                const unsigned short *Vb =
+                    (const unsigned short *)((const char *)hdr + basis_off_vb(n, m));
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                    [&](int c, const double(&col)[RMAX]) {
+                    double *vb = (nbuf == 2 && (c & 1)) ? vbuf1 : vbuf;
+                    if (nbuf == 1 && c > 0) lds_barrier();   // readers of the previous column
+                    store_rows_lds<RMAX>(vb, col);
+                    lds_barrier();
+                    double y[RMAX];
+                    stencil_lds_f32<RMAX>(vb, C, o, y);
+                    store_col_bf16<RMAX>(Wb + (size_t)c * ldv, ldv, y);
+                });
+                vt_rbase(k);
+                __syncthreads();   // Wb rows written by other threads are read below
+                const int ktr = (k + 15) / 16;
+                const rsrc_t rV = mkbuf16(Vb, ldv * k), rW = mkbuf16(Wb, ldv * k);
+                double *tred = Ap + (kMMax + 1) * kLdA;
+                for (int tc0 = 0; tc0 < ktr; tc0 += 2) {
+                    const int ntc = ktr - tc0 < 2 ? ktr - tc0 : 2;
+#define XKP_VTWB(R_, C_) vtw_bf16<R_, C_>(rV, rW, n, ldv, k, tc0, Ap, tred)
+                    switch (ktr * 2 + ntc - 1) {
+                    case 2: XKP_VTWB(1, 1); break;
+                    case 4: XKP_VTWB(2, 1); break;
+                    case 5: XKP_VTWB(2, 2); break;
+                    case 6: XKP_VTWB(3, 1); break;
+                    case 7: XKP_VTWB(3, 2); break;
+                    case 8: XKP_VTWB(4, 1); break;
+                    default: XKP_VTWB(4, 2); break;
+                    }
+#undef XKP_VTWB
+                }
+                lds_barrier();
+                if (wave == 0) {
+                    const double zr = (lane < k) ? zv[lane] : 0.0;
+                    singular = lu_solve_wave(Ap, kLdA, k, zr, alpha, pivl);
+                }
+            } else if (P.mode == XKP_PROJ_TARGET_GALERKIN) {
                 // W = [A' V_k | r_base] in the workspace.  Each thread keeps its rows'
                 // coefficients in registers; the basis columns stream through the prefetch ring
                 // and, for the neighbours, through one of two zero-padded LDS copies.
@@ -806,22 +1044,8 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                     singular = lu_solve_wave(Ap, kLdA, k, zr, alpha, pivl);
                 }
             } else {
-                // z = V_{k(+1)}^T r_base, eight columns per reduction
-                const int nz = (P.mode == XKP_PROJ_SEED_LSQ) ? k + 1 : k;
-                for (int c0 = 0; c0 < nz; c0 += kRedSlots) {
-                    double part[kRedSlots];
-#pragma unroll
-                    for (int q = 0; q < kRedSlots; ++q) {
-                        part[q] = 0.0;
-                        if (c0 + q < nz) {
-                            load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, cur);
-                            part[q] = dot_rows<RMAX>(cur, rb);
-                        }
-                    }
-                    br.sum_multi<kRedSlots>(part);
-                    if (tid == 0)
-                        for (int q = 0; q < kRedSlots && c0 + q < nz; ++q) zv[c0 + q] = part[q];
-                }
+                // z = V_{k(+1)}^T r_base
+                vt_rbase((P.mode == XKP_PROJ_SEED_LSQ) ? k + 1 : k);
                 // Hbar (k+1 rows) or H_k into LDS, row-major
                 for (int t = tid; t < (k + 1) * k; t += kNT) {
                     const int a = t / k, c = t % k;
@@ -927,22 +1151,25 @@ __device__ __forceinline__ xkp_params uni(xkp_params P) {
     P.polish_m = uni(P.polish_m);
     return P;
 }
-__device__ __forceinline__ Coef uni(Coef C) { return Coef{uni(C.E), uni(C.W), uni(C.N), uni(C.S)}; }
+__device__ __forceinline__ Coef uni(Coef C) {
+    return Coef{uni(C.E),   uni(C.W),   uni(C.N),   uni(C.S),
+                uni(C.E32), uni(C.W32), uni(C.N32), uni(C.S32)};
+}
 
-template <int R>
+template <int R, bool MIXED>
 __device__ __noinline__ int project_call(xkp_system s, xkp_info *info, int n_bases,
                                          const void *const *bases, xkp_params P, Coef C,
                                          double *W, int nlds, int nbuf, int nregion) {
-    return project_one<R>(uni(s), uni(info), uni(n_bases), uni(bases), uni(P), uni(C), uni(W),
+    return project_one<R, MIXED>(uni(s), uni(info), uni(n_bases), uni(bases), uni(P), uni(C), uni(W),
                           xkp_dyn_lds, uni(nlds), uni(nbuf), uni(nregion));
 }
 
-template <int R>
+template <int R, bool MIXED>
 __device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, int pre,
                                         xkp_basis_header *hdr, double *Vfirst, double *Hb,
                                         double *Vws, Coef C, xkp_info *info, int nlds) {
     GmresLds L(xkp_dyn_lds, uni(nlds), kNT * R);
-    gmres_one<R>(uni(s), uni(P), uni(flags), uni(pre), uni(hdr), uni(Vfirst), uni(Hb), uni(Vws),
+    gmres_one<R, MIXED>(uni(s), uni(P), uni(flags), uni(pre), uni(hdr), uni(Vfirst), uni(Hb), uni(Vws),
                  uni(C), uni(info), L);
 }
 
@@ -954,7 +1181,11 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           double *lds, int nlds, int nbuf, int nregion) {
     int pre = XKP_OK;
     if constexpr (PROJ) {
-        pre = project_call<R>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds, nbuf, nregion);
+        pre = P.precision == XKP_MIXED
+                  ? project_call<R, true>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds, nbuf,
+                                          nregion)
+                  : project_call<R, false>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds, nbuf,
+                                           nregion);
         if (pre == XKP_EINVAL) return;
         flags |= kStartFromX;
     }
@@ -969,7 +1200,10 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         Vfirst = (double *)((char *)keep_base + 256);
         Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
     }
-    gmres_call<R>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
+    if (P.precision == XKP_MIXED)
+        gmres_call<R, true>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
+    else
+        gmres_call<R, false>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
 }
 
 template <int RMAX, bool PROJ>
@@ -982,7 +1216,9 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
     double *lds = xkp_dyn_lds;
     __shared__ int next[2];
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
-    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS};
+    float *c32 = (float *)(slot + Lw.c32);
+    const Coef C{slot + Lw.cE, slot + Lw.cW, slot + Lw.cN, slot + Lw.cS,
+                 c32, c32 + Lw.npad, c32 + 2 * Lw.npad, c32 + 3 * Lw.npad};
     for (int it = 0;; ++it) {
         // alternating broadcast slots: a fast thread 0 can fetch the next index before slow
         // waves have read this one without overwriting it

@@ -251,7 +251,7 @@ class Bases:
         o = self.offsets[i]
         h = self.buf[o:o + 32].cpu().numpy().view(np.int32)
         return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3]),
-                "ldv": int(h[6])}
+                "ldv": int(h[6]), "bf16": int(h[7])}
 
     def V_padded(self, i):
         """(ldv, m+1) view of basis i's FP64 columns including the zero rows."""
@@ -264,6 +264,15 @@ class Bases:
     def V(self, i):
         """(n, m+1) view of basis i's FP64 columns."""
         return self.V_padded(i)[:self.ns[i]]
+
+    def Vb_bits(self, i):
+        """(ldv, m+1) view of basis i's BF16 copy as raw 16-bit patterns (int16)."""
+        import torch
+        ldv, m = self.ldv(i), self.m
+        o = 256 + 8 * ldv * (m + 1) + 8 * (m + 1) * m
+        off = self.offsets[i] + ((o + 255) & ~255)
+        raw = self.buf[off:off + 2 * ldv * (m + 1)]
+        return raw.view(torch.int16).view(m + 1, ldv).T
 
     def Hbar(self, i):
         import torch
