@@ -12,7 +12,9 @@ unit come from the library's autotuner, run on the chain's own inputs before the
 (--no-tune: restart length m).  Inputs are resident in device memory before the timed region.
 
 Also timed (--no-uneven skips it): the uneven batch, 32x32 / 64x64 / 128x128 grids with 3
-channels each (3072 target systems, 9 seeds) in one launch per timestep.
+channels each (3072 target systems, 9 seeds) in one launch per timestep; and (--no-mixed skips
+it) the 128x128 workload (1 seed + 255 targets, m = 60) in mixed and FP64 precision, with each
+target's error against the FP64 path.
 
 Prints one JSON line.
 """
@@ -101,6 +103,40 @@ def build_c4():
     return cfg, groups
 
 
+def build_c3():
+    from synth import CONFIGS, config_images, initial_state
+    cfg = CONFIGS["c3"]
+    seed, tg = config_images(cfg, 0)
+    return cfg, initial_state(seed[0]), np.stack([initial_state(t[0]) for t in tg])
+
+
+def err_vs_fp64(b, tol=1e-12):
+    """Per-target max |x - x64| / max |x64| of the chain's last solutions against the same
+    systems solved again by the FP64 path (plain GMRES to `tol`)."""
+    import torch
+    from paper_2511_17634_amd import xkp
+    par = b.step_no & 1
+    prev = 1 - par
+    bt = torch.empty_like(b.bt)
+    x64 = torch.empty_like(b.bt)
+    d = b._desc(b.tgt_sys, b.mt, bt, prev, x_from=x64)
+    ctx = xkp.Context(b.nmax, b.m, b.N, stream=b.s_main)
+    info = ctx.new_infos(b.N)
+    b.s_main.wait_stream(torch.cuda.current_stream())
+    P = xkp.Context.params(b.m, tol=tol, mode="none", batch_max_n=b.nmax)
+    ctx.build_rhs(d, b.N)
+    ctx.target_project_solve(d, b.N, 0, None, P, info)
+    b.s_main.synchronize()
+    x = b.state()[1]
+    errs = []
+    for H, off, _ in b.tgt_sys:
+        n = H * H
+        ref = x64[off:off + n]
+        errs.append(float((x[off:off + n] - ref).abs().max() / ref.abs().max()))
+    ok = bool((xkp.infos_to_numpy(info)["status"] == 0).all())
+    return np.array(errs), ok
+
+
 def time_chain(b, args, steps, warmup, graph=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
     captured graph (or enqueued eagerly), then verify every solve of the last chain."""
@@ -175,6 +211,8 @@ def main():
     ap.add_argument("--polish-m", type=int, default=0,
                     help="fixed polish restart length (implies --no-tune)")
     ap.add_argument("--uneven-steps", type=int, default=1)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 128x128 mixed workload")
+    ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
                     help="comma list of the 64x64 legs to run (profiling runs take one)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -288,6 +326,35 @@ def main():
                          "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": cfg4.m,
                          "unit": "target systems/s", **un}
         out["verified"] = out["verified"] and all(v["verified"] for v in un.values())
+    if not args.no_mixed:
+        cfg3, s3, t3 = build_c3()
+        H3 = cfg3.groups[0].H
+        mx = {}
+        for name, method, prec in (("project_mixed", "project", xkp.MIXED),
+                                   ("project_fp64", "project", xkp.FP64),
+                                   ("plain_mixed", "plain", xkp.MIXED),
+                                   ("plain_fp64", "plain", xkp.FP64)):
+            b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec)
+            tu = None if args.no_tune else b.autotune()
+            r = time_chain(b, args, args.mixed_steps, 1, graph)
+            e, eok = err_vs_fp64(b)
+            mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
+                        "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                        "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"] and eok,
+                        "polish_m": r["polish_m"],
+                        "mean_guess_residual": round(r["guess_res_mean"], 4),
+                        "err_vs_fp64_max": float(f"{e.max():.3e}"),
+                        "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
+            print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
+                  f"mean iters {r['iters_mean']:.1f}, max err vs fp64 {e.max():.2e}",
+                  file=sys.stderr, flush=True)
+            del b
+        out["mixed"] = {"workload": cfg3.name, "targets": len(t3), "seeds": 1,
+                        "timesteps": cfg3.T, "m": cfg3.m, "unit": "target systems/s",
+                        "err_note": "per-target max |x - x_fp64| / max |x_fp64| at the last "
+                                    "timestep, x_fp64 = the same systems re-solved by the FP64 "
+                                    "path to 1e-12", **mx}
+        out["verified"] = out["verified"] and all(v["verified"] for v in mx.values())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     print(json.dumps(out), flush=True)
