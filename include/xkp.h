@@ -190,6 +190,38 @@ xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems)
 /* y_i = A_i u_i for a batch (the stencil operator alone): u = systems[i].x0, y = systems[i].x. */
 xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems);
 
+/*
+ * Learned starting guess: a small network maps a target's initial image (64 x 64, FP64, index
+ * [i][j] = unknown p = 64 i + j) and the timestep index n to k coefficients alpha_L in the seed
+ * subspace (x0_L = x_base + V_k alpha_L, see xkp_learned_solve).  Layers: 2x2 average pool to
+ * 32 x 32; three 3x3 stride-2 padding-1 convolutions (1 -> 16 -> 32 -> 64 channels), each with
+ * bias and GELU; mean over the 4 x 4 positions concatenated with a 32-wide sinusoidal embedding
+ * of n (sin / cos of n * 10000^(-i/16), i < 16); linear 96 -> k.  Parameters are one FP32
+ * device array of xkp_cnn_param_count(k) values: conv1.W[16][9], conv1.b[16], conv2.W[32][144],
+ * conv2.b[32], conv3.W[64][288], conv3.b[64], lin.W[k][96], lin.b[k] (weight column
+ * ci*9 + ky*3 + kx).  The convolutions run on BF16 matrix cores with FP32 accumulation; the rest
+ * is FP32.  `work` is a caller-allocated device buffer of xkp_cnn_workspace_bytes(batch, k).
+ * All arrays are device arrays; 1 <= k <= 64, batch >= 1.
+ */
+size_t xkp_cnn_param_count(int32_t k);
+size_t xkp_cnn_workspace_bytes(int32_t batch, int32_t k);
+
+/* alpha[b][0..k) for images[b] (batch x 4096 doubles) at timestep steps[b]. */
+xkp_status xkp_cnn_forward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
+                           const double *images, const int32_t *steps, float *alpha, void *work);
+
+/* Forward pass, then the mean squared error against target[b][0..k) into *loss (one device
+ * float) and its gradient with respect to every parameter into grad (param_count floats,
+ * overwritten).  alpha receives the forward outputs. */
+xkp_status xkp_cnn_backward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
+                            const double *images, const int32_t *steps, const float *target,
+                            float *alpha, float *grad, float *loss, void *work);
+
+/* One Adam step on `count` FP32 parameters: m, v are the moment buffers (zero before step 1),
+ * t >= 1 the step number (bias correction). */
+xkp_status xkp_cnn_adam(xkp_ctx *ctx, int32_t count, float *params, const float *grad, float *m,
+                        float *v, int32_t t, float lr, float beta1, float beta2, float eps);
+
 /* Outcome of xkp_autotune. */
 typedef struct {
     int32_t polish_m;     /* fastest restart length of the polish (for params->polish_m)    */

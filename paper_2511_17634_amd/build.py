@@ -22,6 +22,7 @@ LIB = os.path.join(HERE, "libxkp.so")
 # (source, object, extra flags): the kernel file is compiled once per workgroup size
 UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIANT=v512"]),
          ("xkp_common.hip", "xkp_common.o", []),
+         ("xkp_cnn.hip", "xkp_cnn.o", []),
          ("xkp_api.hip", "xkp_api.o", [])]
 ARCH = os.environ.get("XKP_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

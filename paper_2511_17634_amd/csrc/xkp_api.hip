@@ -282,6 +282,46 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     return best < 0.f ? XKP_ENOCONV : XKP_OK;
 }
 
+size_t xkp_cnn_param_count(int32_t k) {
+    if (k < 1 || k > 64) return 0;
+    return xkp::cnn::param_count(k);
+}
+
+size_t xkp_cnn_workspace_bytes(int32_t batch, int32_t k) {
+    if (batch < 1 || k < 1 || k > 64) return 0;
+    return xkp::cnn::workspace_bytes(batch, k);
+}
+
+xkp_status xkp_cnn_forward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
+                           const double *images, const int32_t *steps, float *alpha, void *work) {
+    if (!ctx || batch < 1 || k < 1 || k > 64 || !params || !images || !steps || !alpha || !work)
+        return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    return from_hip(xkp::cnn::forward(ctx->stream, batch, k, params, images, steps, alpha,
+                                      (float *)work));
+}
+
+xkp_status xkp_cnn_backward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
+                            const double *images, const int32_t *steps, const float *target,
+                            float *alpha, float *grad, float *loss, void *work) {
+    if (!ctx || batch < 1 || k < 1 || k > 64 || !params || !images || !steps || !target ||
+        !alpha || !grad || !loss || !work)
+        return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    return from_hip(xkp::cnn::backward(ctx->stream, batch, k, params, images, steps, target,
+                                       alpha, grad, loss, (float *)work));
+}
+
+xkp_status xkp_cnn_adam(xkp_ctx *ctx, int32_t count, float *params, const float *grad, float *m,
+                        float *v, int32_t t, float lr, float beta1, float beta2, float eps) {
+    if (!ctx || count < 1 || !params || !grad || !m || !v || t < 1 || !(lr > 0.f) ||
+        !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    return from_hip(xkp::cnn::adam(ctx->stream, count, params, grad, m, v, t, lr, beta1, beta2,
+                                   eps));
+}
+
 const char *xkp_status_string(xkp_status s) {
     switch (s) {
     case XKP_OK: return "ok";

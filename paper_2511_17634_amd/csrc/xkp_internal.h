@@ -59,4 +59,17 @@ enum GmresFlags {
 
 XKP_DECLARE_VARIANT(v512)
 
+// The learned-guess network (xkp_cnn.hip).
+namespace cnn {
+size_t param_count(int k);
+size_t workspace_bytes(int B, int k);
+hipError_t forward(hipStream_t st, int B, int k, const float *prm, const double *img,
+                   const int *steps, float *alpha, float *ws);
+hipError_t backward(hipStream_t st, int B, int k, const float *prm, const double *img,
+                    const int *steps, const float *target, float *alpha, float *g, float *loss,
+                    float *ws);
+hipError_t adam(hipStream_t st, int count, float *prm, const float *g, float *m, float *v, int t,
+                float lr, float b1, float b2, float eps);
+}  // namespace cnn
+
 }  // namespace xkp

@@ -75,11 +75,19 @@ def load():
         lib.xkp_build_rhs.argtypes = [P, ct.c_int32, P]
         lib.xkp_autotune.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(Params), P,
                                      ct.POINTER(Tuning)]
+        lib.xkp_cnn_param_count.argtypes = [ct.c_int32]
+        lib.xkp_cnn_param_count.restype = ct.c_size_t
+        lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
+        lib.xkp_cnn_workspace_bytes.restype = ct.c_size_t
+        lib.xkp_cnn_forward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P]
+        lib.xkp_cnn_backward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P, P, P, P]
+        lib.xkp_cnn_adam.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int32, ct.c_float,
+                                     ct.c_float, ct.c_float, ct.c_float]
         lib.xkp_status_string.argtypes = [ct.c_int]
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
-                  "xkp_autotune"):
+                  "xkp_autotune", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -279,3 +287,49 @@ class Bases:
         off = self.offsets[i] + HEADER_BYTES + 8 * self.ldv(i) * (self.m + 1)
         raw = self.buf[off:off + 8 * (self.m + 1) * self.m]
         return raw.view(torch.float64).view(self.m, self.m + 1).T
+
+
+class Net:
+    """The learned-guess network's FP32 parameters, Adam moments and workspace on the device,
+    driven through the library's kernels (forward, backward, Adam)."""
+
+    def __init__(self, ctx, k, batch, params=None):
+        import torch
+        lib = load()
+        self.ctx, self.k, self.batch = ctx, k, batch
+        self.count = int(lib.xkp_cnn_param_count(k))
+        dev = f"cuda:{ctx.device}"
+        if params is None:
+            self.params = torch.zeros(self.count, dtype=torch.float32, device=dev)
+        else:
+            self.params = torch.as_tensor(params, dtype=torch.float32).to(dev).contiguous()
+            assert self.params.numel() == self.count
+        self.grad = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.work = torch.empty(int(lib.xkp_cnn_workspace_bytes(batch, k)), dtype=torch.uint8,
+                                device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def forward(self, images, steps, alpha):
+        """images: (B, 4096) float64, steps: (B,) int32, alpha: (B, k) float32 output."""
+        B = images.shape[0]
+        assert B <= self.batch
+        _check(load().xkp_cnn_forward(self.ctx._h, B, self.k, _ptr(self.params), _ptr(images),
+                                      _ptr(steps), _ptr(alpha), _ptr(self.work)),
+               "xkp_cnn_forward")
+
+    def backward(self, images, steps, target, alpha):
+        """Gradient of the mean squared error into self.grad, the loss into self.loss."""
+        B = images.shape[0]
+        assert B <= self.batch
+        _check(load().xkp_cnn_backward(self.ctx._h, B, self.k, _ptr(self.params), _ptr(images),
+                                       _ptr(steps), _ptr(target), _ptr(alpha), _ptr(self.grad),
+                                       _ptr(self.loss), _ptr(self.work)), "xkp_cnn_backward")
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        _check(load().xkp_cnn_adam(self.ctx._h, self.count, _ptr(self.params), _ptr(self.grad),
+                                   _ptr(self.m), _ptr(self.v), self.t, lr, beta1, beta2, eps),
+               "xkp_cnn_adam")
