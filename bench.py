@@ -156,7 +156,7 @@ def time_chain(b, args, steps, warmup, graph=True):
     elapsed = time.perf_counter() - t0
     seed_inf, tgt_inf = b.all_infos()
     ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
-    if b.method == "project":
+    if b.with_seeds:
         ok = ok and bool((seed_inf["status"] == 0).all())
     # independent FP64 check of the last timestep through the residual entry point
     rel = b.verify_last()
@@ -165,7 +165,7 @@ def time_chain(b, args, steps, warmup, graph=True):
         "elapsed": elapsed, "ok": ok, "per_chain_s": elapsed / steps,
         "iters_mean": float(tgt_inf["iters"].mean()),
         "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"],
-        "seed_iters_total": int(seed_inf["iters"].sum()) if b.method == "project" else 0,
+        "seed_iters_total": int(seed_inf["iters"].sum()) if b.with_seeds else 0,
         "guess_res_mean": float(np.mean(tgt_inf["guess_res"])),
         "max_res": float(max(tgt_inf["res_true"].max(), rel.max())),
         "N": b.N, "polish_m": int(b.params.polish_m) or b.m,

@@ -104,8 +104,9 @@ typedef struct {
     int32_t basis_dim;    /* seed: k kept in the basis; target: k used by the projection    */
     double res_est;       /* last Givens residual estimate, relative                        */
     double res_true;      /* final ||b - A x||_2 / ||b||_2 computed in FP64                  */
-    double guess_res;     /* target: relative residual of the projected guess x0           */
-    double pad;
+    double guess_res;     /* target: relative residual of the starting guess x0            */
+    int32_t guess_source; /* target: 0 x_base, 1 projection onto the seed basis, 2 learned  */
+    int32_t pad;
 } xkp_info;
 
 /*
@@ -177,6 +178,32 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
                                     int32_t n_bases, const void *const *bases,
                                     const xkp_params *params, xkp_info *infos);
 
+/*
+ * Target solve starting from a learned guess.  alpha[i*alpha_ld + r], r <= k (FP32 device array,
+ * e.g. xkp_cnn_forward's output; alpha_ld >= k+1) is the network's prediction of target i's
+ * residual coordinates zeta = Hbar_k (V_k^T x*) / beta on its seed basis
+ * bases[targets[i].basis_id] (Hbar_k and beta = ||r0|| of the seed's kept cycle, see
+ * xkp_basis_coeffs kind 1).  The guess is x0_L = x_base + V_k a with
+ * a = argmin || beta * alpha_scale * zeta - Hbar_k a || (Givens least squares).  If
+ * ||b - A x0_L|| / ||b|| (FP64) <= gate the polish starts from x0_L (info.guess_source = 2);
+ * otherwise the target falls back to xkp_target_project_solve's path for params->mode
+ * (projection then polish, or plain GMRES from x_base for XKP_PROJ_NONE).  One persistent
+ * launch, as xkp_target_project_solve.
+ */
+xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                             int32_t n_bases, const void *const *bases, const xkp_params *params,
+                             const float *alpha, int32_t alpha_ld, double alpha_scale,
+                             double gate, xkp_info *infos);
+
+/* kind 0: alpha[i][c] = v_c . x_i (FP64) for c < k of the basis bases[systems[i].basis_id], 0
+ * for k <= c < m_out (1 <= m_out <= 64): the coordinates of systems[i].x in the seed subspace.
+ * kind 1: alpha[i][r] = (Hbar_k (V_k^T x_i))_r / beta for r <= k, 0 past (m_out <= 65): the
+ * residual coordinates a learned guess predicts (xkp_learned_solve).  A descriptor or basis
+ * that does not fit writes NaN. */
+xkp_status xkp_basis_coeffs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems,
+                            int32_t n_bases, const void *const *bases, int32_t m_out,
+                            int32_t kind, double *alpha);
+
 /* rel_res[i] = ||b_i - A_i x_i||_2 / ||b_i||_2 in FP64 (||r||_2 when b_i = 0), for a device
  * array of n_sys descriptors; rel_res is a device array of n_sys doubles. */
 xkp_status xkp_residual(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, double *rel_res);
@@ -206,16 +233,21 @@ xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems);
 size_t xkp_cnn_param_count(int32_t k);
 size_t xkp_cnn_workspace_bytes(int32_t batch, int32_t k);
 
-/* alpha[b][0..k) for images[b] (batch x 4096 doubles) at timestep steps[b]. */
+/* alpha[b][0..k) (FP32) for sample b = image images + 4096 * image_idx[b] (image_idx NULL:
+ * image b; FP64 images) at timestep steps[b]. */
 xkp_status xkp_cnn_forward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
-                           const double *images, const int32_t *steps, float *alpha, void *work);
+                           const double *images, const int32_t *image_idx, const int32_t *steps,
+                           float *alpha, void *work);
 
-/* Forward pass, then the mean squared error against target[b][0..k) into *loss (one device
- * float) and its gradient with respect to every parameter into grad (param_count floats,
- * overwritten).  alpha receives the forward outputs. */
+/* Forward pass, then the mean squared error against the targets t[b][o] =
+ * target_scale * target[target_idx[b] * target_ld + o] (FP64 rows; target_idx NULL: row b) into
+ * *loss (one device float) and its gradient with respect to every parameter into grad
+ * (param_count floats, overwritten).  alpha receives the forward outputs. */
 xkp_status xkp_cnn_backward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
-                            const double *images, const int32_t *steps, const float *target,
-                            float *alpha, float *grad, float *loss, void *work);
+                            const double *images, const int32_t *image_idx, const int32_t *steps,
+                            const double *target, int32_t target_ld, const int32_t *target_idx,
+                            double target_scale, float *alpha, float *grad, float *loss,
+                            void *work);
 
 /* One Adam step on `count` FP32 parameters: m, v are the moment buffers (zero before step 1),
  * t >= 1 the step number (bias correction). */

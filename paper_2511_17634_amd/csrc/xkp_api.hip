@@ -30,6 +30,7 @@ struct Variant {
     int (*lds_vec_len)(int);
     int (*solve_per_cu)(int);
     decltype(&xkp::v512::launch_solve) solve;
+    decltype(&xkp::v512::launch_coeffs) coeffs;
     decltype(&xkp::v512::launch_residual) residual;
     decltype(&xkp::v512::launch_rhs) rhs;
     decltype(&xkp::v512::launch_apply) apply;
@@ -37,7 +38,8 @@ struct Variant {
 #define XKP_VARIANT_TABLE(NS)                                                          \
     Variant {                                                                          \
         xkp::NS::threads, xkp::NS::rmax_for, xkp::NS::lds_vec_len, xkp::NS::solve_per_cu, \
-            xkp::NS::launch_solve, xkp::NS::launch_residual, xkp::NS::launch_rhs,      \
+            xkp::NS::launch_solve, xkp::NS::launch_coeffs, xkp::NS::launch_residual,   \
+            xkp::NS::launch_rhs,                                                       \
             xkp::NS::launch_apply                                                      \
     }
 const Variant kV512 = XKP_VARIANT_TABLE(v512);
@@ -148,7 +150,7 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     const int grid = solve_grid(ctx, n_seeds);
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
                              *params, xkp::kKeepBasis, 0, nullptr, bases, infos, ctx->ws, ctx->L,
-                             nmax, ctx->queue));
+                             nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}));
 }
 
 xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
@@ -167,7 +169,41 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
     const int flags = params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0;
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
                              *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
-                             nmax, ctx->queue));
+                             nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}));
+}
+
+xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                             int32_t n_bases, const void *const *bases, const xkp_params *params,
+                             const float *alpha, int32_t alpha_ld, double alpha_scale,
+                             double gate, xkp_info *infos) {
+    int nmax = 0, rmax = 0;
+    const Variant *v = nullptr;
+    xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
+    if (st != XKP_OK) return st;
+    if (n_targets > 0 && (!infos || !alpha || alpha_ld < 1 || n_bases < 1 || !bases))
+        return XKP_EINVAL;
+    if (!(gate >= 0.0) || !(alpha_scale == alpha_scale)) return XKP_EINVAL;
+    if (n_targets == 0) return XKP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int grid = solve_grid(ctx, n_targets);
+    const int flags = xkp::kLearned | (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0);
+    return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
+                             *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
+                             nmax, ctx->queue, xkp::Learned{alpha, alpha_ld, alpha_scale, gate}));
+}
+
+xkp_status xkp_basis_coeffs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems,
+                            int32_t n_bases, const void *const *bases, int32_t m_out,
+                            int32_t kind, double *alpha) {
+    if (!ctx || n_sys < 0 || (n_sys > 0 && (!systems || !bases || n_bases < 1 || !alpha)) ||
+        m_out < 1 || m_out > 65 || (kind != 0 && kind != 1) || (kind == 0 && m_out > 64))
+        return XKP_EINVAL;
+    if (n_sys == 0) return XKP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const Variant *v = choose(ctx->max_n);
+    const int grid = n_sys < 4096 ? n_sys : 4096;
+    return from_hip(v->coeffs(ctx->stream, grid, v->rmax_for(ctx->max_n), systems, n_sys, n_bases,
+                              bases, m_out, kind, alpha, ctx->max_n));
 }
 
 xkp_status xkp_residual(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, double *rel_res) {
@@ -293,23 +329,27 @@ size_t xkp_cnn_workspace_bytes(int32_t batch, int32_t k) {
 }
 
 xkp_status xkp_cnn_forward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
-                           const double *images, const int32_t *steps, float *alpha, void *work) {
+                           const double *images, const int32_t *image_idx, const int32_t *steps,
+                           float *alpha, void *work) {
     if (!ctx || batch < 1 || k < 1 || k > 64 || !params || !images || !steps || !alpha || !work)
         return XKP_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    return from_hip(xkp::cnn::forward(ctx->stream, batch, k, params, images, steps, alpha,
-                                      (float *)work));
+    return from_hip(xkp::cnn::forward(ctx->stream, batch, k, params, images, image_idx, steps,
+                                      alpha, (float *)work));
 }
 
 xkp_status xkp_cnn_backward(xkp_ctx *ctx, int32_t batch, int32_t k, const float *params,
-                            const double *images, const int32_t *steps, const float *target,
-                            float *alpha, float *grad, float *loss, void *work) {
+                            const double *images, const int32_t *image_idx, const int32_t *steps,
+                            const double *target, int32_t target_ld, const int32_t *target_idx,
+                            double target_scale, float *alpha, float *grad, float *loss,
+                            void *work) {
     if (!ctx || batch < 1 || k < 1 || k > 64 || !params || !images || !steps || !target ||
-        !alpha || !grad || !loss || !work)
+        target_ld < k || !alpha || !grad || !loss || !work || !(target_scale == target_scale))
         return XKP_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    return from_hip(xkp::cnn::backward(ctx->stream, batch, k, params, images, steps, target,
-                                       alpha, grad, loss, (float *)work));
+    return from_hip(xkp::cnn::backward(ctx->stream, batch, k, params, images, image_idx, steps,
+                                       target, target_ld, target_idx, target_scale, alpha, grad,
+                                       loss, (float *)work));
 }
 
 xkp_status xkp_cnn_adam(xkp_ctx *ctx, int32_t count, float *params, const float *grad, float *m,

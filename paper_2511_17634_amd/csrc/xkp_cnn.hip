@@ -79,11 +79,13 @@ __device__ __forceinline__ float conv_in(const float *x, int q, int oy, int ox) 
 }
 
 // 2x2 average pooling of the FP64 64x64 images (index [i][j], p = 64 i + j) to FP32 32x32.
-__global__ void prep_kernel(int B, const double *__restrict__ img, float *__restrict__ a0) {
+__global__ void prep_kernel(int B, const double *__restrict__ img, const int *__restrict__ idx,
+                            float *__restrict__ a0) {
     const int b = blockIdx.x;
+    const size_t src = idx ? (size_t)idx[b] : (size_t)b;
     for (int t = threadIdx.x; t < kIn * kIn; t += blockDim.x) {
         const int i = t / kIn, j = t - kIn * i;
-        const double *p = img + (size_t)b * kImg * kImg + (2 * i) * kImg + 2 * j;
+        const double *p = img + src * kImg * kImg + (2 * i) * kImg + 2 * j;
         a0[(size_t)b * kIn * kIn + t] = (float)(0.25 * ((p[0] + p[1]) + (p[kImg] + p[kImg + 1])));
     }
 }
@@ -150,16 +152,20 @@ __global__ void head_fwd_kernel(int B, int k, const float *__restrict__ a3,
     }
 }
 
-// Mean squared error over B x k and its gradient d alpha = 2 (alpha - target) / (B k);
-// one workgroup, fixed summation order.
+// Mean squared error over B x k and its gradient d alpha = 2 (alpha - target) / (B k), the
+// target of sample b being scale * target[tidx[b] * ld + o] (FP64 rows); one workgroup, fixed
+// summation order.
 __global__ void loss_kernel(int B, int k, const float *__restrict__ alpha,
-                            const float *__restrict__ target, float *__restrict__ dalpha,
-                            float *__restrict__ loss) {
+                            const double *__restrict__ target, int ld,
+                            const int *__restrict__ tidx, double scale,
+                            float *__restrict__ dalpha, float *__restrict__ loss) {
     __shared__ float part[256];
     const int cnt = B * k;
     float s = 0.f;
     for (int i = threadIdx.x; i < cnt; i += 256) {
-        const float d = alpha[i] - target[i];
+        const int b = i / k, o = i - k * b;
+        const size_t row = tidx ? (size_t)tidx[b] : (size_t)b;
+        const float d = alpha[i] - (float)(scale * target[row * ld + o]);
         dalpha[i] = 2.f * d / (float)cnt;
         s += d * d;
     }
@@ -352,9 +358,9 @@ size_t workspace_bytes(int B, int k) { return plan(B, k).total * sizeof(float); 
 static int blocks(size_t n, int t) { return (int)((n + t - 1) / t); }
 
 hipError_t forward(hipStream_t st, int B, int k, const float *prm, const double *img,
-                   const int *steps, float *alpha, float *ws) {
+                   const int *img_idx, const int *steps, float *alpha, float *ws) {
     const Plan p = plan(B, k);
-    hipLaunchKernelGGL(prep_kernel, dim3(B), dim3(256), 0, st, B, img, ws + p.a0);
+    hipLaunchKernelGGL(prep_kernel, dim3(B), dim3(256), 0, st, B, img, img_idx, ws + p.a0);
     hipLaunchKernelGGL((conv_fwd_kernel<1, 16, 32>), dim3(blocks(1 * (B * 256 / 16), 4)),
                        dim3(256), 0, st, B, ws + p.a0, prm, 0, ws + p.z1, ws + p.a1);
     hipLaunchKernelGGL((conv_fwd_kernel<16, 32, 16>), dim3(blocks(2 * (B * 64 / 16), 4)),
@@ -377,13 +383,14 @@ static void wgrad(hipStream_t st, const Plan &p, int B, const float *x, const fl
 }
 
 hipError_t backward(hipStream_t st, int B, int k, const float *prm, const double *img,
-                    const int *steps, const float *target, float *alpha, float *g, float *loss,
+                    const int *img_idx, const int *steps, const double *target, int ld,
+                    const int *tidx, double scale, float *alpha, float *g, float *loss,
                     float *ws) {
-    hipError_t e = forward(st, B, k, prm, img, steps, alpha, ws);
+    hipError_t e = forward(st, B, k, prm, img, img_idx, steps, alpha, ws);
     if (e != hipSuccess) return e;
     const Plan p = plan(B, k);
-    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, B, k, alpha, target, ws + p.dal,
-                       loss);
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, B, k, alpha, target, ld, tidx,
+                       scale, ws + p.dal, loss);
     hipLaunchKernelGGL(head_wgrad_kernel, dim3(blocks((size_t)k * (kFeat + 1), 128)), dim3(128),
                        0, st, B, k, ws + p.dal, ws + p.u, g);
     hipLaunchKernelGGL(head_dgrad_kernel, dim3(blocks((size_t)B * 1024, 256)), dim3(256), 0, st,

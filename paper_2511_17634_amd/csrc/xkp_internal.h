@@ -32,7 +32,17 @@ size_t basis_bytes(int n, int m);
 enum GmresFlags {
     kStartFromX = 1,   // initial guess is the descriptor's x (the projected x0)
     kKeepBasis = 2,    // seed build: write the first cycle into bases[i]
-    kTarget = 4        // project onto the seed basis first, then polish from the projection
+    kTarget = 4,       // project onto the seed basis first, then polish from the projection
+    kLearned = 8       // try the learned guess first; project only if it fails the gate
+};
+
+// Learned-guess inputs of a solve launch: target i's predicted residual coordinates at
+// alpha + i*ld (FP32, k+1 used), multiplied by scale; the guess is kept when its relative
+// residual is <= gate.
+struct Learned {
+    const float *alpha;
+    int ld;
+    double scale, gate;
 };
 
 // The kernel file can be compiled once per workgroup size into its own namespace; the build
@@ -48,7 +58,10 @@ enum GmresFlags {
                             int nsys, xkp_params P, int flags, int n_bases,                      \
                             const void *const *bases, void *const *keep_bases,                   \
                             xkp_info *infos, double *ws, WsLayout L, int nmax,                   \
-                            unsigned *queue);                                                    \
+                            unsigned *queue, Learned lg);                                        \
+    hipError_t launch_coeffs(hipStream_t st, int grid, int rmax, const xkp_system *sys,         \
+                             int nsys, int n_bases, const void *const *bases, int m_out,         \
+                             int kind, double *alpha, int nmax);                                 \
     hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds,                     \
                                const xkp_system *sys, int nsys, double *rel, int nmax);          \
     hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,   \
@@ -64,9 +77,10 @@ namespace cnn {
 size_t param_count(int k);
 size_t workspace_bytes(int B, int k);
 hipError_t forward(hipStream_t st, int B, int k, const float *prm, const double *img,
-                   const int *steps, float *alpha, float *ws);
+                   const int *img_idx, const int *steps, float *alpha, float *ws);
 hipError_t backward(hipStream_t st, int B, int k, const float *prm, const double *img,
-                    const int *steps, const float *target, float *alpha, float *g, float *loss,
+                    const int *img_idx, const int *steps, const double *target, int ld,
+                    const int *tidx, double scale, float *alpha, float *g, float *loss,
                     float *ws);
 hipError_t adam(hipStream_t st, int count, float *prm, const float *g, float *m, float *v, int t,
                 float lr, float b1, float b2, float eps);

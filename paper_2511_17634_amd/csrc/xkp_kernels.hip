@@ -373,7 +373,8 @@ struct GmresLds {
 __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
 
 template <int RMAX, bool MIXED>
-__device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags, int prestatus,
+__device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags,
+                                          int prestatus, int gsrc,
                           xkp_basis_header *hdr, double *Vfirst, double *Hb, double *Vws,
                           const Coef &C, xkp_info *info, GmresLds &L) {
     const OpConst o = op_const(s);
@@ -595,6 +596,8 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
         info->res_true = res_true;
         if (!(flags & kKeepBasis)) info->guess_res = guess;
         else info->guess_res = 1.0;
+        info->guess_source = gsrc;
+        info->pad = 0;
     }
     // no wave may start the next system (and overwrite LDS / workspace) while others still
     // read this one's values
@@ -1165,12 +1168,99 @@ __device__ __noinline__ int project_call(xkp_system s, xkp_info *info, int n_bas
 }
 
 template <int R, bool MIXED>
-__device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, int pre,
+__device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, int pre, int gsrc,
                                         xkp_basis_header *hdr, double *Vfirst, double *Hb,
                                         double *Vws, Coef C, xkp_info *info, int nlds) {
     GmresLds L(xkp_dyn_lds, uni(nlds), kNT * R);
-    gmres_one<R, MIXED>(uni(s), uni(P), uni(flags), uni(pre), uni(hdr), uni(Vfirst), uni(Hb), uni(Vws),
-                 uni(C), uni(info), L);
+    gmres_one<R, MIXED>(uni(s), uni(P), uni(flags), uni(pre), uni(gsrc), uni(hdr), uni(Vfirst),
+                        uni(Hb), uni(Vws), uni(C), uni(info), L);
+}
+
+// Learned starting guess of one target.  The network predicts the target's residual
+// coordinates in the seed's Arnoldi basis, zeta ~ Hbar_k alpha* / beta_seed (k+1 values, FP32);
+// alpha = argmin || beta_seed * scale * zeta - Hbar_k alpha || (Givens least squares on the seed's
+// Hessenberg matrix, as the least-squares projection mode), x0 = x_base + V_k alpha, written to
+// s.x.  Returns ||b - A x0|| / ||b|| in FP64 (0 when b = 0), or -1 when the target has no usable
+// basis or the least-squares problem is singular (s.x may then hold a partial guess; the caller
+// falls back).  LDS: the projection layout (matrix at the base, vectors after nregion).
+template <int R>
+__device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const void *const *bases,
+                                            xkp_params P0, const float *a, int ka, double scale,
+                                            Coef C0, int nlds, int nregion) {
+    const xkp_system s = uni(s0);
+    const xkp_params P = uni(P0);
+    const Coef C = uni(C0);
+    a = uni(a);
+    ka = uni(ka);
+    scale = uni(scale);
+    nlds = uni(nlds);
+    nregion = uni(nregion);
+    bases = uni(bases);
+    n_bases = uni(n_bases);
+    const int n = s.H * s.H, tid = threadIdx.x;
+    if (!(s.basis_id >= 0 && s.basis_id < n_bases)) return -1.0;
+    const xkp_basis_header *hdr = (const xkp_basis_header *)bases[s.basis_id];
+    if (!(hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m))
+        return -1.0;
+    const int m = P.m, k = hdr->k;
+    if (ka < k + 1) return -1.0;
+    const double *V = (const double *)((const char *)hdr + 256);
+    const double *Hb = (const double *)((const char *)hdr + basis_off_h(n, m));
+    const int ldv = ldv_for(n);
+    double *lds = xkp_dyn_lds;
+    double *Ap = lds;
+    double *zv = lds + nregion;
+    double *alpha = zv + kMMax + 1;
+    int *pivl = (int *)(alpha + kMMax);
+    double *red = alpha + kMMax + kMMax / 2;
+    double *vbuf = lds + (nlds - kNT * R) / 2;
+    BlockRed br{red, 0};
+    const OpConst o = op_const(s);
+    build_coeffs<R>(s, o, C, false);
+    bool singular = false;
+    if (k > 0) {
+        const double zs = hdr->beta * scale;
+        for (int r = tid; r <= k; r += kNT) zv[r] = zs * (double)a[r];
+        for (int t = tid; t < (k + 1) * k; t += kNT) {
+            const int r = t / k, c = t % k;
+            Ap[r * kLdA + c] = Hb[(size_t)c * (m + 1) + r];
+        }
+        lds_barrier();
+        if ((tid >> 6) == 0) singular = lsq_hessenberg_wave(Ap, kLdA, k, zv, alpha);
+        if (tid == 0) pivl[kMMax - 1] = singular ? 1 : 0;
+        lds_barrier();
+        singular = pivl[kMMax - 1] != 0;
+    }
+    double xr[R], w[R];
+    if (s.x0) {
+        load_rows<R>(s.x0, n, xr);
+    } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) xr[q] = 0.0;
+    }
+    if (k > 0 && !singular) {
+        sweep_cols<R, Depth<R>::value>(V, n, ldv, k, k, [&](int c, const double(&col)[R]) {
+            const double al = alpha[c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) xr[q] += al * col[q];
+        });
+    }
+    // the matrix area holds the zero-padded vector copy from here on
+    lds_barrier();
+    for (int t = tid; t < nlds; t += kNT) lds[t] = 0.0;
+    lds_barrier();
+    store_rows<R>(s.x, n, xr);
+    store_rows_lds<R>(vbuf, xr);
+    lds_barrier();
+    stencil_lds<R>(vbuf, C, o, w);
+    load_rows<R>(s.b, n, xr);
+#pragma unroll
+    for (int q = 0; q < R; ++q) w[q] = xr[q] - w[q];
+    double two[2] = {dot_rows<R>(w, w), dot_rows<R>(xr, xr)};
+    br.sum_multi<2>(two);
+    __syncthreads();   // the polish reads rows of x0 written by other threads, and reuses LDS
+    if (singular) return -1.0;
+    return two[1] > 0.0 ? sqrt(two[0]) / sqrt(two[1]) : 0.0;
 }
 
 template <int R, bool PROJ>
@@ -1178,9 +1268,24 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           const xkp_params &P, int flags, int n_bases,
                                           const void *const *bases, void *keep_base,
                                           const Coef &C, double *slot, const WsLayout &Lw,
-                                          double *lds, int nlds, int nbuf, int nregion) {
+                                          double *lds, int nlds, int nbuf, int nregion,
+                                          const Learned &lg, const float *al) {
     int pre = XKP_OK;
-    if constexpr (PROJ) {
+    int gsrc = (flags & kTarget) ? 1 : 0;
+    bool project = PROJ;
+    if (flags & kLearned) {
+        // the network's guess, kept when its FP64 residual passes the gate
+        for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;
+        lds_barrier();
+        const double rel =
+            learned_call<R>(s, n_bases, bases, P, al, lg.ld, lg.scale, C, nlds, nregion);
+        if (rel >= 0.0 && rel <= lg.gate) {
+            project = false;
+            gsrc = 2;
+            flags |= kStartFromX;
+        }
+    }
+    if (PROJ && project) {
         pre = P.precision == XKP_MIXED
                   ? project_call<R, true>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds, nbuf,
                                           nregion)
@@ -1201,9 +1306,9 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
     }
     if (P.precision == XKP_MIXED)
-        gmres_call<R, true>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
+        gmres_call<R, true>(s, P, flags, pre, gsrc, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
     else
-        gmres_call<R, false>(s, P, flags, pre, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
+        gmres_call<R, false>(s, P, flags, pre, gsrc, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
 }
 
 template <int RMAX, bool PROJ>
@@ -1212,7 +1317,8 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
                                                     const void *const *bases,
                                                     void *const *keep_bases, xkp_info *infos,
                                                     double *ws, WsLayout Lw, int nmax, int nlds,
-                                                    int nbuf, int nregion, unsigned *queue) {
+                                                    int nbuf, int nregion, unsigned *queue,
+                                                    Learned lg) {
     double *lds = xkp_dyn_lds;
     __shared__ int next[2];
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
@@ -1234,8 +1340,10 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
         }
         void *kb = (flags & kKeepBasis) ? keep_bases[si] : nullptr;
         const int n = s.H * s.H;
-#define XKP_SOLVE(R_) \
-    solve_one<R_, PROJ>(s, info, P, flags, n_bases, bases, kb, C, slot, Lw, lds, nlds, nbuf, nregion)
+        const float *al = (flags & kLearned) ? lg.alpha + (size_t)si * lg.ld : nullptr;
+#define XKP_SOLVE(R_)                                                                            \
+    solve_one<R_, PROJ>(s, info, P, flags, n_bases, bases, kb, C, slot, Lw, lds, nlds, nbuf, nregion, \
+                        lg, al)
         if constexpr (RMAX > kRClass0) {
             if (n <= kNT * kRClass0) {
                 XKP_SOLVE(kRClass0);
@@ -1262,6 +1370,69 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
 }
 
 // ----------------------------------------------------------------------------------------
+
+// alpha[i][c] = v_c . x_i for c < k (the kept basis of system i's seed), 0 for k <= c < m_out:
+// the coordinates of x_i in the seed subspace (the regression targets of the learned guess).
+// kind 1: the residual coordinates zeta = Hbar_k (V_k^T x_i) / beta_seed (k+1 values, 0 past),
+// the regression targets of the learned guess.
+template <int RMAX>
+__global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restrict__ sys, int nsys,
+                                                     int n_bases, const void *const *bases,
+                                                     int m_out, int kind, double *alpha,
+                                                     int nmax) {
+    extern __shared__ double lds[];
+    BlockRed br{lds, 0};
+    double *av = lds + 2 * kRedSlots * kNW;   // kMMax coordinates
+    for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
+        const xkp_system s = sys[si];
+        double *out = alpha + (size_t)si * m_out;
+        const int n = s.H * s.H;
+        bool ok = s.H > 0 && n <= nmax && s.x != nullptr && s.basis_id >= 0 &&
+                  s.basis_id < n_bases;
+        const xkp_basis_header *hdr = nullptr;
+        if (ok) {
+            hdr = (const xkp_basis_header *)bases[s.basis_id];
+            ok = hdr != nullptr && hdr->n == n && hdr->k >= 0 && hdr->k <= hdr->m;
+        }
+        if (!ok) {
+            for (int c = threadIdx.x; c < m_out; c += kNT) out[c] = __builtin_nan("");
+            continue;
+        }
+        const int k = hdr->k, ldv = ldv_for(n);
+        const double *V = (const double *)((const char *)hdr + 256);
+        double xr[RMAX], col[RMAX];
+        load_rows<RMAX>(s.x, n, xr);
+        for (int c0 = 0; c0 < m_out; c0 += kRedSlots) {
+            double part[kRedSlots];
+#pragma unroll
+            for (int q = 0; q < kRedSlots; ++q) {
+                part[q] = 0.0;
+                if (c0 + q < k) {
+                    load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, col);
+                    part[q] = dot_rows<RMAX>(col, xr);
+                }
+            }
+            br.sum_multi<kRedSlots>(part);
+            if (threadIdx.x == 0)
+                for (int q = 0; q < kRedSlots && c0 + q < m_out; ++q) {
+                    if (kind == 0) out[c0 + q] = part[q];
+                    else if (c0 + q < kMMax) av[c0 + q] = part[q];
+                }
+        }
+        if (kind == 1) {
+            __syncthreads();
+            const double *Hb = (const double *)((const char *)hdr + basis_off_h(n, hdr->m));
+            const int m = hdr->m;
+            for (int r = threadIdx.x; r < m_out; r += kNT) {
+                double z = 0.0;
+                if (r <= k)
+                    for (int c = (r > 0 ? r - 1 : 0); c < k; ++c) z += Hb[(size_t)c * (m + 1) + r] * av[c];
+                out[r] = hdr->beta > 0.0 ? z / hdr->beta : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+}
 
 template <int RMAX>
 __global__ __launch_bounds__(kNT) void residual_kernel(const xkp_system *__restrict__ sys, int nsys,
@@ -1443,16 +1614,16 @@ static SolvePlan solve_plan(int nlds, bool proj) {
 hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
                         int nsys, xkp_params P, int flags, int n_bases, const void *const *bases,
                         void *const *keep_bases, xkp_info *infos, double *ws, WsLayout L,
-                        int nmax, unsigned *queue) {
+                        int nmax, unsigned *queue, Learned lg) {
     const bool proj = (flags & kTarget) != 0;
-    const SolvePlan sp = solve_plan(nlds, proj);
+    const SolvePlan sp = solve_plan(nlds, proj || (flags & kLearned) != 0);
 #define XKP_LAUNCH_SOLVE(PJ)                                                                   \
     {                                                                                          \
         hipError_t e = set_lds(solve_kernel<R, PJ>, sp.lds);                                   \
         if (e != hipSuccess) return e;                                                         \
         hipLaunchKernelGGL((solve_kernel<R, PJ>), dim3(grid), dim3(kNT), sp.lds, st, sys, nsys, \
                            P, flags, n_bases, bases, keep_bases, infos, ws, L, nmax, nlds,     \
-                           sp.nbuf, sp.nregion, queue);                                        \
+                           sp.nbuf, sp.nregion, queue, lg);                                    \
     }
     XKP_DISPATCH(rmax, {
         if (proj) XKP_LAUNCH_SOLVE(true) else XKP_LAUNCH_SOLVE(false)
@@ -1489,6 +1660,17 @@ int solve_per_cu(int nmax) {
         if (nb > best) best = nb;
     }
     return best;
+}
+
+hipError_t launch_coeffs(hipStream_t st, int grid, int rmax, const xkp_system *sys, int nsys,
+                         int n_bases, const void *const *bases, int m_out, int kind,
+                         double *alpha, int nmax) {
+    const size_t lds = sizeof(double) * (2 * kRedSlots * kNW + kMMax);
+    XKP_DISPATCH(rmax, {
+        hipLaunchKernelGGL(coeffs_kernel<R>, dim3(grid), dim3(kNT), lds, st, sys, nsys, n_bases,
+                           bases, m_out, kind, alpha, nmax);
+    });
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,

@@ -48,18 +48,23 @@ class Batch:
 
     def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
                  mode="target_galerkin", warm=False, max_restarts=1000, device=0,
-                 precision=xkp.FP64, pipeline=True, polish_m=0):
+                 precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None):
+        """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
+        (the network's guess behind the residual gate, projection as fallback; `learned` =
+        dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
+        gate=residual gate), single 64x64 group of one channel).  with_seeds: also solve the seeds with plain targets."""
         import torch
         self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
         self.T, self.m, self.g, self.tol = T, m, g, tol
         self.method = method
+        self.with_seeds = (method != "plain") if with_seeds is None else with_seeds
         self.dev = torch.device(f"cuda:{device}")
         self.nmax = max(gr.n for gr in self.groups)
         self.S = sum(gr.C for gr in self.groups)
         self.N = sum(gr.N * gr.C for gr in self.groups)
         self.s_main = torch.cuda.Stream(device=self.dev)
         self.ctx = xkp.Context(self.nmax, m, max(self.N, 1), device=device, stream=self.s_main)
-        self.pipeline = pipeline and method == "project"
+        self.pipeline = pipeline and self.with_seeds
         if self.pipeline:
             self.s_seed = torch.cuda.Stream(device=self.dev)
             self.ctx_seed = xkp.Context(self.nmax, m, self.S, device=device, stream=self.s_seed)
@@ -92,6 +97,17 @@ class Batch:
         self.bases = xkp.Bases(2 * self.S, ns * 2, m, device=device)
         self.dt = 1.0 / T
         mode_id = xkp.NONE if method == "plain" else xkp.MODES[mode]
+        self.learned = None
+        if method == "learned":
+            assert len(self.groups) == 1 and self.groups[0].H == 64 and self.groups[0].C == 1
+            gr = self.groups[0]
+            k = m + 1                      # residual coordinates of an m-column basis
+            self.learned = dict(learned)
+            self.net = xkp.Net(self.ctx, k, self.N, learned["params"])
+            self.images = torch.tensor(gr.target_m0.reshape(self.N, -1), **f64)
+            steps = np.repeat(np.arange(1, T + 1, dtype=np.int32)[:, None], self.N, axis=1)
+            self.steps_all = torch.from_numpy(steps).to(self.dev)
+            self.alpha_l = torch.empty((self.N, k), dtype=torch.float32, device=self.dev)
         self.params = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
                                          precision=precision, mode=mode_id,
                                          batch_max_n=self.nmax, polish_m=polish_m)
@@ -142,14 +158,15 @@ class Batch:
         return (self.info_s_all[t * self.S * w:(t + 1) * self.S * w],
                 self.info_t_all[t * self.N * w:(t + 1) * self.N * w])
 
-    def step(self, events=None):
+    def step(self, events=None, after_targets=None):
         """Enqueue one timestep.  `events`, if given, is a pair of HIP events recorded on the
-        main stream around the target call."""
+        main stream around the target call; `after_targets(par, bases)` is called after the
+        target call is enqueued."""
         par = self.step_no & 1
         c = self.ctx
         inf_s, inf_t = self._info_slices(self.step_no % self.T)
         bases = self.bases.ptrs[par * self.S:(par + 1) * self.S]
-        if self.method == "project":
+        if self.with_seeds:
             cs = self.ctx_seed
             if self.pipeline and self.step_no >= 2:
                 self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
@@ -161,9 +178,17 @@ class Batch:
         c.build_rhs(self.tgt_desc[par], self.N)
         if events is not None:
             events[0].record(c.stream)
-        c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
+        if self.learned is not None:
+            t = self.step_no % self.T
+            self.net.forward(self.images, self.steps_all[t], self.alpha_l)
+            c.learned_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, self.alpha_l,
+                            self.m + 1, self.learned["scale"], self.learned["gate"], inf_t)
+        else:
+            c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         if events is not None:
             events[1].record(c.stream)
+        if after_targets is not None:
+            after_targets(par, bases)
         if self.pipeline:
             self.ev_tgt[par].record(c.stream)
         self.step_no += 1
@@ -210,7 +235,7 @@ class Batch:
         par = self.step_no & 1
         bases = self.bases.ptrs[par * self.S:(par + 1) * self.S]
         inf_s, inf_t = self._info_slices(self.step_no % self.T)
-        if self.method == "project":
+        if self.with_seeds:
             self.ctx_seed.build_rhs(self.seed_desc[par], self.S)
             self.ctx_seed.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
         self.ctx.build_rhs(self.tgt_desc[par], self.N)

@@ -1,0 +1,65 @@
+"""Learned starting guess: training data from the method's own solves, training with the
+library's network kernels, and the regression target.
+
+For every target t and timestep n the best guess inside the seed subspace is V_n alpha*_{t,n},
+alpha* = V_n^T x*_{t,n} (the 2-norm fit to the target's converged solution).  The network learns
+it in residual coordinates, zeta*_{t,n} = Hbar_n alpha*_{t,n} / beta_n (Hbar_n, beta_n: the
+seed's kept Arnoldi cycle at step n), from the target's initial image and n: since
+A_seed V_n = V_{n,k+1} Hbar_n, an error in zeta is (for targets close to the seed) the error of
+the guess's relative residual, so the squared loss measures what the guess is judged by, and
+the solve recovers alpha by the Hessenberg least-squares problem.  zeta* is order one (its first
+entry is about ||b_t|| / ||b_seed||), so no further scaling is applied.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import xkp
+from .driver import Batch, Group
+
+
+def generate(seed_m0, target_m0, T, m, device=0):
+    """Run the chain (seeds with kept bases, targets by plain GMRES to 1e-8) and collect
+    zeta*[t][i] = Hbar_{t+1} V_{t+1}^T x*_{i,t+1} / beta_{t+1} (float64 device tensor
+    (T, N, m + 1))."""
+    import torch
+    gr = Group(64, np.asarray(seed_m0).reshape(1, -1), np.asarray(target_m0).reshape(-1, 1, 4096))
+    b = Batch([gr], T, m, method="plain", with_seeds=True, pipeline=False, device=device)
+    alpha = torch.empty((T, b.N, m + 1), dtype=torch.float64, device=b.dev)
+    b.reset()
+    for t in range(T):
+        b.step(after_targets=lambda par, bases, t=t: b.ctx.basis_coeffs(
+            b.tgt_desc[par], b.N, b.S, bases, m + 1, alpha[t], kind=1))
+    s_inf, t_inf = b.all_infos()
+    ok = bool((s_inf["status"] == 0).all() and (t_inf["status"] == 0).all())
+    torch.cuda.synchronize()
+    return alpha, ok
+
+
+def train(net, images, alpha_star, epochs, batch, lr, seed=0, log=None):
+    """Adam on the mean squared error between the network's outputs for (image i, timestep t+1)
+    and zeta*[t][i], every (i, t) once per epoch in a random order.  Returns the per-epoch mean
+    loss."""
+    import torch
+    T, N, m = alpha_star.shape
+    rows = alpha_star.reshape(T * N, m)
+    scale = 1.0
+    dev = alpha_star.device
+    rng = np.random.default_rng(seed)
+    out = torch.empty((batch, net.k), dtype=torch.float32, device=dev)
+    hist = []
+    for ep in range(epochs):
+        perm = rng.permutation(T * N).astype(np.int32)
+        img_idx = torch.from_numpy(perm % N).to(dev)
+        steps = torch.from_numpy(perm // N + 1).to(dev)
+        tidx = torch.from_numpy(perm).to(dev)
+        losses = torch.zeros((T * N) // batch, dtype=torch.float32, device=dev)
+        for j, s0 in enumerate(range(0, T * N - batch + 1, batch)):
+            net.backward(images, steps[s0:s0 + batch], rows, out, image_idx=img_idx[s0:s0 + batch],
+                         target_idx=tidx[s0:s0 + batch], target_scale=scale)
+            net.adam(lr)
+            losses[j:j + 1].copy_(net.loss)
+        hist.append(float(losses.mean()))
+        if log:
+            log(f"epoch {ep}: mean loss {hist[-1]:.5f}")
+    return hist

@@ -27,7 +27,7 @@ SYSTEM_DTYPE = np.dtype([("H", "<i4"), ("basis_id", "<i4"), ("dt", "<f8"), ("g",
                          ("x0", "<u8"), ("x", "<u8")])
 INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("restarts", "<i4"),
                        ("basis_dim", "<i4"), ("res_est", "<f8"), ("res_true", "<f8"),
-                       ("guess_res", "<f8"), ("pad", "<f8")])
+                       ("guess_res", "<f8"), ("guess_source", "<i4"), ("pad", "<i4")])
 HEADER_BYTES = 256
 
 
@@ -79,15 +79,21 @@ def load():
         lib.xkp_cnn_param_count.restype = ct.c_size_t
         lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
         lib.xkp_cnn_workspace_bytes.restype = ct.c_size_t
-        lib.xkp_cnn_forward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P]
-        lib.xkp_cnn_backward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P, P, P, P]
+        lib.xkp_cnn_forward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P, P]
+        lib.xkp_cnn_backward.argtypes = [P, ct.c_int32, ct.c_int32, P, P, P, P, P, ct.c_int32, P,
+                                         ct.c_double, P, P, P, P]
         lib.xkp_cnn_adam.argtypes = [P, ct.c_int32, P, P, P, P, ct.c_int32, ct.c_float,
                                      ct.c_float, ct.c_float, ct.c_float]
+        lib.xkp_learned_solve.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(Params),
+                                          P, ct.c_int32, ct.c_double, ct.c_double, P]
+        lib.xkp_basis_coeffs.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.c_int32, ct.c_int32,
+                                         P]
         lib.xkp_status_string.argtypes = [ct.c_int]
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
-                  "xkp_autotune", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam"):
+                  "xkp_autotune", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
+                  "xkp_learned_solve", "xkp_basis_coeffs"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -220,6 +226,20 @@ class Context:
                                    ct.byref(params), _ptr(infos), ct.byref(t)), "xkp_autotune")
         return t
 
+    def learned_solve(self, systems, n_sys, n_bases, bases_ptrs, params, alpha, alpha_ld,
+                      alpha_scale, gate, infos):
+        """Polish from the guess rebuilt from the predicted residual coordinates alpha (times
+        alpha_scale) when its residual is <= gate, else the projection path of params.mode."""
+        _check(load().xkp_learned_solve(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
+                                        ct.byref(params), _ptr(alpha), alpha_ld, alpha_scale,
+                                        gate, _ptr(infos)), "xkp_learned_solve")
+
+    def basis_coeffs(self, systems, n_sys, n_bases, bases_ptrs, m_out, alpha, kind=0):
+        """kind 0: alpha[i][c] = v_c . x_i on each system's seed basis; kind 1: the residual
+        coordinates Hbar (V^T x_i) / beta (float64 device, (n_sys, m_out))."""
+        _check(load().xkp_basis_coeffs(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
+                                       m_out, kind, _ptr(alpha)), "xkp_basis_coeffs")
+
     def residual(self, systems, n_sys, rel_out):
         _check(load().xkp_residual(self._h, n_sys, _ptr(systems), _ptr(rel_out)), "xkp_residual")
 
@@ -312,21 +332,26 @@ class Net:
                                 device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
 
-    def forward(self, images, steps, alpha):
-        """images: (B, 4096) float64, steps: (B,) int32, alpha: (B, k) float32 output."""
-        B = images.shape[0]
+    def forward(self, images, steps, alpha, image_idx=None, B=None):
+        """images: (M, 4096) float64 (sample b uses row image_idx[b], or row b), steps: (B,)
+        int32, alpha: (B, k) float32 output."""
+        B = B or steps.shape[0]
         assert B <= self.batch
         _check(load().xkp_cnn_forward(self.ctx._h, B, self.k, _ptr(self.params), _ptr(images),
-                                      _ptr(steps), _ptr(alpha), _ptr(self.work)),
-               "xkp_cnn_forward")
+                                      _ptr(image_idx), _ptr(steps), _ptr(alpha),
+                                      _ptr(self.work)), "xkp_cnn_forward")
 
-    def backward(self, images, steps, target, alpha):
-        """Gradient of the mean squared error into self.grad, the loss into self.loss."""
-        B = images.shape[0]
+    def backward(self, images, steps, target, alpha, image_idx=None, target_idx=None,
+                 target_scale=1.0, B=None):
+        """Gradient of the mean squared error against target_scale * target rows (float64,
+        (R, ld)) into self.grad, the loss into self.loss."""
+        B = B or steps.shape[0]
         assert B <= self.batch
         _check(load().xkp_cnn_backward(self.ctx._h, B, self.k, _ptr(self.params), _ptr(images),
-                                       _ptr(steps), _ptr(target), _ptr(alpha), _ptr(self.grad),
-                                       _ptr(self.loss), _ptr(self.work)), "xkp_cnn_backward")
+                                       _ptr(image_idx), _ptr(steps), _ptr(target),
+                                       target.shape[-1], _ptr(target_idx), target_scale,
+                                       _ptr(alpha), _ptr(self.grad), _ptr(self.loss),
+                                       _ptr(self.work)), "xkp_cnn_backward")
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1

@@ -53,9 +53,11 @@ def test_forward_matches_reference(X):
     k, theta, imgs, steps, _ = problem()
     ctx = X.Context(4096, 40, 1)
     net = X.Net(ctx, k, len(imgs), theta)
-    im, st = to_dev(X, imgs, steps)
+    # images stored in reverse order, addressed through image_idx
+    im, st = to_dev(X, imgs[::-1].copy(), steps)
+    idx = torch.tensor(np.arange(len(imgs))[::-1].copy(), dtype=torch.int32, device=dev())
     alpha = torch.empty((len(imgs), k), dtype=torch.float32, device=dev())
-    net.forward(im, st, alpha)
+    net.forward(im, st, alpha, image_idx=idx)
     torch.cuda.synchronize()
     ref = cnn.forward(theta, k, imgs, steps)
     rel, cos = close(cpu(alpha), ref)
@@ -69,9 +71,14 @@ def test_gradient_matches_reference(X):
     ctx = X.Context(4096, 40, 1)
     net = X.Net(ctx, k, len(imgs), theta)
     im, st = to_dev(X, imgs, steps)
-    tg = torch.tensor(target, dtype=torch.float32, device=dev())
+    # rows in shuffled order, scaled by 1/4: the kernel reads row perm[b] times 4
+    perm = np.array([3, 0, 5, 1, 4, 2], dtype=np.int32)
+    stored = np.empty_like(target)
+    stored[perm] = target / 4.0
+    tg = torch.tensor(stored, dtype=torch.float64, device=dev())
+    ti = torch.tensor(perm, dtype=torch.int32, device=dev())
     alpha = torch.empty((len(imgs), k), dtype=torch.float32, device=dev())
-    net.backward(im, st, tg, alpha)
+    net.backward(im, st, tg, alpha, target_idx=ti, target_scale=4.0)
     torch.cuda.synchronize()
     L, g = cnn.loss_and_grad(theta, k, imgs, steps, target)
     gl = cpu(net.grad)
@@ -113,7 +120,7 @@ def test_training_lowers_the_loss(X):
     ctx = X.Context(4096, 40, 1)
     net = X.Net(ctx, k, len(imgs), theta)
     im, st = to_dev(X, imgs, steps)
-    tg = torch.tensor(target, dtype=torch.float32, device=dev())
+    tg = torch.tensor(target, dtype=torch.float64, device=dev())
     alpha = torch.empty((len(imgs), k), dtype=torch.float32, device=dev())
     losses = []
     for _ in range(50):
