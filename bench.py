@@ -12,9 +12,11 @@ unit come from the library's autotuner, run on the chain's own inputs before the
 (--no-tune: restart length m).  Inputs are resident in device memory before the timed region.
 
 Also timed (--no-uneven skips it): the uneven batch, 32x32 / 64x64 / 128x128 grids with 3
-channels each (3072 target systems, 9 seeds) in one launch per timestep; and (--no-mixed skips
+channels each (3072 target systems, 9 seeds) in one launch per timestep; (--no-mixed skips
 it) the 128x128 workload (1 seed + 255 targets, m = 60) in mixed and FP64 precision, with each
-target's error against the FP64 path.
+target's error against the FP64 path; and (--no-learned skips it) the learned-guess workload:
+training data from the method's own 64x64 chain (4096 targets), training, and 1024 held-out
+targets solved with the learned guess behind residual gates beside projection and plain GMRES.
 
 Prints one JSON line.
 """
@@ -137,6 +139,66 @@ def err_vs_fp64(b, tol=1e-12):
     return np.array(errs), ok
 
 
+def learned_leg(args):
+    """64x64 learned-guess workload: training data from the method's own chain (seed + 4096
+    targets x 100 timesteps), training on the GPU, then 1024 held-out targets solved by plain
+    GMRES, projection + polish and the learned guess behind residual gates 1e-6, 1e-2, 1e300."""
+    import torch
+    from paper_2511_17634_amd import learned, xkp
+    from paper_2511_17634_amd.driver import Batch, Group
+    from synth import CONFIGS, config_images, initial_state
+    from synth.configs import ROLE_EVAL
+    cfg = CONFIGS["c5"]
+    T, m = cfg.T, cfg.m
+    seed, tg = config_images(cfg, 0)
+    s0 = initial_state(seed[0])
+    t0 = np.stack([initial_state(t[0]) for t in tg])
+    _, ev = config_images(cfg, 0, 0, 1024, role=ROLE_EVAL)
+    e0 = np.stack([initial_state(t[0]) for t in ev])
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter()
+    zeta, gen_ok = learned.generate(s0, t0, T, m)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    ctx = xkp.Context(4096, m, 1)
+    net = xkp.Net(ctx, m + 1, 512, learned.init_params(m + 1, np.random.default_rng(0)))
+    imgs = torch.tensor(t0, dtype=torch.float64, device="cuda")
+    t_tr = time.perf_counter()
+    hist = learned.train(net, imgs, zeta, args.learned_epochs, 512, 2e-3)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t_tr
+    legs, polish_m = {}, 0
+    for name, kw in (("project", dict(method="project")), ("plain", dict(method="plain")),
+                     ("learned_gate_1e-6", dict(method="learned", gate=1e-6)),
+                     ("learned_gate_1e-2", dict(method="learned", gate=1e-2)),
+                     ("learned_gate_inf", dict(method="learned", gate=1e300))):
+        if kw["method"] == "learned":
+            kw = dict(method="learned", polish_m=polish_m,
+                      learned=dict(params=net.params, scale=1.0, gate=kw["gate"]))
+        b = Batch([Group(64, s0[None], e0[:, None])], T, m, **kw)
+        if kw["method"] == "project" and not args.no_tune:
+            polish_m = b.autotune().polish_m
+        elif kw["method"] == "plain" and not args.no_tune:
+            b.autotune()
+        r = time_chain(b, args, 1, 1, not args.eager)
+        _, ti = b.all_infos()
+        legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
+                      "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                      "mean_iters": round(r["iters_mean"], 2),
+                      "median_guess_residual": float(f"{np.median(ti['guess_res']):.4g}"),
+                      "accepted": round(float((ti["guess_source"] == 2).mean()), 4),
+                      "polish_m": r["polish_m"], "verified": r["ok"] and gen_ok}
+        print(f"# learned workload {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, "
+              f"mean iters {r['iters_mean']:.1f}, accepted {legs[name]['accepted']:.3f}",
+              file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg.name, "train_targets": len(t0), "eval_targets": len(e0),
+            "timesteps": T, "m": m, "unit": "target systems/s",
+            "generate_s": round(t_gen, 2), "train_s": round(t_tr, 2),
+            "epochs": args.learned_epochs, "loss_per_epoch": [float(f"{v:.4g}") for v in hist],
+            "legs": legs}
+
+
 def time_chain(b, args, steps, warmup, graph=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
     captured graph (or enqueued eagerly), then verify every solve of the last chain."""
@@ -212,6 +274,8 @@ def main():
                     help="fixed polish restart length (implies --no-tune)")
     ap.add_argument("--uneven-steps", type=int, default=1)
     ap.add_argument("--no-mixed", action="store_true", help="skip the 128x128 mixed workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess workload")
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
                     help="comma list of the 64x64 legs to run (profiling runs take one)")
@@ -355,6 +419,10 @@ def main():
                                     "timestep, x_fp64 = the same systems re-solved by the FP64 "
                                     "path to 1e-12", **mx}
         out["verified"] = out["verified"] and all(v["verified"] for v in mx.values())
+    if not args.no_learned:
+        out["learned"] = learned_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for v in out["learned"]["legs"].values())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -18,6 +18,19 @@ from . import xkp
 from .driver import Batch, Group
 
 
+def init_params(k, rng):
+    """Initial FP32 parameters of a network with k outputs (the layout of xkp_cnn_param_count):
+    normal weights with variance 2 / fan-in, zero biases."""
+    shapes = [(16, 9), (16,), (32, 144), (32,), (64, 288), (64,), (k, 96), (k,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 1:
+            parts.append(np.zeros(s))
+        else:
+            parts.append(rng.standard_normal(s).reshape(-1) * np.sqrt(2.0 / s[1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def generate(seed_m0, target_m0, T, m, device=0):
     """Run the chain (seeds with kept bases, targets by plain GMRES to 1e-8) and collect
     zeta*[t][i] = Hbar_{t+1} V_{t+1}^T x*_{i,t+1} / beta_{t+1} (float64 device tensor
