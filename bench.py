@@ -361,7 +361,7 @@ def main():
         "projection": {"mean_polish_iters": round(legs["project"]["iters_mean"], 2),
                        "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
                        "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
-        "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu,
+        "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu, "waves": t.waves,
                          "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4)}
                      for k, t in tunings.items()},
         "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
@@ -382,7 +382,8 @@ def main():
                         "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                         "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
                         "polish_m": r["polish_m"],
-                        "wg_per_cu": None if tu is None else tu.wg_per_cu}
+                        "wg_per_cu": None if tu is None else tu.wg_per_cu,
+                        "waves": None if tu is None else tu.waves}
             print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
                   file=sys.stderr, flush=True)
             del b

@@ -140,6 +140,11 @@ xkp_status xkp_ctx_create(xkp_ctx **ctx, int device, void *hip_stream, int32_t m
                           int32_t max_m, int32_t max_batch);
 xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
 
+/* Launch shape of the context's later solve calls: workgroups of `waves` wave64s (8 or 16;
+ * 16 needs max_n <= 16384) and up to wg_per_cu workgroups per compute unit.  Results do not
+ * depend on it.  XKP_EUNSUPPORTED if no kernel variant of that size covers max_n. */
+xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
+
 /* Size in bytes of one seed basis buffer for n unknowns and restart length m. */
 size_t xkp_basis_bytes(int32_t n, int32_t m);
 
@@ -259,18 +264,19 @@ typedef struct {
     int32_t polish_m;     /* fastest restart length of the polish (for params->polish_m)    */
     int32_t wg_per_cu;    /* fastest workgroups per compute unit (now set in the context)    */
     float ms_best;        /* time of one call with the chosen values, milliseconds           */
-    float ms_default;     /* time with polish_m = m and the most workgroups per compute unit */
+    float ms_default;     /* time with polish_m = m, 8-wave workgroups, the most per CU     */
     int32_t n_tried;      /* candidates timed                                               */
-    int32_t pad;
+    int32_t waves;        /* fastest workgroup size in wave64s (now set in the context)     */
 } xkp_tuning;
 
 /*
  * Launch autotuner for target calls: times xkp_target_project_solve on the given batch (one
- * representative timestep) for each candidate restart length of the polish (m/2, 3m/4 and m,
- * at least 8) and each workgroup count per compute unit the kernels can hold (1..occupancy),
- * two timed calls each after one untimed call, and keeps the fastest candidate whose every
- * target converged.  The chosen workgroup count is stored in the context and applies to its
- * later seed and target calls; the chosen restart length is returned for the caller's params.
+ * representative timestep) for each kernel variant covering the batch (workgroups of 8 or 16
+ * wave64s), each candidate restart length of the polish (m/2, 3m/4 and m, at least 8) and each
+ * workgroup count per compute unit the kernels can hold (1..occupancy), two timed calls each
+ * after one untimed call, and keeps the fastest candidate whose every target converged.  The
+ * chosen variant and workgroup count are stored in the context and apply to its later seed and
+ * target calls; the chosen restart length is returned for the caller's params.
  * Side effects: targets[i].x and infos hold the last candidate's results.  Unlike the other
  * calls this one synchronises the stream (it reads timings and statuses back), so it must not
  * be captured in a graph.  Returns XKP_ENOCONV if no candidate converged everywhere.

@@ -21,6 +21,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libxkp.so")
 # (source, object, extra flags): the kernel file is compiled once per workgroup size
 UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIANT=v512"]),
+         ("xkp_kernels.hip", "xkp_kernels_1024.o", ["-DXKP_NT=1024", "-DXKP_VARIANT=v1024"]),
          ("xkp_common.hip", "xkp_common.o", []),
          ("xkp_cnn.hip", "xkp_cnn.o", []),
          ("xkp_api.hip", "xkp_api.o", [])]

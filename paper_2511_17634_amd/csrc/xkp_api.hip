@@ -17,6 +17,7 @@ struct xkp_ctx {
     unsigned *queue;    // work-queue counters of the solve kernels (reset by each launch)
     int cus;            // compute units of the device
     int per_cu;         // workgroups per compute unit used for the grid (autotuned)
+    int variant;        // kernel variant (workgroup size) of the solve launches (autotuned)
 };
 
 namespace {
@@ -42,13 +43,29 @@ struct Variant {
             xkp::NS::launch_rhs,                                                       \
             xkp::NS::launch_apply                                                      \
     }
-const Variant kV512 = XKP_VARIANT_TABLE(v512);
+// Kernel variants by workgroup size: 8 wave64s (2, 8 or 32 rows per thread for up to 1024, 4096,
+// 16384 unknowns) and 16 (4 or 16 rows per thread for up to 4096, 16384).  Variant 0 serves
+// every size and the single-pass kernels (residual, rhs, apply).
+const Variant kVariants[] = {XKP_VARIANT_TABLE(v512), XKP_VARIANT_TABLE(v1024)};
+constexpr int kNumVariants = 2;
 
-// Kernel variant for systems of up to nmax unknowns (512 threads: 2 rows per thread up to 1024
-// unknowns, 8 up to 4096, 32 up to 16384).
-const Variant *choose(int nmax) { return kV512.rmax_for(nmax) ? &kV512 : nullptr; }
+const Variant *choose(int nmax) { return kVariants[0].rmax_for(nmax) ? &kVariants[0] : nullptr; }
 
-int npad_for(int nmax) { return kV512.rmax_for(nmax) * kV512.threads(); }
+// The context's solve variant if it covers nmax, else variant 0.
+const Variant *choose_solve(const xkp_ctx *ctx, int nmax) {
+    const Variant &v = kVariants[ctx->variant];
+    return v.rmax_for(nmax) ? &v : choose(nmax);
+}
+
+// Rows covered by the workspace's coefficient arrays: the most any variant uses for nmax.
+int npad_for(int nmax) {
+    int best = 0;
+    for (const Variant &v : kVariants) {
+        const int r = v.rmax_for(nmax) * v.threads();
+        if (r > best) best = r;
+    }
+    return best;
+}
 
 // Shared host checks of a batched call; fills the effective n limit and kernel variant.
 xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const xkp_params *P,
@@ -60,7 +77,7 @@ xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const 
     if (P->precision != XKP_FP64 && P->precision != XKP_MIXED) return XKP_EINVAL;
     if (P->mode < XKP_PROJ_TARGET_GALERKIN || P->mode > XKP_PROJ_NONE) return XKP_EINVAL;
     *nmax = P->batch_max_n > 0 ? P->batch_max_n : ctx->max_n;
-    *var = choose(*nmax);
+    *var = choose_solve(ctx, *nmax);
     if (!*var) return XKP_EUNSUPPORTED;
     *rmax = (*var)->rmax_for(*nmax);
     return XKP_OK;
@@ -95,14 +112,20 @@ xkp_status xkp_ctx_create(xkp_ctx **out, int device, void *hip_stream, int32_t m
     c->max_batch = max_batch;
     // one workspace slot per workgroup that can be resident at once: a larger grid would only
     // add workgroups that find the work queue empty
-    const int per_cu = choose(max_n)->solve_per_cu(max_n);
-    if (per_cu < 1) {
-        delete c;
-        return XKP_EDEVICE;
+    int per_cu = 0;
+    for (const Variant &v : kVariants) {
+        if (!v.rmax_for(max_n)) continue;
+        const int p = v.solve_per_cu(max_n);
+        if (p < 1) {
+            delete c;
+            return XKP_EDEVICE;
+        }
+        if (p > per_cu) per_cu = p;
     }
     c->slots = max_batch < per_cu * cus ? max_batch : per_cu * cus;
     c->cus = cus;
-    c->per_cu = per_cu;
+    c->per_cu = choose(max_n)->solve_per_cu(max_n);
+    c->variant = 0;
     c->L = xkp::ws_layout(max_n, max_m, npad_for(max_n));
     if (hipMalloc((void **)&c->ws, sizeof(double) * c->L.stride * (size_t)c->slots) != hipSuccess) {
         delete c;
@@ -131,6 +154,19 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t q = hipFree(ctx->queue);
     delete ctx;
     return (e == hipSuccess && f == hipSuccess && q == hipSuccess) ? XKP_OK : XKP_EDEVICE;
+}
+
+xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu) {
+    if (!ctx || wg_per_cu < 1) return XKP_EINVAL;
+    for (int vi = 0; vi < kNumVariants; ++vi) {
+        if (kVariants[vi].threads() != 64 * waves) continue;
+        if (!kVariants[vi].rmax_for(ctx->max_n)) return XKP_EUNSUPPORTED;
+        if (wg_per_cu * ctx->cus > ctx->slots && wg_per_cu > 1) return XKP_EINVAL;
+        ctx->variant = vi;
+        ctx->per_cu = wg_per_cu;
+        return XKP_OK;
+    }
+    return XKP_EINVAL;
 }
 
 size_t xkp_basis_bytes(int32_t n, int32_t m) {
@@ -240,22 +276,19 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
                         int32_t n_bases, const void *const *bases, const xkp_params *params,
                         xkp_info *infos, xkp_tuning *out) {
     if (!ctx || !params || !out || n_targets < 1 || !targets || !infos) return XKP_EINVAL;
-    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    const int m = params->m;
-    int cand_m[3] = {m / 2, (3 * m) / 4, m};
-    for (int &c : cand_m) {
-        if (c < 8) c = 8;
-        if (c > m) c = m;
-    }
-    int nb = 0;
     {
         int nmax = 0, rmax = 0;
         const Variant *v = nullptr;
         xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
         if (st != XKP_OK) return st;
-        nb = v->solve_per_cu(nmax);
-        if (nb < 1) return XKP_EDEVICE;
-        if (nb * ctx->cus > ctx->slots) nb = (ctx->slots + ctx->cus - 1) / ctx->cus;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int m = params->m;
+    const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
+    int cand_m[3] = {m / 2, (3 * m) / 4, m};
+    for (int &c : cand_m) {
+        if (c < 8) c = 8;
+        if (c > m) c = m;
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
@@ -264,58 +297,74 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
         return XKP_EDEVICE;
     }
     std::vector<xkp_info> host(n_targets);
-    const int saved = ctx->per_cu;
+    const int saved_w = ctx->per_cu, saved_v = ctx->variant;
     xkp_status result = XKP_OK;
     float best = -1.f, def = -1.f;
-    int best_m = m, best_w = saved, tried = 0;
-    for (int ci = 0; ci < 3 && result == XKP_OK; ++ci) {
-        if (ci > 0 && cand_m[ci] == cand_m[ci - 1]) continue;
-        for (int w = 1; w <= nb && result == XKP_OK; ++w) {
-            xkp_params P = *params;
-            P.polish_m = cand_m[ci];
-            ctx->per_cu = w;
-            float ms = 0.f;
-            for (int rep = 0; rep < 3 && result == XKP_OK; ++rep) {
-                if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess) result = XKP_EDEVICE;
-                xkp_status st = xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
-                                                         &P, infos);
-                if (st != XKP_OK) result = st;
-            }
-            if (result != XKP_OK) break;
-            if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
-                hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
-                hipMemcpy(host.data(), infos, sizeof(xkp_info) * n_targets,
-                          hipMemcpyDeviceToHost) != hipSuccess) {
-                result = XKP_EDEVICE;
-                break;
-            }
-            ms *= 0.5f;
-            ++tried;
-            bool ok = true;
-            for (const xkp_info &i : host) ok = ok && (i.status == XKP_OK || i.status == XKP_ESINGULAR);
-            if (cand_m[ci] == m && w == nb) def = ms;
-            if (ok && (best < 0.f || ms < best)) {
-                best = ms;
-                best_m = cand_m[ci];
-                best_w = w;
+    int best_m = m, best_w = saved_w, best_v = saved_v, tried = 0;
+    for (int vi = 0; vi < kNumVariants && result == XKP_OK; ++vi) {
+        const Variant &var = kVariants[vi];
+        if (!var.rmax_for(nmax)) continue;
+        int nb = var.solve_per_cu(nmax);
+        if (nb < 1) {
+            result = XKP_EDEVICE;
+            break;
+        }
+        if (nb * ctx->cus > ctx->slots) nb = (ctx->slots + ctx->cus - 1) / ctx->cus;
+        ctx->variant = vi;
+        for (int ci = 0; ci < 3 && result == XKP_OK; ++ci) {
+            if (ci > 0 && cand_m[ci] == cand_m[ci - 1]) continue;
+            for (int w = 1; w <= nb && result == XKP_OK; ++w) {
+                xkp_params P = *params;
+                P.polish_m = cand_m[ci];
+                ctx->per_cu = w;
+                float ms = 0.f;
+                for (int rep = 0; rep < 3 && result == XKP_OK; ++rep) {
+                    if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess)
+                        result = XKP_EDEVICE;
+                    xkp_status st = xkp_target_project_solve(ctx, n_targets, targets, n_bases,
+                                                             bases, &P, infos);
+                    if (st != XKP_OK) result = st;
+                }
+                if (result != XKP_OK) break;
+                if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+                    hipMemcpy(host.data(), infos, sizeof(xkp_info) * n_targets,
+                              hipMemcpyDeviceToHost) != hipSuccess) {
+                    result = XKP_EDEVICE;
+                    break;
+                }
+                ms *= 0.5f;
+                ++tried;
+                bool ok = true;
+                for (const xkp_info &i : host)
+                    ok = ok && (i.status == XKP_OK || i.status == XKP_ESINGULAR);
+                if (vi == 0 && cand_m[ci] == m && w == nb) def = ms;
+                if (ok && (best < 0.f || ms < best)) {
+                    best = ms;
+                    best_m = cand_m[ci];
+                    best_w = w;
+                    best_v = vi;
+                }
             }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (result != XKP_OK) {
-        ctx->per_cu = saved;
-        return result;
+    if (result != XKP_OK || best < 0.f) {
+        ctx->per_cu = saved_w;
+        ctx->variant = saved_v;
+        return result != XKP_OK ? result : XKP_ENOCONV;
     }
     out->polish_m = best_m;
     out->wg_per_cu = best_w;
     out->ms_best = best;
     out->ms_default = def;
     out->n_tried = tried;
-    out->pad = 0;
-    ctx->per_cu = best < 0.f ? saved : best_w;
-    return best < 0.f ? XKP_ENOCONV : XKP_OK;
+    out->waves = kVariants[best_v].threads() / 64;
+    ctx->per_cu = best_w;
+    ctx->variant = best_v;
+    return XKP_OK;
 }
 
 size_t xkp_cnn_param_count(int32_t k) {

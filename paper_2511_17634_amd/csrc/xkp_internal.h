@@ -71,6 +71,7 @@ struct Learned {
     }
 
 XKP_DECLARE_VARIANT(v512)
+XKP_DECLARE_VARIANT(v1024)
 
 // The learned-guess network (xkp_cnn.hip).
 namespace cnn {

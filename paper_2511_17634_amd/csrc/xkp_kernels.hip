@@ -34,6 +34,9 @@ namespace xkp {
 namespace XKP_VARIANT {
 
 constexpr int kLdA = 81;   // leading dimension of the projected matrix in LDS (<= 80 columns)
+// Column tiles of V^T W per matrix-core pass: two at 8 waves, one at 16 waves (128 registers per
+// lane leave no room for a second set of accumulators).
+constexpr int kNtcMax = kNT >= 1024 ? 1 : 2;
 // Mixed precision: a GMRES cycle with the FP32 operator stops once its residual estimate has
 // dropped by this factor (about 170 FP32 unit roundoffs, the attainable reduction for operators
 // of condition number up to a few hundred); the FP64 true residual then restarts it.
@@ -961,17 +964,23 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 const int ktr = (k + 15) / 16;
                 const rsrc_t rV = mkbuf16(Vb, ldv * k), rW = mkbuf16(Wb, ldv * k);
                 double *tred = Ap + (kMMax + 1) * kLdA;
-                for (int tc0 = 0; tc0 < ktr; tc0 += 2) {
-                    const int ntc = ktr - tc0 < 2 ? ktr - tc0 : 2;
+                for (int tc0 = 0; tc0 < ktr; tc0 += kNtcMax) {
+                    const int ntc = ktr - tc0 < kNtcMax ? ktr - tc0 : kNtcMax;
 #define XKP_VTWB(R_, C_) vtw_bf16<R_, C_>(rV, rW, n, ldv, k, tc0, Ap, tred)
                     switch (ktr * 2 + ntc - 1) {
                     case 2: XKP_VTWB(1, 1); break;
                     case 4: XKP_VTWB(2, 1); break;
-                    case 5: XKP_VTWB(2, 2); break;
                     case 6: XKP_VTWB(3, 1); break;
-                    case 7: XKP_VTWB(3, 2); break;
                     case 8: XKP_VTWB(4, 1); break;
-                    default: XKP_VTWB(4, 2); break;
+                    default:
+                        if constexpr (kNtcMax > 1) {
+                            if (ntc == 2) {
+                                if (ktr == 2) XKP_VTWB(2, 2);
+                                else if (ktr == 3) XKP_VTWB(3, 2);
+                                else XKP_VTWB(4, 2);
+                            }
+                        }
+                        break;
                     }
 #undef XKP_VTWB
                 }
@@ -986,9 +995,11 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 // and, for the neighbours, through one of two zero-padded LDS copies.
                 // (with 32 rows per thread the coefficients are re-read from the workspace
                 // instead: four register arrays of 32 would not fit)
-                constexpr int RC = RMAX >= 32 ? 1 : RMAX;
+                // (so do 16-wave variants: 128 registers per lane)
+                constexpr bool kRegC = RMAX < 32 && kNT < 1024;
+                constexpr int RC = kRegC ? RMAX : 1;
                 double cEr[RC], cWr[RC], cNr[RC], cSr[RC];
-                if constexpr (RMAX < 32) {
+                if constexpr (kRegC) {
                     const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
                     const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
 #pragma unroll
@@ -1008,7 +1019,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                     store_rows_lds<RMAX>(vb, col);
                     lds_barrier();
                     double y[RMAX];
-                    if constexpr (RMAX < 32) {
+                    if constexpr (kRegC) {
 #pragma unroll
                         for (int q = 0; q < RMAX; ++q) {
                             const double *u = vb + threadIdx.x + q * kNT;
@@ -1026,18 +1037,24 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 const int ktr = (k + 15) / 16, ktc = (k + 16) / 16;
                 const rsrc_t rV = mkbuf(V, ldv * (k + 1)), rW = mkbuf(W, ldv * (k + 1));
                 double *tred = Ap + (kMMax + 1) * kLdA;   // kNW x 256 partial tile
-                for (int tc0 = 0; tc0 < ktc; tc0 += 2) {
-                    const int ntc = ktc - tc0 < 2 ? ktc - tc0 : 2;
+                for (int tc0 = 0; tc0 < ktc; tc0 += kNtcMax) {
+                    const int ntc = ktc - tc0 < kNtcMax ? ktc - tc0 : kNtcMax;
 #define XKP_VTW(R_, C_) vtw_chunk<R_, C_>(rV, rW, n, ldv, k, tc0, Ap, tred)
                     switch (ktr * 2 + ntc - 1) {
                     case 2: XKP_VTW(1, 1); break;
-                    case 3: XKP_VTW(1, 2); break;
                     case 4: XKP_VTW(2, 1); break;
-                    case 5: XKP_VTW(2, 2); break;
                     case 6: XKP_VTW(3, 1); break;
-                    case 7: XKP_VTW(3, 2); break;
                     case 8: XKP_VTW(4, 1); break;
-                    default: XKP_VTW(4, 2); break;
+                    default:
+                        if constexpr (kNtcMax > 1) {
+                            if (ntc == 2) {
+                                if (ktr == 1) XKP_VTW(1, 2);
+                                else if (ktr == 2) XKP_VTW(2, 2);
+                                else if (ktr == 3) XKP_VTW(3, 2);
+                                else XKP_VTW(4, 2);
+                            }
+                        }
+                        break;
                     }
 #undef XKP_VTW
                 }

@@ -39,7 +39,7 @@ class Params(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("polish_m", ct.c_int32), ("wg_per_cu", ct.c_int32), ("ms_best", ct.c_float),
-                ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("pad", ct.c_int32)]
+                ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("waves", ct.c_int32)]
 
 
 class XkpError(RuntimeError):
@@ -65,6 +65,7 @@ def load():
         lib.xkp_ctx_create.argtypes = [ct.POINTER(P), ct.c_int, P, ct.c_int32, ct.c_int32,
                                        ct.c_int32]
         lib.xkp_ctx_destroy.argtypes = [P]
+        lib.xkp_ctx_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
         lib.xkp_basis_bytes.argtypes = [ct.c_int32, ct.c_int32]
         lib.xkp_basis_bytes.restype = ct.c_size_t
         lib.xkp_seed_build.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P]
@@ -93,7 +94,7 @@ def load():
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
                   "xkp_autotune", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
-                  "xkp_learned_solve", "xkp_basis_coeffs"):
+                  "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -183,6 +184,10 @@ class Context:
                                   max_n, max_m, max_batch), "xkp_ctx_create")
         self._h = h
         self.max_n, self.max_m, self.max_batch = max_n, max_m, max_batch
+
+    def set_launch(self, waves, wg_per_cu=1):
+        """Workgroup size (8 or 16 wave64s) and workgroups per compute unit of later solves."""
+        _check(load().xkp_ctx_set_launch(self._h, waves, wg_per_cu), "xkp_ctx_set_launch")
 
     def close(self):
         if getattr(self, "_h", None):
