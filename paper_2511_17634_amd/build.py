@@ -44,14 +44,17 @@ def _run(cmd, verbose):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OUT, exist_ok=True)
+def build(verbose: bool = False, out_lib: str = LIB, build_dir: str = OUT,
+          extra_flags=()) -> str:
+    """Compile every unit and link `out_lib`.  extra_flags (e.g. -D tuning macros) are added to
+    every hipcc line."""
+    os.makedirs(build_dir, exist_ok=True)
     hipcc = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
     objs = []
     procs = []
     for src, objname, extra in UNITS:
-        obj = os.path.join(OUT, objname)
-        cmd = [hipcc, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+        obj = os.path.join(build_dir, objname)
+        cmd = [hipcc, *FLAGS, *extra, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -70,7 +73,7 @@ def build(verbose: bool = False) -> str:
             name = line.split()[-1]
             if re.match(r"^(__)?hip", name):
                 undef.add(name)
-    stubdir = os.path.join(OUT, "linkstub")
+    stubdir = os.path.join(build_dir, "linkstub")
     os.makedirs(stubdir, exist_ok=True)
     stub_c = os.path.join(stubdir, "stub.c")
     with open(stub_c, "w") as f:
@@ -79,15 +82,15 @@ def build(verbose: bool = False) -> str:
             f.write(f"void {name}(void) {{}}\n")
     _run(["gcc", "-shared", "-fPIC", "-o", os.path.join(stubdir, "libamdhip64.so"), stub_c],
          verbose)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out_lib + ".tmp%d" % os.getpid()
     rocm_lib = os.path.realpath(os.path.join(ROCM, "lib"))
     _run(["g++", "-shared", "-o", tmp, *objs, "-L" + stubdir, "-lamdhip64",
           "-Wl,-rpath," + rocm_lib, "-Wl,--no-undefined"], verbose)
     needed = _run(["readelf", "-d", tmp], False)
     if "[libamdhip64.so]" not in needed:
         raise RuntimeError("libxkp.so does not depend on the unversioned HIP runtime name")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":

@@ -23,6 +23,9 @@
 #ifndef XKP_DEPTH4
 #define XKP_DEPTH4 4
 #endif
+#ifndef XKP_DEPTH8
+#define XKP_DEPTH8 2
+#endif
 #ifndef XKP_DEPTH16
 #define XKP_DEPTH16 1
 #endif
@@ -184,7 +187,7 @@ __device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int n, 
 template <int R> struct Depth { static constexpr int value = 2; };
 template <> struct Depth<2> { static constexpr int value = 8; };
 template <> struct Depth<4> { static constexpr int value = XKP_DEPTH4; };
-template <> struct Depth<8> { static constexpr int value = 3; };
+template <> struct Depth<8> { static constexpr int value = XKP_DEPTH8; };
 template <> struct Depth<16> { static constexpr int value = XKP_DEPTH16; };
 template <> struct Depth<32> { static constexpr int value = XKP_DEPTH32; };
 

@@ -13,7 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libxkp.so")
+# XKP_LIB selects another build of the library (e.g. one compiled with other tuning macros)
+LIB_PATH = os.environ.get("XKP_LIB") or os.path.join(HERE, "libxkp.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, EUNSUPPORTED = range(7)
 FP64, MIXED = 0, 1
