@@ -139,6 +139,63 @@ def err_vs_fp64(b, tol=1e-12):
     return np.array(errs), ok
 
 
+def uneven_leg(args):
+    """Uneven batch: 32x32 / 64x64 / 128x128 x 3 channels, one launch per timestep."""
+    from paper_2511_17634_amd.driver import Batch
+    graph = not args.eager
+    cfg4, groups = build_c4()
+    un = {}
+    for name, method in (("project", "project"), ("plain", "plain")):
+        b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin")
+        tu = None if args.no_tune else b.autotune()
+        r = time_chain(b, args, args.uneven_steps, 1, graph)
+        un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
+                    "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                    "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
+                    "polish_m": r["polish_m"],
+                    "wg_per_cu": None if tu is None else tu.wg_per_cu,
+                    "waves": None if tu is None else tu.waves}
+        print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
+              file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg4.name, "targets": sum(g.N * g.C for g in groups),
+            "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": cfg4.m,
+            "unit": "target systems/s", **un}
+
+
+def mixed_leg(args):
+    """128x128, 1 seed + 255 targets, m = 60, mixed and FP64 precision."""
+    from paper_2511_17634_amd import xkp
+    from paper_2511_17634_amd.driver import Chain
+    graph = not args.eager
+    cfg3, s3, t3 = build_c3()
+    H3 = cfg3.groups[0].H
+    mx = {}
+    for name, method, prec in (("project_mixed", "project", xkp.MIXED),
+                               ("project_fp64", "project", xkp.FP64),
+                               ("plain_mixed", "plain", xkp.MIXED),
+                               ("plain_fp64", "plain", xkp.FP64)):
+        b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec)
+        tu = None if args.no_tune else b.autotune()
+        r = time_chain(b, args, args.mixed_steps, 1, graph)
+        e, eok = err_vs_fp64(b)
+        mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
+                    "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                    "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"] and eok,
+                    "polish_m": r["polish_m"],
+                    "mean_guess_residual": round(r["guess_res_mean"], 4),
+                    "err_vs_fp64_max": float(f"{e.max():.3e}"),
+                    "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
+        print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
+              f"mean iters {r['iters_mean']:.1f}, max err vs fp64 {e.max():.2e}",
+              file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg3.name, "targets": len(t3), "seeds": 1,
+            "timesteps": cfg3.T, "m": cfg3.m, "unit": "target systems/s",
+            "err_note": "per-target max |x - x_fp64| / max |x_fp64| at the last timestep, "
+                        "x_fp64 = the same systems re-solved by the FP64 path to 1e-12", **mx}
+
+
 def learned_leg(args):
     """64x64 learned-guess workload: training data from the method's own chain (seed + 4096
     targets x 100 timesteps), training on the GPU, then 1024 held-out targets solved by plain
@@ -276,6 +333,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 128x128 mixed workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess workload")
     ap.add_argument("--learned-epochs", type=int, default=4)
+    ap.add_argument("--only", choices=("uneven", "mixed", "learned"),
+                    help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
                     help="comma list of the 64x64 legs to run (profiling runs take one)")
@@ -293,6 +352,10 @@ def main():
     from paper_2511_17634_amd.driver import Batch, Chain
 
     xkp.load()
+    if args.only:
+        rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg}[args.only](args)
+        print(json.dumps(rec), flush=True)
+        return
     cfg, s0, t0 = build_c2()
     H, T, m = cfg.groups[0].H, cfg.T, cfg.m
     n = H * H
@@ -372,54 +435,13 @@ def main():
     }
     del plain_chain
     if not args.no_uneven:
-        cfg4, groups = build_c4()
-        un = {}
-        for name, method in (("project", "project"), ("plain", "plain")):
-            b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin")
-            tu = None if args.no_tune else b.autotune()
-            r = time_chain(b, args, args.uneven_steps, 1, graph)
-            un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
-                        "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
-                        "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
-                        "polish_m": r["polish_m"],
-                        "wg_per_cu": None if tu is None else tu.wg_per_cu,
-                        "waves": None if tu is None else tu.waves}
-            print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
-                  file=sys.stderr, flush=True)
-            del b
-        out["uneven"] = {"workload": cfg4.name, "targets": sum(g.N * g.C for g in groups),
-                         "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": cfg4.m,
-                         "unit": "target systems/s", **un}
-        out["verified"] = out["verified"] and all(v["verified"] for v in un.values())
+        out["uneven"] = uneven_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for k, v in out["uneven"].items() if k in ("project", "plain"))
     if not args.no_mixed:
-        cfg3, s3, t3 = build_c3()
-        H3 = cfg3.groups[0].H
-        mx = {}
-        for name, method, prec in (("project_mixed", "project", xkp.MIXED),
-                                   ("project_fp64", "project", xkp.FP64),
-                                   ("plain_mixed", "plain", xkp.MIXED),
-                                   ("plain_fp64", "plain", xkp.FP64)):
-            b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec)
-            tu = None if args.no_tune else b.autotune()
-            r = time_chain(b, args, args.mixed_steps, 1, graph)
-            e, eok = err_vs_fp64(b)
-            mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
-                        "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
-                        "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"] and eok,
-                        "polish_m": r["polish_m"],
-                        "mean_guess_residual": round(r["guess_res_mean"], 4),
-                        "err_vs_fp64_max": float(f"{e.max():.3e}"),
-                        "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
-            print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
-                  f"mean iters {r['iters_mean']:.1f}, max err vs fp64 {e.max():.2e}",
-                  file=sys.stderr, flush=True)
-            del b
-        out["mixed"] = {"workload": cfg3.name, "targets": len(t3), "seeds": 1,
-                        "timesteps": cfg3.T, "m": cfg3.m, "unit": "target systems/s",
-                        "err_note": "per-target max |x - x_fp64| / max |x_fp64| at the last "
-                                    "timestep, x_fp64 = the same systems re-solved by the FP64 "
-                                    "path to 1e-12", **mx}
-        out["verified"] = out["verified"] and all(v["verified"] for v in mx.values())
+        out["mixed"] = mixed_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for v in out["mixed"].values() if isinstance(v, dict))
     if not args.no_learned:
         out["learned"] = learned_leg(args)
         out["verified"] = out["verified"] and all(

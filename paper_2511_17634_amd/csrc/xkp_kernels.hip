@@ -26,6 +26,9 @@
 #ifndef XKP_DEPTH8
 #define XKP_DEPTH8 2
 #endif
+#ifndef XKP_STENCIL_GROUP
+#define XKP_STENCIL_GROUP 2
+#endif
 #ifndef XKP_DEPTH16
 #define XKP_DEPTH16 1
 #endif
@@ -262,7 +265,8 @@ __device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, cons
                + bld(bN, lo, so) * q[1] + bld(bS, lo, so) * q[-1];
         // bound the scheduling region: issuing every row's loads at once needs more registers
         // than the kernel has while the basis prefetch is in flight
-        if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        if (XKP_STENCIL_GROUP > 0 && k % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
+            __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -285,7 +289,8 @@ __device__ __forceinline__ void stencil_lds_f32(const double *u, const Coef &C, 
                         + bldf(bW, lo, so) * (float)q[-H] + bldf(bN, lo, so) * (float)q[1]
                         + bldf(bS, lo, so) * (float)q[-1];
         w[k] = (double)y;
-        if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        if (XKP_STENCIL_GROUP > 0 && k % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
+            __builtin_amdgcn_sched_barrier(0);
     }
 }
 
