@@ -140,8 +140,9 @@ xkp_status xkp_ctx_create(xkp_ctx **ctx, int device, void *hip_stream, int32_t m
                           int32_t max_m, int32_t max_batch);
 xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
 
-/* Launch shape of the context's later solve calls: workgroups of `waves` wave64s (8 or 16;
- * 16 needs max_n <= 16384) and up to wg_per_cu workgroups per compute unit.  Results do not
+/* Launch shape of the context's later solve calls: workgroups of `waves` wave64s (8, 16 or 4;
+ * 16 needs max_n <= 16384, 4 needs max_n <= 4096) and up to wg_per_cu workgroups per compute
+ * unit.  Results do not
  * depend on it.  XKP_EUNSUPPORTED if no kernel variant of that size covers max_n. */
 xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
 
@@ -271,7 +272,7 @@ typedef struct {
 
 /*
  * Launch autotuner for target calls: times xkp_target_project_solve on the given batch (one
- * representative timestep) for each kernel variant covering the batch (workgroups of 8 or 16
+ * representative timestep) for each kernel variant covering the batch (workgroups of 8, 16 or 4
  * wave64s), each candidate restart length of the polish (m/2, 3m/4 and m, at least 8) and each
  * workgroup count per compute unit the kernels can hold (1..occupancy), two timed calls each
  * after one untimed call, and keeps the fastest candidate whose every target converged.  The

@@ -22,6 +22,8 @@ LIB = os.path.join(HERE, "libxkp.so")
 # (source, object, extra flags): the kernel file is compiled once per workgroup size
 UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIANT=v512"]),
          ("xkp_kernels.hip", "xkp_kernels_1024.o", ["-DXKP_NT=1024", "-DXKP_VARIANT=v1024"]),
+         ("xkp_kernels.hip", "xkp_kernels_256.o", ["-DXKP_NT=256", "-DXKP_VARIANT=v256",
+                                                   "-DXKP_DEPTH16=2"]),
          ("xkp_common.hip", "xkp_common.o", []),
          ("xkp_cnn.hip", "xkp_cnn.o", []),
          ("xkp_api.hip", "xkp_api.o", [])]
@@ -45,17 +47,17 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False, out_lib: str = LIB, build_dir: str = OUT,
-          extra_flags=()) -> str:
-    """Compile every unit and link `out_lib`.  extra_flags (e.g. -D tuning macros) are added to
-    every hipcc line."""
+          extra_flags=(), csrc: str = CSRC) -> str:
+    """Compile every unit (sources from `csrc`) and link `out_lib`.  extra_flags (e.g. -D tuning
+    macros) are added to every hipcc line."""
     os.makedirs(build_dir, exist_ok=True)
     hipcc = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
     objs = []
     procs = []
     for src, objname, extra in UNITS:
         obj = os.path.join(build_dir, objname)
-        cmd = [hipcc, *FLAGS, *extra, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *FLAGS, *extra, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I",
+               csrc, "-c", os.path.join(csrc, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,

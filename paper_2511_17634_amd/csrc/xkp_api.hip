@@ -44,10 +44,12 @@ struct Variant {
             xkp::NS::launch_apply                                                      \
     }
 // Kernel variants by workgroup size: 8 wave64s (2, 8 or 32 rows per thread for up to 1024, 4096,
-// 16384 unknowns) and 16 (4 or 16 rows per thread for up to 4096, 16384).  Variant 0 serves
-// every size and the single-pass kernels (residual, rhs, apply).
-const Variant kVariants[] = {XKP_VARIANT_TABLE(v512), XKP_VARIANT_TABLE(v1024)};
-constexpr int kNumVariants = 2;
+// 16384 unknowns), 16 (4 or 16 rows per thread for up to 4096, 16384) and 4 (4 or 16 rows per
+// thread for up to 1024, 4096).  Variant 0 serves every size and the single-pass kernels
+// (residual, rhs, apply).
+const Variant kVariants[] = {XKP_VARIANT_TABLE(v512), XKP_VARIANT_TABLE(v1024),
+                             XKP_VARIANT_TABLE(v256)};
+constexpr int kNumVariants = 3;
 
 const Variant *choose(int nmax) { return kVariants[0].rmax_for(nmax) ? &kVariants[0] : nullptr; }
 

@@ -37,11 +37,13 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// Lane permutation of a double by a DPP control; every control used here reads a valid source
+// lane for every lane, so the destination needs no initial value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
@@ -72,6 +74,16 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Workgroup reductions.  `red` is LDS of 2 * kRedSlots * kNW doubles; `par` alternates the half
 // used so that one barrier per reduction suffices.
+// Sum of p[0..N) as a balanced tree (fixed order, short dependency chain), N a power of two.
+template <int N>
+__device__ __forceinline__ double tree_sum(const double *p) {
+    if constexpr (N == 1) {
+        return p[0];
+    } else {
+        return tree_sum<N / 2>(p) + tree_sum<N / 2>(p + N / 2);
+    }
+}
+
 struct BlockRed {
     double *red;
     int par;
@@ -80,9 +92,7 @@ struct BlockRed {
         double *slot = red + par * (kRedSlots * kNW);
         if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = s;
         lds_barrier();
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < kNW; ++w) t += slot[w];
+        const double t = tree_sum<kNW>(slot);
         par ^= 1;
         return t;
     }
@@ -97,12 +107,7 @@ struct BlockRed {
         }
         lds_barrier();
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < kNW; ++w) t += slot[q * kNW + w];
-            v[q] = t;
-        }
+        for (int q = 0; q < NV; ++q) v[q] = tree_sum<kNW>(slot + q * kNW);
         par ^= 1;
     }
 };

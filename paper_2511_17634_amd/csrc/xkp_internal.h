@@ -72,6 +72,7 @@ struct Learned {
 
 XKP_DECLARE_VARIANT(v512)
 XKP_DECLARE_VARIANT(v1024)
+XKP_DECLARE_VARIANT(v256)
 
 // The learned-guess network (xkp_cnn.hip).
 namespace cnn {

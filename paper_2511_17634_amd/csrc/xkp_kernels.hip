@@ -127,10 +127,14 @@ __device__ __forceinline__ void store_rows(double *__restrict__ v, int n, const 
 
 template <int RMAX>
 __device__ __forceinline__ double dot_rows(const double (&a)[RMAX], const double (&b)[RMAX]) {
-    double s = 0.0;
+    // two interleaved partial sums halve the dependent FMA chain
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) s += a[k] * b[k];
-    return s;
+    for (int k = 0; k < RMAX; k += 2) {
+        s0 += a[k] * b[k];
+        if (k + 1 < RMAX) s1 += a[k + 1] * b[k + 1];
+    }
+    return s0 + s1;
 }
 
 // Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), each loaded by the rows'

@@ -1,7 +1,8 @@
-"""The 16-wave kernel variant (1024-thread workgroups, 4 or 16 rows per thread) against the
-8-wave variant and the oracle: seeds of six sizes in one launch, projections in every mode,
-project + polish, mixed precision.  Both variants sum in different orders, so they agree to
-rounding, not bitwise."""
+"""The 16-wave (1024-thread workgroups, 4 or 16 rows per thread, n <= 16384) and 4-wave
+(256-thread, 4 or 16 rows per thread, n <= 4096) kernel variants against the 8-wave variant and
+the oracle: seeds of several sizes in one launch, projections in every mode, project + polish,
+mixed precision.  The variants sum in different orders, so they agree to rounding, not
+bitwise."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,7 @@ import oracle
 from gpu_util import blob_pair, cpu, dev, t64
 
 pytestmark = pytest.mark.gpu
-SIZES = [128, 100, 64, 45, 32, 20]
+SIZES_BY_WAVES = {16: [128, 100, 64, 45, 32, 20], 4: [64, 45, 32, 20]}
 
 
 @pytest.fixture(scope="module")
@@ -24,29 +25,32 @@ def zeros(n):
     return torch.zeros(n, dtype=torch.float64, device=dev())
 
 
-def seeds(X, waves, m=30, T=100, precision=0):
+def seeds(X, waves, m=30, T=100, precision=0, sizes=None):
     import torch
+    sizes = sizes or SIZES_BY_WAVES[waves]
     specs, mss = [], []
-    for H in SIZES:
+    for H in sizes:
         ms, _ = blob_pair(H, seed=1000 + H)
         mss.append(ms)
         specs.append(X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=zeros(H * H), x=zeros(H * H)))
-    ctx = X.Context(128 * 128, m, len(specs))
+    ctx = X.Context(max(sizes) ** 2, m, len(specs))
     ctx.set_launch(waves)
     d = X.pack_systems(specs, dev())
     ctx.build_rhs(d, len(specs))
-    bases = X.Bases(len(specs), [H * H for H in SIZES], m)
+    bases = X.Bases(len(specs), [H * H for H in sizes], m)
     info = ctx.new_infos(len(specs))
     ctx.seed_build(d, len(specs), bases.ptrs, X.Context.params(m, precision=precision), info)
     torch.cuda.synchronize()
     return ctx, bases, [cpu(s.x) for s in specs], X.infos_to_numpy(info), mss
 
 
+@pytest.mark.parametrize("waves", [16, 4])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_seeds_16_waves_match_8_waves_and_oracle(X, precision):
-    _, b16, x16, i16, mss = seeds(X, 16, precision=precision)
-    _, b8, x8, i8, _ = seeds(X, 8, precision=precision)
-    for i, H in enumerate(SIZES):
+def test_seeds_match_8_waves_and_oracle(X, waves, precision):
+    sizes = SIZES_BY_WAVES[waves]
+    _, b16, x16, i16, mss = seeds(X, waves, precision=precision)
+    _, b8, x8, i8, _ = seeds(X, 8, precision=precision, sizes=sizes)
+    for i, H in enumerate(sizes):
         A = oracle.Operator(H, 0.01, 0.5, mss[i])
         bo = oracle.rhs(A, mss[i])
         assert i16[i]["status"] == X.OK and oracle.residual(A, bo, x16[i]) <= 1e-8
@@ -57,14 +61,16 @@ def test_seeds_16_waves_match_8_waves_and_oracle(X, precision):
         assert k >= 1
 
 
+@pytest.mark.parametrize("waves", [16, 4])
 @pytest.mark.parametrize("mode", ["target_galerkin", "seed_galerkin", "seed_lsq"])
-def test_projection_16_waves_matches_oracle(X, mode):
-    """Targets of every size projected on the 16-wave seeds' bases (guess only) vs the oracle's
+def test_projection_matches_oracle(X, waves, mode):
+    """Targets of every size projected on the seeds' bases (guess only) vs the oracle's
     projection on the same bases, then polished."""
     import torch
-    ctx, bases, _, _, mss = seeds(X, 16)
+    sizes = SIZES_BY_WAVES[waves]
+    ctx, bases, _, _, mss = seeds(X, waves)
     specs, mts = [], []
-    for i, H in enumerate(SIZES):
+    for i, H in enumerate(sizes):
         _, mt = blob_pair(H, seed=1000 + H, jitter=1.5)
         mts.append(mt)
         specs.append(X.SystemSpec(H, 0.01, 0.5, t64(mt), b=zeros(H * H), x=zeros(H * H),
@@ -72,23 +78,23 @@ def test_projection_16_waves_matches_oracle(X, mode):
     d = X.pack_systems(specs, dev())
     ctx.build_rhs(d, len(specs))
     info = ctx.new_infos(len(specs))
-    ctx.target_project_solve(d, len(specs), len(SIZES), bases.ptrs,
+    ctx.target_project_solve(d, len(specs), len(sizes), bases.ptrs,
                              X.Context.params(30, tol=1e300, mode=mode), info)
     torch.cuda.synchronize()
     mid = {"target_galerkin": oracle.TARGET_GALERKIN, "seed_galerkin": oracle.SEED_GALERKIN,
            "seed_lsq": oracle.SEED_LSQ}[mode]
-    for i, H in enumerate(SIZES):
+    for i, H in enumerate(sizes):
         At = oracle.Operator(H, 0.01, 0.5, mts[i])
         bt = oracle.rhs(At, mts[i])
         k = bases.header(i)["k"]
         x0o, _, _ = oracle.project(At, bt, cpu(bases.V(i))[:, :k + 1],
                                    cpu(bases.Hbar(i))[:k + 1, :k], mode=mid)
         assert np.abs(cpu(specs[i].x) - x0o).max() <= 1e-9 * np.abs(x0o).max(), H
-    ctx.target_project_solve(d, len(specs), len(SIZES), bases.ptrs,
+    ctx.target_project_solve(d, len(specs), len(sizes), bases.ptrs,
                              X.Context.params(30, mode=mode), info)
     torch.cuda.synchronize()
     inf = X.infos_to_numpy(info)
-    for i, H in enumerate(SIZES):
+    for i, H in enumerate(sizes):
         At = oracle.Operator(H, 0.01, 0.5, mts[i])
         assert inf[i]["status"] == X.OK
         assert oracle.residual(At, oracle.rhs(At, mts[i]), cpu(specs[i].x)) <= 1e-8
