@@ -28,15 +28,16 @@
  *   - A context is used from one host thread at a time.  Calls on one context run in stream
  *     order; they share the context's workspace, so two contexts are needed for overlap.
  *   - All solver arithmetic is FP64 in XKP_FP64 mode.  In XKP_MIXED mode the operator inside
- *     the GMRES cycles is applied in FP32 (FP32 coefficients, operands rounded to FP32, FP32
- *     row sums); the Krylov vectors are still orthogonalised, rotated and updated in FP64, every
- *     restart recomputes the true residual b - A x with the FP64 operator, and convergence is
- *     judged on it, so results meet params->tol in FP64.  A cycle ends early once its residual
- *     estimate has fallen by 1e-5 (the reduction the FP32 operator can deliver; a seed's kept
- *     first cycle is exempt).  Seeds also write a BF16 copy of the kept basis, and the
- *     target-Galerkin projection forms A'V_k with the FP32 operator, rounds it to BF16 and
- *     contracts V_k^T (A'V_k) on BF16 matrix cores with FP32 accumulation; V_k^T r_base, the
- *     k x k solve and x0 = x_base + V_k alpha stay FP64.
+ *     the targets' GMRES cycles is applied in FP32 (FP32 coefficients, operands rounded to FP32,
+ *     FP32 row sums); the Krylov vectors are still orthogonalised, rotated and updated in FP64,
+ *     every restart recomputes the true residual b - A x with the FP64 operator, and
+ *     convergence is judged on it, so results meet params->tol in FP64.  A cycle ends early
+ *     once its residual estimate has fallen by 1e-5 (the reduction the FP32 operator can
+ *     deliver).  Seeds keep the FP64 operator (a seed is one system per timestep on the
+ *     chain's critical path, where the cycle limit would cost it restarts) and write a BF16
+ *     copy of the kept basis; the target-Galerkin projection forms A'V_k with the FP32
+ *     operator, rounds it to BF16 and contracts V_k^T (A'V_k) on BF16 matrix cores with FP32
+ *     accumulation; V_k^T r_base, the k x k solve and x0 = x_base + V_k alpha stay FP64.
  */
 #ifndef XKP_H
 #define XKP_H
@@ -167,7 +168,7 @@ size_t xkp_basis_bytes(int32_t n, int32_t m);
  * cycle's basis V, Hessenberg matrix and header into the buffer bases[i].
  *   seeds: device array of n_seeds descriptors; bases: device array of n_seeds device
  *   pointers to buffers of xkp_basis_bytes(n, params->m); infos: device array of n_seeds.
- * In XKP_MIXED mode a BF16 copy of V is also written.
+ * In XKP_MIXED mode a BF16 copy of V is also written (the seed itself is solved in FP64).
  */
 xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds,
                           void *const *bases, const xkp_params *params, xkp_info *infos);

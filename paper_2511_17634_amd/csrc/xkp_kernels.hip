@@ -400,8 +400,10 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
     BlockRed br{L.red, 0};
     // mixed precision: FP32 operator inside the Krylov cycles, FP64 everywhere else
     constexpr bool mixed = MIXED;
-    unsigned short *Vb = (keep && mixed) ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
-                                         : nullptr;
+    // a mixed-precision seed (solved with the FP64 operator) also writes the BF16 basis copy
+    unsigned short *Vb = (keep && P.precision == XKP_MIXED)
+                             ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
+                             : nullptr;
 
     build_coeffs<RMAX>(s, o, C, mixed);
     if (keep) {
@@ -598,7 +600,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
             hdr->status = status;
             hdr->beta = beta_first;
             hdr->ldv = ldv;
-            hdr->bf16 = mixed ? 1 : 0;
+            hdr->bf16 = Vb ? 1 : 0;
         }
         int st = status;
         if (st == XKP_OK && (flags & kTarget) && prestatus == XKP_ESINGULAR) st = XKP_ESINGULAR;
@@ -1334,7 +1336,9 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         Vfirst = (double *)((char *)keep_base + 256);
         Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
     }
-    if (P.precision == XKP_MIXED)
+    // seeds keep the FP64 operator in mixed precision: one system per timestep on the chain's
+    // critical path, where the FP32 operator's cycle limit would cost restarts
+    if (P.precision == XKP_MIXED && !keep_base)
         gmres_call<R, true>(s, P, flags, pre, gsrc, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
     else
         gmres_call<R, false>(s, P, flags, pre, gsrc, hdr, Vfirst, Hb, slot + Lw.v, C, info, nlds);
