@@ -77,6 +77,20 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.xkp_residual(None, 1, None, None) == xkp.EINVAL
     t = xkp.Tuning()
     assert lib.xkp_autotune(None, 1, None, 0, None, ct.byref(P), None, ct.byref(t)) == xkp.EINVAL
+    assert lib.xkp_ctx_set_launch(None, 8, 1) == xkp.EINVAL
+    assert lib.xkp_learned_solve(None, 1, None, 1, None, ct.byref(P), None, 41, 1.0, 1e-6,
+                                 None) == xkp.EINVAL
+    assert lib.xkp_basis_coeffs(None, 1, None, 1, None, 40, 0, None) == xkp.EINVAL
+    # the network's sizes and argument checks
+    assert lib.xkp_cnn_param_count(40) == 16 * 9 + 16 + 32 * 144 + 32 + 64 * 288 + 64 + 40 * 97
+    assert lib.xkp_cnn_param_count(0) == 0 and lib.xkp_cnn_param_count(65) == 0
+    assert lib.xkp_cnn_workspace_bytes(0, 40) == 0
+    assert lib.xkp_cnn_workspace_bytes(512, 41) > lib.xkp_cnn_workspace_bytes(256, 41) > 0
+    assert lib.xkp_cnn_forward(None, 1, 40, None, None, None, None, None, None) == xkp.EINVAL
+    assert lib.xkp_cnn_backward(None, 1, 40, None, None, None, None, None, 40, None, 1.0, None,
+                                None, None, None) == xkp.EINVAL
+    assert lib.xkp_cnn_adam(None, 1, None, None, None, None, 1, 1e-3, 0.9, 0.999,
+                            1e-8) == xkp.EINVAL
     assert xkp.basis_bytes(0, 10) == 0
     n, m = 4096, 40
     assert xkp.basis_bytes(n, m) >= 256 + 8 * n * (m + 1) + 8 * (m + 1) * m + 2 * n * (m + 1)

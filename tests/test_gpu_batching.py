@@ -276,3 +276,23 @@ def test_autotune_picks_a_converging_candidate(X):
     _, ti = ch.all_infos()
     assert np.all(ti["status"] == X.OK) and np.all(ti["res_true"] <= 1e-8)
     assert np.all(ch.verify_last() <= 1e-8 * (1 + 1e-6))
+
+
+def test_uneven_mixed_precision_chain(X):
+    """Mixed precision over an uneven two-size, two-channel batch: every solve meets the FP64
+    tolerance and the states stay within the chain bound of the FP64 oracle."""
+    T, m = 8, 20
+    b, groups = uneven_batch(T, m, precision=X.MIXED)
+    b.run()
+    s_inf, t_inf = b.all_infos()
+    assert np.all(s_inf["status"] == X.OK) and np.all(t_inf["status"] == X.OK)
+    assert np.all(t_inf["res_true"] <= 1e-8)
+    assert np.all(b.verify_last() <= 1e-8 * (1 + 1e-6))
+    from oracle.chain import run_chain
+    for gi, gr in enumerate(b.groups):
+        _, mt_g = b.group_states(gi)
+        mt_g = cpu(mt_g)
+        for c in range(gr.C):
+            _, mt_o, _ = run_chain(gr.seed_m0[c], gr.target_m0[:, c], gr.H, T, m)
+            bound = T * 1e-8 * np.linalg.norm(gr.target_m0[:, c], axis=1).max()
+            assert np.abs(mt_g[:, c] - mt_o).max() <= bound

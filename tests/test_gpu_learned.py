@@ -188,3 +188,29 @@ def test_learned_pipeline_trains_and_falls_back(X):
           f"{tp['iters'].mean():.1f}; accepted at gate 1e-2: "
           f"{(res[('trained', 1e-2)]['guess_source'] == 2).mean():.2f}")
     assert np.median(tr["guess_res"]) < 0.5 * np.median(un["guess_res"])
+
+
+def test_learned_chain_graph_replays_match_eager(X):
+    """A chain with the learned guess (network inference inside every timestep) captured once
+    and replayed twice with eager work between: bitwise the eager chain."""
+    import torch
+    from oracle import cnn
+    from paper_2511_17634_amd.driver import Batch, Group
+    T, m = 6, 40
+    s0, _ = blob_pair(64, seed=55)
+    tg = np.stack([blob_pair(64, seed=55, jitter=1.0 + 0.3 * i)[1] for i in range(5)])
+    theta = cnn.init_params(m + 1, np.random.default_rng(1)) * 0.01
+    b = Batch([Group(64, s0[None], tg[:, None])], T, m, method="learned",
+              learned=dict(params=theta, scale=1.0, gate=1e300))
+    b.run()
+    ref = cpu(b.state()[1]).copy()
+    ref_i = b.all_infos()[1].copy()
+    assert np.all(ref_i["status"] == X.OK) and np.all(ref_i["guess_source"] == 2)
+    b.capture()
+    for _ in range(2):
+        b.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(cpu(b.state()[1]), ref)
+        assert np.array_equal(b.all_infos()[1], ref_i)
+        b.run()
+        torch.cuda.synchronize()
