@@ -132,16 +132,6 @@ __device__ __forceinline__ OpConst op_const(const xkp_system &s) {
     return o;
 }
 
-// Row walker: rows p = tid + k*kNT of one thread, with grid indices (i, j) kept incrementally.
-struct RowIdx {
-    int i0, j0, di, dj;
-    __device__ __forceinline__ void init(int H) {
-        i0 = (int)threadIdx.x / H;
-        j0 = (int)threadIdx.x - i0 * H;
-        di = kNT / H;
-        dj = kNT - di * H;
-    }
-};
 
 }  // namespace XKP_VARIANT
 }  // namespace xkp

@@ -1,8 +1,9 @@
 // HIP kernels (gfx950) of the cross-matrix Krylov projection path.
 //
 // One workgroup of kNT threads owns one linear system at a time (persistent loop over the
-// batch).  Thread t owns rows p = t + k*kNT, k < rmax, of every grid vector: basis columns are
-// read and written only by the thread owning the row, so global memory needs no cross-thread
+// batch).  Thread t owns the row pairs p = 2t + 2k*kNT + e (e = 0, 1; k < rmax/2) of every grid
+// vector, so that a basis column moves through 16-byte loads and stores: basis columns are read
+// and written only by the thread owning the row, so global memory needs no cross-thread
 // ordering; the stencil's neighbour values come from an LDS copy of the vector.
 //
 //   solve_kernel    one persistent launch per batch, systems taken from a work queue:
@@ -69,7 +70,18 @@ __device__ __forceinline__ double bld(rsrc_t r, unsigned byte_off, unsigned soff
 __device__ __forceinline__ void bst(rsrc_t r, unsigned byte_off, double v, unsigned soff = 0) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, byte_off, soff, 0);
 }
-__device__ __forceinline__ unsigned row_off(int k) { return (threadIdx.x + k * kNT) * 8u; }
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
+// Two consecutive doubles (one 16-byte access); the pair lies wholly inside or wholly outside
+// every range it is used with (even element counts).
+__device__ __forceinline__ double2_t bld2(rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(double2_t, __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, soff, 0));
+}
+__device__ __forceinline__ void bst2(rsrc_t r, unsigned byte_off, double a, double b,
+                                     unsigned soff = 0) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, double2_t{a, b}), r,
+                                           byte_off, soff, 0);
+}
 
 // FP32 / BF16 views: the same resources with 4- and 2-byte elements.
 __device__ __forceinline__ rsrc_t mkbuf32(const float *base, int count) {
@@ -80,8 +92,9 @@ __device__ __forceinline__ rsrc_t mkbuf16(const unsigned short *base, int count)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned short *>(base), (short)0,
                                              count * 2, kRsrcWord3);
 }
-__device__ __forceinline__ float bldf(rsrc_t r, unsigned byte_off, unsigned soff = 0) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, soff, 0));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f32x2_t bldf2(rsrc_t r, unsigned byte_off, unsigned soff = 0) {
+    return __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, soff, 0));
 }
 __device__ __forceinline__ void bstf(rsrc_t r, unsigned byte_off, float v, unsigned soff = 0) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, soff, 0);
@@ -97,9 +110,16 @@ __device__ __forceinline__ unsigned short to_bf16(double d) {
     const unsigned u = __builtin_bit_cast(unsigned, (float)d);
     return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
-// Row k of this thread = lane offset (one register) + scalar offset k * kNT * 8.
-__device__ __forceinline__ unsigned lane_off() { return threadIdx.x * 8u; }
-__device__ __forceinline__ unsigned row_soff(int k) { return (unsigned)(k * kNT * 8); }
+// Row k of this thread: p = 2t + (k & 1) + (k >> 1) * 2 kNT, addressed as the lane offset of the
+// pair (one register) + a scalar offset.  Every per-row array a thread holds is indexed by k.
+__device__ __forceinline__ int row_of(int k) {
+    return 2 * (int)threadIdx.x + (k & 1) + (k >> 1) * 2 * kNT;
+}
+__device__ __forceinline__ unsigned lane_off() { return threadIdx.x * 16u; }
+__device__ __forceinline__ unsigned row_soff(int k) {
+    return (unsigned)(((k >> 1) * 2 * kNT + (k & 1)) * 8);
+}
+__device__ __forceinline__ unsigned row_off(int k) { return (unsigned)row_of(k) * 8u; }
 
 // Plain global accessors (global address space) for the few non-row accesses.
 typedef __attribute__((address_space(1))) const double gcdouble;
@@ -137,29 +157,33 @@ __device__ __forceinline__ double dot_rows(const double (&a)[RMAX], const double
     return s0 + s1;
 }
 
-// Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), each loaded by the rows'
-// owners, with a ring of D columns in flight: the loads for visit q+D are issued as soon as
-// visit q has consumed its buffer, so global-memory latency overlaps the per-column work (the
-// reductions of modified Gram-Schmidt are sequential in q).  f(q, column) does the work.
-// Basis columns have leading dimension ldv = roundup(n + 1, 8) and zeros in rows n..ldv-1.
+// Basis columns have leading dimension ldv = roundup(n + 1, 8) and zeros in rows n..ldv-1, so a
+// column is read and written in row pairs over its ldv rows (a pair never straddles ldv).
 __device__ __forceinline__ int ldv_for(int n) { return (n + 8) & ~7; }
-
-template <int RMAX>
-__device__ __forceinline__ void load_col(const double *__restrict__ v, int n, double (&r)[RMAX]) {
-    load_rows<RMAX>(v, n, r);
-}
-
-// Stores rows p < ldv (the rows past n carry zeros), keeping the column's zero padding.
-template <int RMAX>
-__device__ __forceinline__ void store_col(double *__restrict__ v, int ldv, const double (&r)[RMAX]) {
-    store_rows<RMAX>(v, ldv, r);
-}
 
 template <int RMAX>
 __device__ __forceinline__ void load_buf(rsrc_t b, double (&r)[RMAX]) {
     const unsigned lo = lane_off();
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) r[k] = bld(b, lo, row_soff(k));
+    for (int k = 0; k < RMAX; k += 2) {
+        const double2_t v = bld2(b, lo, row_soff(k));
+        r[k] = v[0];
+        r[k + 1] = v[1];
+    }
+}
+
+template <int RMAX>
+__device__ __forceinline__ void load_col(const double *__restrict__ v, int ldv, double (&r)[RMAX]) {
+    load_buf<RMAX>(mkbuf(v, ldv), r);
+}
+
+// Stores rows p < ldv (the rows past n carry zeros), keeping the column's zero padding.
+template <int RMAX>
+__device__ __forceinline__ void store_col(double *__restrict__ v, int ldv, const double (&r)[RMAX]) {
+    const rsrc_t b = mkbuf(v, ldv);
+    const unsigned lo = lane_off();
+#pragma unroll
+    for (int k = 0; k < RMAX; k += 2) bst2(b, lo, r[k], r[k + 1], row_soff(k));
 }
 
 // Visits basis columns col(q), q = 0..nvisit-1 (col(q) = q mod ncols), with a ring of D columns
@@ -170,13 +194,13 @@ __device__ __forceinline__ void load_buf(rsrc_t b, double (&r)[RMAX]) {
 // the loop has the same loads outstanding and the waits stay partial.  f(q, column) must not
 // access global memory.
 template <int RMAX, int D, typename F>
-__device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int n, int ldv, int ncols,
+__device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int ldv, int ncols,
                                            int nvisit, F &&f) {
     double buf[D][RMAX];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int c = d < ncols ? d : d % ncols;
-        load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, d < nvisit ? n : 0), buf[d]);
+        load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, d < nvisit ? ldv : 0), buf[d]);
     }
     for (int q0 = 0; q0 < nvisit; q0 += D) {
 #pragma unroll
@@ -185,7 +209,7 @@ __device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int n, 
             if (q < nvisit) f(q, buf[d]);
             const int qn = q + D;
             const int c = qn < ncols ? qn : (qn < 2 * ncols ? qn - ncols : 0);
-            load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, qn < nvisit ? n : 0), buf[d]);
+            load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, qn < nvisit ? ldv : 0), buf[d]);
         }
     }
 }
@@ -217,7 +241,7 @@ __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &
     const double *__restrict__ mt = s.mt;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        const int p = (int)threadIdx.x + k * kNT;
+        const int p = row_of(k);
         double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
         if (p < o.n) {
             const int i = p / H, j = p - (p / H) * H;
@@ -257,19 +281,23 @@ template <int RMAX>
 __device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, const OpConst &o,
                                             double (&w)[RMAX]) {
     const int H = o.H;
-    const double *uc = u + threadIdx.x;
+    const double *uc = u + 2 * threadIdx.x;
     const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
     const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
     const unsigned lo = lane_off();
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
+    for (int k = 0; k < RMAX; k += 2) {
+        // rows q[0], q[1] of the pair; q[-1] and q[2] are their south and north neighbours
         const unsigned so = row_soff(k);
         const double *q = uc + k * kNT;
-        w[k] = o.cd * q[0] + bld(bE, lo, so) * q[H] + bld(bW, lo, so) * q[-H]
-               + bld(bN, lo, so) * q[1] + bld(bS, lo, so) * q[-1];
+        const double2_t cE = bld2(bE, lo, so), cW = bld2(bW, lo, so);
+        const double2_t cN = bld2(bN, lo, so), cS = bld2(bS, lo, so);
+        const double2_t u0 = *(const double2_t *)q;
+        w[k] = o.cd * u0[0] + cE[0] * q[H] + cW[0] * q[-H] + cN[0] * u0[1] + cS[0] * q[-1];
+        w[k + 1] = o.cd * u0[1] + cE[1] * q[H + 1] + cW[1] * q[1 - H] + cN[1] * q[2] + cS[1] * u0[0];
         // bound the scheduling region: issuing every row's loads at once needs more registers
         // than the kernel has while the basis prefetch is in flight
-        if (XKP_STENCIL_GROUP > 0 && k % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
+        if (XKP_STENCIL_GROUP > 0 && (k / 2) % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
             __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -281,50 +309,37 @@ __device__ __forceinline__ void stencil_lds_f32(const double *u, const Coef &C, 
                                                 double (&w)[RMAX]) {
     const int H = o.H;
     const float cd = (float)o.cd;
-    const double *uc = u + threadIdx.x;
+    const double *uc = u + 2 * threadIdx.x;
     const rsrc_t bE = mkbuf32(C.E32, kNT * RMAX), bW = mkbuf32(C.W32, kNT * RMAX);
     const rsrc_t bN = mkbuf32(C.N32, kNT * RMAX), bS = mkbuf32(C.S32, kNT * RMAX);
-    const unsigned lo = threadIdx.x * 4u;
+    const unsigned lo = threadIdx.x * 8u;
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
+    for (int k = 0; k < RMAX; k += 2) {
         const unsigned so = (unsigned)(k * kNT * 4);
         const double *q = uc + k * kNT;
-        const float y = cd * (float)q[0] + bldf(bE, lo, so) * (float)q[H]
-                        + bldf(bW, lo, so) * (float)q[-H] + bldf(bN, lo, so) * (float)q[1]
-                        + bldf(bS, lo, so) * (float)q[-1];
-        w[k] = (double)y;
-        if (XKP_STENCIL_GROUP > 0 && k % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
+        const f32x2_t cE = bldf2(bE, lo, so), cW = bldf2(bW, lo, so);
+        const f32x2_t cN = bldf2(bN, lo, so), cS = bldf2(bS, lo, so);
+        const double2_t u0 = *(const double2_t *)q;
+        const float y0 = cd * (float)u0[0] + cE[0] * (float)q[H] + cW[0] * (float)q[-H]
+                         + cN[0] * (float)u0[1] + cS[0] * (float)q[-1];
+        const float y1 = cd * (float)u0[1] + cE[1] * (float)q[H + 1] + cW[1] * (float)q[1 - H]
+                         + cN[1] * (float)q[2] + cS[1] * (float)u0[0];
+        w[k] = (double)y0;
+        w[k + 1] = (double)y1;
+        if (XKP_STENCIL_GROUP > 0 && (k / 2) % XKP_STENCIL_GROUP == XKP_STENCIL_GROUP - 1)
             __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// BF16 copy of a column (rows p < ldv), 2-byte elements.
+// BF16 copy of a column (rows p < ldv), 2-byte elements, one 4-byte store per row pair.
 template <int RMAX>
 __device__ __forceinline__ void store_col_bf16(unsigned short *v, int ldv, const double (&r)[RMAX]) {
     const rsrc_t b = mkbuf16(v, ldv);
-    const unsigned lo = threadIdx.x * 2u;
+    const unsigned lo = threadIdx.x * 4u;
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) bst16(b, lo, to_bf16(r[k]), (unsigned)(k * kNT * 2));
-}
-
-// w = A u with u a length-n global vector: every neighbour index clamped into [0, n), rows past
-// n masked to zero.
-template <int RMAX>
-__device__ __forceinline__ void stencil_glob(const double *__restrict__ u, const Coef &C,
-                                             const OpConst &o, double (&w)[RMAX]) {
-    const unsigned H = o.H, n = o.n;
-    const rsrc_t bu = mkbuf(u, n);
-    const rsrc_t bE = mkbuf(C.E, kNT * RMAX), bW = mkbuf(C.W, kNT * RMAX);
-    const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
-#pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-        const unsigned p = threadIdx.x + k * kNT, off = p * 8u;
-        // neighbours outside [0, n) read as zero (range check); their coefficient is 0 anyway
-        const unsigned ow = p >= H ? (p - H) * 8u : 0xFFFFFFF0u;
-        const unsigned os = p >= 1u ? (p - 1u) * 8u : 0xFFFFFFF0u;
-        w[k] = o.cd * bld(bu, off) + bld(bE, off) * bld(bu, off + 8u * H)
-               + bld(bW, off) * bld(bu, ow) + bld(bN, off) * bld(bu, off + 8u)
-               + bld(bS, off) * bld(bu, os);
+    for (int k = 0; k < RMAX; k += 2) {
+        const unsigned pair = (unsigned)to_bf16(r[k]) | ((unsigned)to_bf16(r[k + 1]) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(pair, b, lo, (unsigned)(k * kNT * 2), 0);
     }
 }
 
@@ -336,7 +351,7 @@ __device__ __forceinline__ void stencil_direct(const double *u, const xkp_system
     const double *__restrict__ mt = s.mt;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
-        const int p = (int)threadIdx.x + k * kNT;
+        const int p = row_of(k);
         double r = 0.0;
         if (p < o.n) {
             const int i = p / H, j = p - (p / H) * H;
@@ -359,8 +374,9 @@ __device__ __forceinline__ void stencil_direct(const double *u, const xkp_system
 // All rows (including the zero rows past n) into the padded LDS vector.
 template <int RMAX>
 __device__ __forceinline__ void store_rows_lds(double *v, const double (&r)[RMAX]) {
+    double *vc = v + 2 * threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) v[threadIdx.x + k * kNT] = r[k];
+    for (int k = 0; k < RMAX; k += 2) *(double2_t *)(vc + k * kNT) = double2_t{r[k], r[k + 1]};
 }
 
 __device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
@@ -479,7 +495,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     // two modified Gram-Schmidt passes over v_0..v_j as one sweep of 2(j+1)
                     // column visits; the second pass re-orthogonalises and completes h_{i,j}
                     const int nc = j + 1;
-                    sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, nc, 2 * nc,
+                    sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, nc, 2 * nc,
                         [&](int q, const double(&col)[RMAX]) {
                         const int i = q < nc ? q : q - nc;
                         double part = 0.0;
@@ -563,7 +579,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 lds_barrier();
                 // x += V_k y
                 load_rows<RMAX>(s.x, n, w);
-                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, kk, kk,
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, kk, kk,
                     [&](int c, const double(&col)[RMAX]) {
                     const double yc = L.yv[c];
 #pragma unroll
@@ -789,7 +805,6 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 // Mixed-precision counterpart of vtw_chunk: partial Vb^T Wb of the BF16 copies of V_k and
 // A'V_k (k columns each, leading dimension ldv elements), over 32-row chunks
@@ -946,7 +961,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 for (int q = 0; q < kRedSlots; ++q) {
                     part[q] = 0.0;
                     if (c0 + q < nz) {
-                        load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, cur);
+                        load_col<RMAX>(V + (size_t)(c0 + q) * ldv, ldv, cur);
                         part[q] = dot_rows<RMAX>(cur, rb);
                     }
                 }
@@ -963,7 +978,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 unsigned short *Wb = (unsigned short *)W;
                 const unsigned short *Vb =
                     (const unsigned short *)((const char *)hdr + basis_off_vb(n, m));
-                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, k, k,
                     [&](int c, const double(&col)[RMAX]) {
                     double *vb = (nbuf == 2 && (c & 1)) ? vbuf1 : vbuf;
                     if (nbuf == 1 && c > 0) lds_barrier();   // readers of the previous column
@@ -1026,7 +1041,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                 }
                 const int H = o.H;
                 store_col<RMAX>(W + (size_t)k * ldv, ldv, rb);
-                sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+                sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, k, k,
                     [&](int c, const double(&col)[RMAX]) {
                     double *vb = (nbuf == 2 && (c & 1)) ? vbuf1 : vbuf;
                     if (nbuf == 1 && c > 0) lds_barrier();   // readers of the previous column
@@ -1036,7 +1051,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                     if constexpr (kRegC) {
 #pragma unroll
                         for (int q = 0; q < RMAX; ++q) {
-                            const double *u = vb + threadIdx.x + q * kNT;
+                            const double *u = vb + row_of(q);
                             y[q] = o.cd * u[0] + cEr[q] * u[H] + cWr[q] * u[-H] + cNr[q] * u[1]
                                    + cSr[q] * u[-1];
                         }
@@ -1109,7 +1124,7 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
             for (int q = 0; q < RMAX; ++q) xr[q] = 0.0;
         }
         if (k > 0 && !singular) {
-            sweep_cols<RMAX, Depth<RMAX>::value>(V, n, ldv, k, k,
+            sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, k, k,
                 [&](int c, const double(&col)[RMAX]) {
                 const double al = alpha[c];
 #pragma unroll
@@ -1148,7 +1163,8 @@ constexpr int kRClass0 = 4, kRClass1 = 16;
 // another spill inside its loops.  Their arguments arrive in vector registers; every one is
 // the same across the workgroup, and readfirstlane says so to the compiler (buffer descriptors
 // and loop bounds must be scalar).  The LDS is addressed through the dynamic-LDS symbol itself.
-extern __shared__ double xkp_dyn_lds[];
+// (16-byte aligned: row pairs are read and written as 16-byte LDS accesses)
+extern __shared__ __attribute__((aligned(16))) double xkp_dyn_lds[];
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ double uni(double v) {
@@ -1270,7 +1286,7 @@ __device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const vo
         for (int q = 0; q < R; ++q) xr[q] = 0.0;
     }
     if (k > 0 && !singular) {
-        sweep_cols<R, Depth<R>::value>(V, n, ldv, k, k, [&](int c, const double(&col)[R]) {
+        sweep_cols<R, Depth<R>::value>(V, ldv, k, k, [&](int c, const double(&col)[R]) {
             const double al = alpha[c];
 #pragma unroll
             for (int q = 0; q < R; ++q) xr[q] += al * col[q];
@@ -1413,7 +1429,7 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
                                                      int n_bases, const void *const *bases,
                                                      int m_out, int kind, double *alpha,
                                                      int nmax) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     BlockRed br{lds, 0};
     double *av = lds + 2 * kRedSlots * kNW;   // kMMax coordinates
     for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
@@ -1441,7 +1457,7 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
             for (int q = 0; q < kRedSlots; ++q) {
                 part[q] = 0.0;
                 if (c0 + q < k) {
-                    load_col<RMAX>(V + (size_t)(c0 + q) * ldv, n, col);
+                    load_col<RMAX>(V + (size_t)(c0 + q) * ldv, ldv, col);
                     part[q] = dot_rows<RMAX>(col, xr);
                 }
             }
@@ -1470,7 +1486,7 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
 template <int RMAX>
 __global__ __launch_bounds__(kNT) void residual_kernel(const xkp_system *__restrict__ sys, int nsys,
                                                        double *rel, int nmax, int nlds) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     double *vbuf = lds;
     double *red = lds + nlds;
     for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
@@ -1499,7 +1515,7 @@ __global__ __launch_bounds__(kNT) void residual_kernel(const xkp_system *__restr
 template <int RMAX>
 __global__ __launch_bounds__(kNT) void apply_kernel(const xkp_system *__restrict__ sys, int nsys,
                                                     int nmax, int nlds) {
-    extern __shared__ double lds[];
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     for (int si = blockIdx.x; si < nsys; si += gridDim.x) {
         const xkp_system s = sys[si];
         if (!desc_ok(s, nmax) || s.x0 == nullptr) continue;
@@ -1523,22 +1539,17 @@ __global__ __launch_bounds__(kNT) void rhs_kernel(const xkp_system *__restrict__
         if (!(s.H > 0 && (long)s.H * s.H <= nmax && s.mt && s.b && s.dt > 0.0)) continue;
         const OpConst o = op_const(s);
         double *b = const_cast<double *>(s.b);
-        RowIdx ri;
-        ri.init(o.H);
-        int i = ri.i0, j = ri.j0;
         const int H = o.H;
 #pragma unroll
         for (int k = 0; k < RMAX; ++k) {
-            const int p = (int)threadIdx.x + k * kNT;
+            const int p = row_of(k);
+            const int i = p / H, j = p - i * H;
             if (p < o.n) {
                 double div = 0.0;
                 if (s.fx) div += ((i + 1 < H) ? ld(s.fx, p + H) : 0.0) - ((i > 0) ? ld(s.fx, p - H) : 0.0);
                 if (s.fy) div += ((j + 1 < H) ? ld(s.fy, p + 1) : 0.0) - ((j > 0) ? ld(s.fy, p - 1) : 0.0);
                 b[p] = ld(s.mt, p) / s.dt - div * o.inv2h;
             }
-            j += ri.dj;
-            i += ri.di;
-            if (j >= H) { j -= H; ++i; }
         }
     }
 }
