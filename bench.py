@@ -65,11 +65,11 @@ def traffic_bytes():
                        + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
 
 
-def gmres_bytes(n, m, iters, restarts):
-    """Algorithmic HBM bytes of restarted GMRES(m) with two Gram-Schmidt passes, FP64:
-    Arnoldi step j reads v_0..v_j twice (16 n (j+1)), writes v_{j+1} (8 n) and applies the
-    operator (read u and m~, write w: 24 n); each cycle end forms x += V y (8 n k) and the true
-    residual (48 n)."""
+def gmres_bytes(n, m, iters, restarts, passes=1):
+    """Algorithmic HBM bytes of restarted GMRES(m) with `passes` Gram-Schmidt passes, FP64:
+    Arnoldi step j reads v_0..v_j once per pass (8 n (j+1) each), writes v_{j+1} (8 n) and
+    applies the operator (read u and m~, write w: 24 n); each cycle end forms x += V y (8 n k)
+    and the true residual (48 n)."""
     iters = np.asarray(iters, dtype=np.int64)
     restarts = np.asarray(restarts, dtype=np.int64)
     total = 0
@@ -78,7 +78,7 @@ def gmres_bytes(n, m, iters, restarts):
         for k in cycles:
             if k <= 0:
                 continue
-            total += sum(16 * n * (j + 1) + 8 * n + 24 * n for j in range(k))
+            total += sum(8 * passes * n * (j + 1) + 8 * n + 24 * n for j in range(k))
             total += 8 * n * k + 48 * n
     return total
 
@@ -146,7 +146,8 @@ def uneven_leg(args):
     cfg4, groups = build_c4()
     un = {}
     for name, method in (("project", "project"), ("plain", "plain")):
-        b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin")
+        b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin",
+                  reorth=args.reorth)
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.uneven_steps, 1, graph)
         un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
@@ -175,7 +176,8 @@ def mixed_leg(args):
                                ("project_fp64", "project", xkp.FP64),
                                ("plain_mixed", "plain", xkp.MIXED),
                                ("plain_fp64", "plain", xkp.FP64)):
-        b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec)
+        b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec,
+                  reorth=args.reorth)
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.mixed_steps, 1, graph)
         e, eok = err_vs_fp64(b)
@@ -232,7 +234,7 @@ def learned_leg(args):
         if kw["method"] == "learned":
             kw = dict(method="learned", polish_m=polish_m,
                       learned=dict(params=net.params, scale=1.0, gate=kw["gate"]))
-        b = Batch([Group(64, s0[None], e0[:, None])], T, m, **kw)
+        b = Batch([Group(64, s0[None], e0[:, None])], T, m, reorth=args.reorth, **kw)
         if kw["method"] == "project" and not args.no_tune:
             polish_m = b.autotune().polish_m
         elif kw["method"] == "plain" and not args.no_tune:
@@ -304,11 +306,12 @@ def target_call_ms(b):
     return [a.elapsed_time(e) for a, e in ev]
 
 
-def cpu_baseline(H, T, m, s0, t0, n_targets, steps):
+def cpu_baseline(H, T, m, s0, t0, n_targets, steps, reorth="auto"):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same chain."""
     from oracle.chain import run_chain
     t = time.perf_counter()
-    _, _, st = run_chain(s0, t0[:n_targets], H, T, m, method="project", steps=steps)
+    _, _, st = run_chain(s0, t0[:n_targets], H, T, m, method="project", steps=steps,
+                         reorth=reorth)
     el = time.perf_counter() - t
     return {"value": n_targets * steps / el, "unit": "target systems/s", "cores": 1,
             "kind": "oracle",
@@ -340,6 +343,8 @@ def main():
                     help="comma list of the 64x64 legs to run (profiling runs take one)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--reorth", choices=("auto", "always"), default="auto",
+                    help="Gram-Schmidt passes: two only while a seed basis is kept, or always")
     ap.add_argument("--cpu-targets", type=int, default=20)
     ap.add_argument("--cpu-steps", type=int, default=100)
     args = ap.parse_args()
@@ -377,7 +382,8 @@ def main():
                                ("plain", "plain", "none")):
         if name not in wanted:
             continue
-        ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m)
+        ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m,
+                   reorth=args.reorth)
         if not args.no_tune and not args.polish_m:
             tunings[name] = ch.autotune()
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
@@ -400,7 +406,8 @@ def main():
     # roofline of the dominant kernel: the batched solve kernel in the plain leg (GMRES only),
     # one launch per timestep, timed by HIP events on its stream
     pl = legs["plain"]
-    byts = gmres_bytes(n, pl["polish_m"], pl["iters"], pl["restarts"]) / T   # per launch
+    passes = 1 if args.reorth == "auto" else 2
+    byts = gmres_bytes(n, pl["polish_m"], pl["iters"], pl["restarts"], passes) / T  # per launch
     launch_s = sum(launch_ms) / 1e3 / T
     achieved = byts / launch_s / 1e9
     out = {
@@ -411,7 +418,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg.name, "grid": f"{H}x{H}", "n": n, "targets": N, "seeds": 1,
                    "timesteps": T, "m": m, "tol": args.tol, "projection": "target_galerkin",
-                   "polish_m": legs["project"]["polish_m"], "graph": graph},
+                   "polish_m": legs["project"]["polish_m"], "graph": graph,
+                   "reorth": args.reorth},
         "verified": all(v["ok"] for v in legs.values()),
         "plain_gmres": {"value": round(N * T / per_step["plain"], 2),
                         "ms_per_step": round(per_step["plain"] * 1e3, 3),
@@ -430,7 +438,7 @@ def main():
         "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes(),
+                     "traffic": traffic_bytes() if args.reorth == "auto" else None,
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
     del plain_chain
@@ -447,7 +455,8 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps,
+                                           args.reorth)
     print(json.dumps(out), flush=True)
 
 

@@ -70,6 +70,19 @@ typedef enum {
     XKP_PROJ_NONE = 3             /* no projection: plain GMRES from x_base                  */
 } xkp_proj_mode;
 
+/*
+ * Gram-Schmidt passes per Arnoldi step.  A basis that is kept (the first cycle of a seed,
+ * Section 3, Phase 1) must be orthonormal to working precision for the projection, which two
+ * modified Gram-Schmidt passes give; a GMRES cycle whose basis is discarded (target polish, plain
+ * GMRES, the seed's later cycles) converges as well with one pass, GMRES with modified
+ * Gram-Schmidt being backward stable (Paige, Rozloznik and Strakos, SIAM J. Matrix Anal. Appl.
+ * 28, 2006), at half the basis traffic and half the sequential reductions.
+ */
+typedef enum {
+    XKP_REORTH_AUTO = 0,   /* two passes while a basis is kept, one pass elsewhere          */
+    XKP_REORTH_ALWAYS = 1  /* two passes in every Arnoldi step                              */
+} xkp_reorth;
+
 /* One linear system of one image channel at one timestep (device-resident array element). */
 typedef struct {
     int32_t H;            /* grid side; n = H*H unknowns                                    */
@@ -95,6 +108,7 @@ typedef struct {
                              unknowns than this gets status XKP_EINVAL.                    */
     int32_t polish_m;     /* targets: restart length of the polish (and of plain GMRES),
                              1..64, or 0 for m.  The seed basis dimension stays m.          */
+    int32_t reorth;       /* xkp_reorth                                                     */
 } xkp_params;
 
 /* Per-system outcome, device-resident. */

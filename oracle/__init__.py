@@ -66,7 +66,8 @@ def lib():
         _lib.xo_banded_solve.argtypes = [ct.POINTER(_Op), P, P]
         _lib.xo_residual.argtypes = [ct.POINTER(_Op), P, P]
         _lib.xo_residual.restype = ct.c_double
-        gm = [ct.c_int, ct.c_int, ct.c_double, ct.c_int, P, P, ct.POINTER(_Info), P, ct.c_int]
+        gm = [ct.c_int, ct.c_int, ct.c_double, ct.c_int, ct.c_int, P, P, ct.POINTER(_Info), P,
+              ct.c_int]
         _lib.xo_gmres.argtypes = [ct.POINTER(_Op), P, P] + gm
         _lib.xo_gmres_dense.argtypes = [ct.c_int, P, P, P] + gm
         _lib.xo_project.argtypes = [ct.POINTER(_Op), P, P, ct.c_int, P, P, ct.c_int, ct.c_int, P, P]
@@ -200,23 +201,30 @@ def _gmres_common(call, n, b, x0, m, max_restarts, tol, max_iters, keep_basis, h
 
 
 def gmres(A: Operator, b, x0=None, m=30, max_restarts=1000, tol=1e-8, max_iters=0,
-          keep_basis=False, hist_cap=0) -> GmresResult:
-    """Restarted GMRES(m) on the stencil operator (Section 3 Krylov solve; Saad Alg. 6.9/6.11)."""
+          keep_basis=False, hist_cap=0, passes=2) -> GmresResult:
+    """Restarted GMRES(m) on the stencil operator (Section 3 Krylov solve; Saad Alg. 6.9/6.11),
+    with `passes` (1 or 2) modified Gram-Schmidt passes per Arnoldi step."""
+    if passes not in (1, 2):
+        raise ValueError("passes must be 1 or 2")
+
     def call(b, x, V, Hb, info, hist):
-        lib().xo_gmres(A.ref, _p(b), _p(x), m, max_restarts, tol, max_iters, _p(V), _p(Hb),
-                       ct.byref(info), _p(hist), 0 if hist is None else hist.size)
+        lib().xo_gmres(A.ref, _p(b), _p(x), m, max_restarts, tol, max_iters, passes, _p(V),
+                       _p(Hb), ct.byref(info), _p(hist), 0 if hist is None else hist.size)
     return _gmres_common(call, A.n, b, x0, m, max_restarts, tol, max_iters, keep_basis, hist_cap)
 
 
 def gmres_dense(D, b, x0=None, m=30, max_restarts=1000, tol=1e-8, max_iters=0,
-                keep_basis=False, hist_cap=0) -> GmresResult:
+                keep_basis=False, hist_cap=0, passes=2) -> GmresResult:
     """The same GMRES(m) on an explicit dense matrix (for the brute-force pins)."""
+    if passes not in (1, 2):
+        raise ValueError("passes must be 1 or 2")
     D = _f64(D)
     n = D.shape[0]
 
     def call(b, x, V, Hb, info, hist):
-        lib().xo_gmres_dense(n, _p(D), _p(b), _p(x), m, max_restarts, tol, max_iters, _p(V),
-                             _p(Hb), ct.byref(info), _p(hist), 0 if hist is None else hist.size)
+        lib().xo_gmres_dense(n, _p(D), _p(b), _p(x), m, max_restarts, tol, max_iters, passes,
+                             _p(V), _p(Hb), ct.byref(info), _p(hist),
+                             0 if hist is None else hist.size)
     return _gmres_common(call, n, b, x0, m, max_restarts, tol, max_iters, keep_basis, hist_cap)
 
 

@@ -30,12 +30,17 @@ class ChainStats:
 
 
 def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
-              mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000):
+              mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000, reorth="auto"):
     """Advance the seed and every target through `steps` (default T) timesteps.
 
     seed_m0: (n,) initial state of the seed; target_m0: (N, n).  Returns (m_seed, m_targets,
-    stats).  With method "plain" or "direct" the seed chain is not solved.
+    stats).  With method "plain" or "direct" the seed chain is not solved.  reorth "auto": two
+    Gram-Schmidt passes in the seed solves (their first-cycle basis is kept), one in the target
+    solves (their basis is discarded); "always": two passes everywhere.
     """
+    if reorth not in ("auto", "always"):
+        raise ValueError("reorth must be 'auto' or 'always'")
+    tpasses = 1 if reorth == "auto" else 2
     dt = 1.0 / T
     ms = np.array(seed_m0, dtype=np.float64).reshape(-1)
     mt = np.array(target_m0, dtype=np.float64).reshape(len(target_m0), -1)
@@ -66,7 +71,8 @@ def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
                 else:
                     x0 = xb
                 g_row.append(residual(At, bt, x0) if x0 is not None else 1.0)
-                r = gmres(At, bt, x0=x0, m=m, tol=tol, max_restarts=max_restarts)
+                r = gmres(At, bt, x0=x0, m=m, tol=tol, max_restarts=max_restarts,
+                          passes=tpasses)
                 x = r.x
                 it_row.append(r.iters); rs_row.append(r.restarts); stt_row.append(r.status)
                 res_row.append(r.res_true)

@@ -15,9 +15,10 @@
  *   xo_lu_solve / xo_banded_solve  -- the direct LU solve the paper uses as its baseline
  *       (end of Section 2.3; Experiment 2, "SpSolve").
  *   xo_gmres  -- the Krylov solve of Section 3 (Krylov subspace K_a(A, r0)), as restarted GMRES:
- *       Arnoldi with modified Gram-Schmidt (done twice), Givens rotations on the Hessenberg
- *       matrix, restart on the true residual (Saad, Iterative Methods for Sparse Linear Systems,
- *       2nd ed., Alg. 6.9 and Section 6.5.3).  The first cycle's orthonormal basis V and
+ *       Arnoldi with modified Gram-Schmidt (one pass, or two: the second re-orthogonalises),
+ *       Givens rotations on the Hessenberg matrix, restart on the true residual (Saad,
+ *       Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 6.2, Alg. 6.9 and Section
+ *       6.5.3).  The first cycle's orthonormal basis V and
  *       Hessenberg matrix are returned: that is the per-timestep seed basis V_a^n of Section 3,
  *       Phase 1.
  *   xo_project  -- Section 3, Phase 2: A_proj alpha = b_proj in the seed basis, x0 = V alpha.
@@ -307,12 +308,13 @@ double xo_residual(const xo_op *A, const double *b, const double *x)
  *                 normalised last Arnoldi vector, or zero after a breakdown.
  *   hist:         if not NULL, receives the Givens residual estimate after each step (up to
  *                 hist_cap values).
- * Arnoldi step j: w = A v_j; two passes of modified Gram-Schmidt against v_0..v_j (the second
- * pass re-orthogonalises and adds to the same Hessenberg entries); h_{j+1,j} = ||w||;
- * breakdown when h_{j+1,j} <= 1e-14 ||A v_j||.
+ *   passes:       modified Gram-Schmidt passes per Arnoldi step (1 or 2).
+ * Arnoldi step j: w = A v_j; `passes` passes of modified Gram-Schmidt against v_0..v_j (Saad
+ * Alg. 6.2; a second pass re-orthogonalises and adds to the same Hessenberg entries);
+ * h_{j+1,j} = ||w||; breakdown when h_{j+1,j} <= 1e-14 ||A v_j||.
  */
 int xo_gmres_linop(const xo_linop *L, const double *b, double *x, int m, int max_restarts,
-                   double tol, int max_iters, double *V1, double *H1, xo_info *info,
+                   double tol, int max_iters, int passes, double *V1, double *H1, xo_info *info,
                    double *hist, int hist_cap)
 {
     const int n = L->n, ldh = m + 1;
@@ -351,7 +353,7 @@ int xo_gmres_linop(const xo_linop *L, const double *b, double *x, int m, int max
             linop_apply(L, vj, w);
             inf.iters++;
             const double wn0 = nrm2(n, w);
-            for (int pass = 0; pass < 2; ++pass) {
+            for (int pass = 0; pass < passes; ++pass) {
                 for (int i = 0; i <= j; ++i) {
                     const double *vi = V + (size_t)i * n;
                     const double d = dot(n, w, vi);
@@ -416,18 +418,21 @@ done:
 }
 
 int xo_gmres(const xo_op *A, const double *b, double *x, int m, int max_restarts, double tol,
-             int max_iters, double *V1, double *H1, xo_info *info, double *hist, int hist_cap)
+             int max_iters, int passes, double *V1, double *H1, xo_info *info, double *hist,
+             int hist_cap)
 {
     xo_linop L = {0, A->H * A->W, A, NULL};
-    return xo_gmres_linop(&L, b, x, m, max_restarts, tol, max_iters, V1, H1, info, hist, hist_cap);
+    return xo_gmres_linop(&L, b, x, m, max_restarts, tol, max_iters, passes, V1, H1, info, hist,
+                          hist_cap);
 }
 
 int xo_gmres_dense(int n, const double *D, const double *b, double *x, int m, int max_restarts,
-                   double tol, int max_iters, double *V1, double *H1, xo_info *info,
+                   double tol, int max_iters, int passes, double *V1, double *H1, xo_info *info,
                    double *hist, int hist_cap)
 {
     xo_linop L = {1, n, NULL, D};
-    return xo_gmres_linop(&L, b, x, m, max_restarts, tol, max_iters, V1, H1, info, hist, hist_cap);
+    return xo_gmres_linop(&L, b, x, m, max_restarts, tol, max_iters, passes, V1, H1, info, hist,
+                          hist_cap);
 }
 
 /* ---------------------------------------------------------------------------------------- */

@@ -74,7 +74,8 @@ xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const 
                       int *nmax, int *rmax, const Variant **var) {
     if (!ctx || count < 0 || (count > 0 && !arr) || !P) return XKP_EINVAL;
     if (P->m < 1 || P->m > ctx->max_m || !(P->tol >= 0.0) || P->max_restarts < 0 ||
-        P->polish_m < 0 || P->polish_m > ctx->max_m || P->batch_max_n < 0 || P->batch_max_n > ctx->max_n)
+        P->polish_m < 0 || P->polish_m > ctx->max_m || P->batch_max_n < 0 || P->batch_max_n > ctx->max_n ||
+        (P->reorth != XKP_REORTH_AUTO && P->reorth != XKP_REORTH_ALWAYS))
         return XKP_EINVAL;
     if (P->precision != XKP_FP64 && P->precision != XKP_MIXED) return XKP_EINVAL;
     if (P->mode < XKP_PROJ_TARGET_GALERKIN || P->mode > XKP_PROJ_NONE) return XKP_EINVAL;

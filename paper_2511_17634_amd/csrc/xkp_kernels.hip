@@ -8,9 +8,9 @@
 //
 //   solve_kernel    one persistent launch per batch, systems taken from a work queue:
 //     gmres_one     restarted GMRES(m): stencil operator (Section 2.3), Arnoldi with modified
-//                   Gram-Schmidt done twice, Givens rotations, restart on the FP64 true
-//                   residual; optionally keeps the first cycle as the seed basis (Section 3,
-//                   Phase 1) or starts from the projected guess (Phase 2 polish).
+//                   Gram-Schmidt (two passes while a basis is kept), Givens rotations, restart
+//                   on the FP64 true residual; optionally keeps the first cycle as the seed
+//                   basis (Section 3, Phase 1) or starts from the projected guess (Phase 2).
 //     project_one   Phase 2 projection of a target onto its seed basis: the k x k system
 //                   V^T A' V (FP64 matrix cores), H_k, or the least-squares Hessenberg problem,
 //                   solved by one wavefront; x0 = x_base + V alpha.
@@ -474,6 +474,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 // takes over (the kept first cycle of a seed runs to m or the tolerance).
                 const double gfloor =
                     (mixed && !(keep && first)) ? kMixedCycleDrop * beta : 0.0;
+                const bool two_pass = (keep && first) || P.reorth == XKP_REORTH_ALWAYS;
                 int kk = 0;
                 for (int j = 0; j < m; ++j) {
                     // With many rows per thread the Krylov vector w lives in the LDS copy of
@@ -492,10 +493,11 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                         for (int k = 0; k < RMAX; ++k) wl[k * kNT] = w[k];
                     }
                     double wn0 = 0.0, t = 0.0;
-                    // two modified Gram-Schmidt passes over v_0..v_j as one sweep of 2(j+1)
-                    // column visits; the second pass re-orthogonalises and completes h_{i,j}
-                    const int nc = j + 1;
-                    sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, nc, 2 * nc,
+                    // modified Gram-Schmidt over v_0..v_j: two passes as one sweep of 2(j+1)
+                    // column visits while the basis is kept (the second pass re-orthogonalises
+                    // and completes h_{i,j}), else one pass
+                    const int nc = j + 1, nvis = two_pass ? 2 * nc : nc;
+                    sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, nc, nvis,
                         [&](int q, const double(&col)[RMAX]) {
                         const int i = q < nc ? q : q - nc;
                         double part = 0.0;
@@ -521,11 +523,11 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
 #pragma unroll
                             for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
                         }
-                        if (q < nc) {
+                        if (q < nvis - nc) {
                             if (tid == 0) L.h1[i] = d;
                         } else {
                             // final h_{i,j}; fold the Givens rotations in as entries arrive
-                            const double hf = L.h1[i] + d;
+                            const double hf = two_pass ? L.h1[i] + d : d;
                             if (tid == 0) L.h2[i] = hf;
                             if (i == 0) {
                                 t = hf;
@@ -1199,6 +1201,7 @@ __device__ __forceinline__ xkp_params uni(xkp_params P) {
     P.mode = uni(P.mode);
     P.batch_max_n = uni(P.batch_max_n);
     P.polish_m = uni(P.polish_m);
+    P.reorth = uni(P.reorth);
     return P;
 }
 __device__ __forceinline__ Coef uni(Coef C) {

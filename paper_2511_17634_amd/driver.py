@@ -48,11 +48,14 @@ class Batch:
 
     def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
                  mode="target_galerkin", warm=False, max_restarts=1000, device=0,
-                 precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None):
+                 precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None,
+                 reorth="auto"):
         """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
         (the network's guess behind the residual gate, projection as fallback; `learned` =
         dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
-        gate=residual gate), single 64x64 group of one channel).  with_seeds: also solve the seeds with plain targets."""
+        gate=residual gate), single 64x64 group of one channel).  with_seeds: also solve the
+        seeds with plain targets.  reorth: "auto" (two Gram-Schmidt passes only while a seed's
+        basis is kept) or "always"."""
         import torch
         self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
         self.T, self.m, self.g, self.tol = T, m, g, tol
@@ -110,7 +113,8 @@ class Batch:
             self.alpha_l = torch.empty((self.N, k), dtype=torch.float32, device=self.dev)
         self.params = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
                                          precision=precision, mode=mode_id,
-                                         batch_max_n=self.nmax, polish_m=polish_m)
+                                         batch_max_n=self.nmax, polish_m=polish_m,
+                                         reorth=reorth)
         self.warm = warm
         self.seed_desc = [self._desc(self.seed_sys, self.ms, self.bs, par) for par in (0, 1)]
         self.tgt_desc = [self._desc(self.tgt_sys, self.mt, self.bt, par) for par in (0, 1)]

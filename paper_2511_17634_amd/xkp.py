@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("XKP_LIB") or os.path.join(HERE, "libxkp.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, EUNSUPPORTED = range(7)
 FP64, MIXED = 0, 1
 TARGET_GALERKIN, SEED_GALERKIN, SEED_LSQ, NONE = 0, 1, 2, 3
+REORTH_AUTO, REORTH_ALWAYS = 0, 1
 MODES = {"target_galerkin": TARGET_GALERKIN, "seed_galerkin": SEED_GALERKIN,
          "seed_lsq": SEED_LSQ, "none": NONE}
 
@@ -35,7 +36,7 @@ HEADER_BYTES = 256
 class Params(ct.Structure):
     _fields_ = [("m", ct.c_int32), ("max_restarts", ct.c_int32), ("tol", ct.c_double),
                 ("precision", ct.c_int32), ("mode", ct.c_int32), ("batch_max_n", ct.c_int32),
-                ("polish_m", ct.c_int32)]
+                ("polish_m", ct.c_int32), ("reorth", ct.c_int32)]
 
 
 class Tuning(ct.Structure):
@@ -203,10 +204,12 @@ class Context:
 
     @staticmethod
     def params(m, tol=1e-8, max_restarts=1000, precision=FP64, mode=TARGET_GALERKIN,
-               batch_max_n=0, polish_m=0):
+               batch_max_n=0, polish_m=0, reorth=REORTH_AUTO):
         if isinstance(mode, str):
             mode = MODES[mode]
-        return Params(m, max_restarts, tol, precision, mode, batch_max_n, polish_m)
+        if isinstance(reorth, str):
+            reorth = {"auto": REORTH_AUTO, "always": REORTH_ALWAYS}[reorth]
+        return Params(m, max_restarts, tol, precision, mode, batch_max_n, polish_m, reorth)
 
     def new_infos(self, count):
         import torch

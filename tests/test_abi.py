@@ -47,8 +47,8 @@ int main(void) {
          offsetof(xkp_system, mt), offsetof(xkp_system, x), sizeof(xkp_info), sizeof(xkp_params));
   printf("%zu %zu %zu\n", sizeof(xkp_basis_header), offsetof(xkp_info, res_est),
          offsetof(xkp_params, tol));
-  printf("%zu %zu %zu\n", offsetof(xkp_params, polish_m), sizeof(xkp_tuning),
-         offsetof(xkp_tuning, ms_default));
+  printf("%zu %zu %zu %zu\n", offsetof(xkp_params, polish_m), sizeof(xkp_tuning),
+         offsetof(xkp_tuning, ms_default), offsetof(xkp_params, reorth));
   return 0;
 }''')
     exe = tmp_path / "probe"
@@ -62,7 +62,7 @@ int main(void) {
     assert v[6] == xkp.HEADER_BYTES and v[7] == I.fields["res_est"][1]
     assert v[8] == xkp.Params.tol.offset
     assert v[9] == xkp.Params.polish_m.offset and v[10] == ct.sizeof(xkp.Tuning)
-    assert v[11] == xkp.Tuning.ms_default.offset
+    assert v[11] == xkp.Tuning.ms_default.offset and v[12] == xkp.Params.reorth.offset
 
 
 def test_host_side_errors_without_gpu(lib):

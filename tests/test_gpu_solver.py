@@ -254,3 +254,64 @@ def test_noconvergence_and_bad_descriptors(X):
         ctx.target_project_solve(d, 2, 0, None, X.Context.params(m + 10, mode="none"), inf)
     with pytest.raises(X.XkpError):
         ctx.target_project_solve(d, 2, 0, None, X.Context.params(m, mode="target_galerkin"), inf)
+
+
+@pytest.mark.parametrize("reorth,passes", [("auto", 1), ("always", 2)])
+def test_gram_schmidt_passes_match_oracle(X, reorth, passes):
+    """One cycle of eight Arnoldi steps from x_base = 0 (tolerance unreachable, no restart): the
+    iterate is GMRES's minimal-residual iterate, with one modified Gram-Schmidt pass (the
+    default for a discarded basis) as with two."""
+    import torch
+    H, T, m = 48, 100, 8
+    ms, mt = blob_pair(H, seed=9, jitter=1.5)
+    ctx = X.Context(H * H, m, 1)
+    tm = t64(mt)
+    bt = torch.zeros(H * H, dtype=torch.float64, device=dev())
+    xt = torch.zeros(H * H, dtype=torch.float64, device=dev())
+    d = X.pack_systems([X.SystemSpec(H, 1.0 / T, 0.5, tm, b=bt, x=xt)], dev())
+    ctx.build_rhs(d, 1)
+    inf = ctx.new_infos(1)
+    P = X.Context.params(m, tol=1e-300, max_restarts=0, mode="none", reorth=reorth)
+    ctx.target_project_solve(d, 1, 0, None, P, inf)
+    torch.cuda.synchronize()
+    i = X.infos_to_numpy(inf)[0]
+    assert i["status"] == X.ENOCONV and i["iters"] == m and i["restarts"] == 0
+    A = oracle.Operator(H, 1.0 / T, 0.5, mt)
+    b = oracle.rhs(A, mt)
+    ro = oracle.gmres(A, b, m=m, max_iters=m, tol=0.0, passes=passes)
+    x = cpu(xt)
+    assert np.abs(x - ro.x).max() <= 1e-11 * np.abs(ro.x).max()
+    assert abs(i["res_true"] - ro.res_true) <= 1e-12
+
+
+@pytest.mark.parametrize("H,m", [(64, 40), (128, 60)])
+def test_reorth_modes_agree(X, H, m):
+    """Projected and plain targets with one and with two Gram-Schmidt passes: both converge to
+    the tolerance within one iteration of each other and within two of the oracle's count."""
+    import torch
+    T = 100
+    ctx, bases, d, xt, ms, mt = target_setup(X, H, T, m, warm=True)
+    At = oracle.Operator(H, 1.0 / T, 0.5, mt)
+    bt = oracle.rhs(At, mt)
+    xs, _ = oracle.banded_solve(At, bt)
+    for mode in ("target_galerkin", "none"):
+        its = {}
+        for reorth in ("auto", "always"):
+            info = ctx.new_infos(1)
+            ctx.target_project_solve(d, 1, 1, bases.ptrs,
+                                     X.Context.params(m, mode=mode, reorth=reorth), info)
+            torch.cuda.synchronize()
+            inf = X.infos_to_numpy(info)[0]
+            x = cpu(xt)
+            assert inf["status"] == X.OK and inf["res_true"] <= 1e-8, (mode, reorth)
+            assert oracle.residual(At, bt, x) <= 1e-8 and varah_ok(At, bt, x, xs)
+            its[reorth] = int(inf["iters"])
+        assert abs(its["auto"] - its["always"]) <= 1, (mode, its)
+        if mode == "none":
+            for passes in (1, 2):
+                ro = oracle.gmres(At, bt, x0=mt, m=m, tol=1e-8, passes=passes)
+                assert abs(its["auto"] - ro.iters) <= 2, (passes, its, ro.iters)
+    with pytest.raises(X.XkpError):
+        P = X.Context.params(m, mode="none")
+        P.reorth = 2
+        ctx.target_project_solve(d, 1, 1, bases.ptrs, P, ctx.new_infos(1))

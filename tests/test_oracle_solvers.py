@@ -58,27 +58,62 @@ def brute_force_gmres(D, b, x0, j):
     return x0 + Q @ c
 
 
+@pytest.mark.parametrize("passes", [1, 2])
 @pytest.mark.parametrize("j", [1, 3, 8])
-def test_gmres_minimal_residual_property(olib, j):
+def test_gmres_minimal_residual_property(olib, j, passes):
     rng = np.random.default_rng(10 + j)
     n = 40
     D = 3 * np.eye(n) + rng.normal(size=(n, n)) / np.sqrt(n)     # nonsymmetric
     b = rng.normal(size=n)
     x0 = rng.normal(size=n)
-    r = oracle.gmres_dense(D, b, x0=x0, m=j, max_iters=j, tol=0.0)
+    r = oracle.gmres_dense(D, b, x0=x0, m=j, max_iters=j, tol=0.0, passes=passes)
     assert r.iters == j
     xb = brute_force_gmres(D, b, x0, j)
     assert np.linalg.norm(r.x - xb) <= 1e-10 * np.linalg.norm(xb)
 
 
-def test_gmres_stencil_minimal_residual(olib):
+@pytest.mark.parametrize("passes", [1, 2])
+def test_gmres_stencil_minimal_residual(olib, passes):
     A = rand_op(6, 7)
     D = oracle.dense(A)
     b = oracle.rhs(A, A.mt)
     for j in [2, 5]:
-        r = oracle.gmres(A, b, m=j, max_iters=j, tol=0.0)
+        r = oracle.gmres(A, b, m=j, max_iters=j, tol=0.0, passes=passes)
         xb = brute_force_gmres(D, b, np.zeros_like(b), j)
         assert np.linalg.norm(r.x - xb) <= 1e-10 * np.linalg.norm(xb)
+
+
+def test_one_pass_basis_loses_orthogonality_that_the_second_pass_restores(olib):
+    """With one modified Gram-Schmidt pass the Arnoldi basis loses orthogonality as the residual
+    falls (in inverse proportion to it), here completely; the second pass keeps V^T V = I to the
+    unit roundoff (the reason a kept basis gets two passes).  The GMRES residual still reaches
+    the roundoff level with one pass: GMRES with modified Gram-Schmidt is backward stable."""
+    rng = np.random.default_rng(5)
+    n, j = 60, 30
+    D = np.eye(n) + 0.3 * rng.normal(size=(n, n)) / np.sqrt(n)   # clustered spectrum
+    b = rng.normal(size=n)
+    r1 = oracle.gmres_dense(D, b, m=j, max_iters=j, tol=0.0, keep_basis=True, passes=1)
+    r2 = oracle.gmres_dense(D, b, m=j, max_iters=j, tol=0.0, keep_basis=True, passes=2)
+    o1 = np.abs(r1.V.T @ r1.V - np.eye(j + 1)).max()
+    o2 = np.abs(r2.V.T @ r2.V - np.eye(j + 1)).max()
+    assert o2 <= 1e-14 and o1 >= 1e-2, (o1, o2)
+    for r in (r1, r2):
+        assert np.abs(D @ r.V[:, :j] - r.V @ r.Hbar).max() <= 1e-13 * np.abs(D).max()
+        assert np.linalg.norm(b - D @ r.x) <= 1e-14 * np.linalg.norm(b)
+    # early in the cycle (residual 1e-5) one pass is still orthogonal to about u / residual
+    r1 = oracle.gmres_dense(D, b, m=10, max_iters=10, tol=0.0, keep_basis=True, passes=1)
+    assert np.abs(r1.V.T @ r1.V - np.eye(11)).max() <= 1e-9
+
+
+def test_one_pass_gmres_matches_two_on_the_stencil(olib):
+    """On the Fokker-Planck operator both variants take the same number of steps to 1e-8."""
+    for H, m, seed in [(16, 20, 1), (24, 30, 2), (32, 40, 3)]:
+        A = rand_op(H, seed, T=100)
+        b = oracle.rhs(A, A.mt)
+        r1 = oracle.gmres(A, b, m=m, tol=1e-8, passes=1)
+        r2 = oracle.gmres(A, b, m=m, tol=1e-8, passes=2)
+        assert r1.status == r2.status == oracle.OK
+        assert r1.iters == r2.iters and r1.res_true <= 1e-8 and r2.res_true <= 1e-8
 
 
 @pytest.mark.parametrize("H,m", [(8, 10), (16, 30)])
