@@ -155,7 +155,9 @@ def uneven_leg(args):
                     "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
                     "polish_m": r["polish_m"],
                     "wg_per_cu": None if tu is None else tu.wg_per_cu,
-                    "waves": None if tu is None else tu.waves}
+                    "waves": None if tu is None else tu.waves,
+                    "seed_waves": None if tu is None or b.seed_tuning is None
+                    else b.seed_tuning.waves}
         print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
               file=sys.stderr, flush=True)
         del b
@@ -185,6 +187,9 @@ def mixed_leg(args):
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                     "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"] and eok,
                     "polish_m": r["polish_m"],
+                    "waves": None if tu is None else tu.waves,
+                    "seed_waves": None if tu is None or b.seed_tuning is None
+                    else b.seed_tuning.waves,
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
                     "err_vs_fp64_max": float(f"{e.max():.3e}"),
                     "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
@@ -385,7 +390,7 @@ def main():
         ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m,
                    reorth=args.reorth)
         if not args.no_tune and not args.polish_m:
-            tunings[name] = ch.autotune()
+            tunings[name] = (ch.autotune(), ch.seed_tuning)
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name == "plain":
             launch_ms = target_call_ms(ch)
@@ -433,8 +438,9 @@ def main():
                        "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
                        "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
         "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu, "waves": t.waves,
-                         "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4)}
-                     for k, t in tunings.items()},
+                         "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4),
+                         "seed_waves": None if ts is None else ts.waves}
+                     for k, (t, ts) in tunings.items()},
         "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

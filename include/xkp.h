@@ -301,6 +301,20 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
                         int32_t n_bases, const void *const *bases, const xkp_params *params,
                         xkp_info *infos, xkp_tuning *out);
 
+/*
+ * Launch autotuner for seed calls: times xkp_seed_build on the given seeds (one representative
+ * timestep) for each kernel variant covering them and each workgroup count per compute unit,
+ * two timed calls each after one untimed call, and keeps the fastest candidate whose every seed
+ * converged; the variant and workgroup count are stored in the context (meant for a context
+ * that serves seed calls only: a seed is one workgroup on the chain's critical path, whose best
+ * workgroup size can differ from the targets').  out->polish_m is params->m.
+ * Side effects: the bases, seeds[i].x and infos hold the last candidate's results.  Synchronises
+ * the stream; must not be captured.  Returns XKP_ENOCONV if no candidate converged everywhere.
+ */
+xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds,
+                              void *const *bases, const xkp_params *params, xkp_info *infos,
+                              xkp_tuning *out);
+
 /* Static description of a status code. */
 const char *xkp_status_string(xkp_status s);
 

@@ -275,35 +275,25 @@ xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {
                              v->lds_vec_len(ctx->max_n), systems, n_sys, ctx->max_n));
 }
 
-xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
-                        int32_t n_bases, const void *const *bases, const xkp_params *params,
-                        xkp_info *infos, xkp_tuning *out) {
-    if (!ctx || !params || !out || n_targets < 1 || !targets || !infos) return XKP_EINVAL;
-    {
-        int nmax = 0, rmax = 0;
-        const Variant *v = nullptr;
-        xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
-        if (st != XKP_OK) return st;
-    }
-    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
-    const int m = params->m;
-    const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
-    int cand_m[3] = {m / 2, (3 * m) / 4, m};
-    for (int &c : cand_m) {
-        if (c < 8) c = 8;
-        if (c > m) c = m;
-    }
+// Shared timing loop of the autotuners: for each kernel variant covering nmax, each candidate
+// restart length and each workgroup count per compute unit, one untimed and two timed calls of
+// `call(P)`; keeps the fastest candidate whose every system ended with an accepted status.  The
+// chosen variant and workgroup count stay in the context.
+extern "C++" template <typename Call>
+static xkp_status tune_loop(xkp_ctx *ctx, int nmax, int nsys, xkp_info *infos,
+                            const xkp_params *params, const int *cand_m, int ncand, bool seeds,
+                            Call call, xkp_tuning *out) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
         hipEventDestroy(e0);
         return XKP_EDEVICE;
     }
-    std::vector<xkp_info> host(n_targets);
+    std::vector<xkp_info> host(nsys);
     const int saved_w = ctx->per_cu, saved_v = ctx->variant;
     xkp_status result = XKP_OK;
     float best = -1.f, def = -1.f;
-    int best_m = m, best_w = saved_w, best_v = saved_v, tried = 0;
+    int best_m = cand_m[ncand - 1], best_w = saved_w, best_v = saved_v, tried = 0;
     for (int vi = 0; vi < kNumVariants && result == XKP_OK; ++vi) {
         const Variant &var = kVariants[vi];
         if (!var.rmax_for(nmax)) continue;
@@ -314,25 +304,24 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
         }
         if (nb * ctx->cus > ctx->slots) nb = (ctx->slots + ctx->cus - 1) / ctx->cus;
         ctx->variant = vi;
-        for (int ci = 0; ci < 3 && result == XKP_OK; ++ci) {
+        for (int ci = 0; ci < ncand && result == XKP_OK; ++ci) {
             if (ci > 0 && cand_m[ci] == cand_m[ci - 1]) continue;
             for (int w = 1; w <= nb && result == XKP_OK; ++w) {
                 xkp_params P = *params;
-                P.polish_m = cand_m[ci];
+                if (!seeds) P.polish_m = cand_m[ci];
                 ctx->per_cu = w;
                 float ms = 0.f;
                 for (int rep = 0; rep < 3 && result == XKP_OK; ++rep) {
                     if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess)
                         result = XKP_EDEVICE;
-                    xkp_status st = xkp_target_project_solve(ctx, n_targets, targets, n_bases,
-                                                             bases, &P, infos);
+                    xkp_status st = call(P);
                     if (st != XKP_OK) result = st;
                 }
                 if (result != XKP_OK) break;
                 if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
                     hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
-                    hipMemcpy(host.data(), infos, sizeof(xkp_info) * n_targets,
+                    hipMemcpy(host.data(), infos, sizeof(xkp_info) * nsys,
                               hipMemcpyDeviceToHost) != hipSuccess) {
                     result = XKP_EDEVICE;
                     break;
@@ -341,8 +330,8 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
                 ++tried;
                 bool ok = true;
                 for (const xkp_info &i : host)
-                    ok = ok && (i.status == XKP_OK || i.status == XKP_ESINGULAR);
-                if (vi == 0 && cand_m[ci] == m && w == nb) def = ms;
+                    ok = ok && (i.status == XKP_OK || (!seeds && i.status == XKP_ESINGULAR));
+                if (vi == 0 && ci == ncand - 1 && w == nb) def = ms;
                 if (ok && (best < 0.f || ms < best)) {
                     best = ms;
                     best_m = cand_m[ci];
@@ -368,6 +357,52 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     ctx->per_cu = best_w;
     ctx->variant = best_v;
     return XKP_OK;
+}
+
+xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
+                        int32_t n_bases, const void *const *bases, const xkp_params *params,
+                        xkp_info *infos, xkp_tuning *out) {
+    if (!ctx || !params || !out || n_targets < 1 || !targets || !infos) return XKP_EINVAL;
+    {
+        int nmax = 0, rmax = 0;
+        const Variant *v = nullptr;
+        xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
+        if (st != XKP_OK) return st;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int m = params->m;
+    const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
+    int cand_m[3] = {m / 2, (3 * m) / 4, m};
+    for (int &c : cand_m) {
+        if (c < 8) c = 8;
+        if (c > m) c = m;
+    }
+    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 3, false,
+                     [&](const xkp_params &P) {
+                         return xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
+                                                         &P, infos);
+                     },
+                     out);
+}
+
+xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds,
+                              void *const *bases, const xkp_params *params, xkp_info *infos,
+                              xkp_tuning *out) {
+    if (!ctx || !params || !out || n_seeds < 1 || !seeds || !bases || !infos) return XKP_EINVAL;
+    {
+        int nmax = 0, rmax = 0;
+        const Variant *v = nullptr;
+        xkp_status st = check_call(ctx, n_seeds, seeds, params, &nmax, &rmax, &v);
+        if (st != XKP_OK) return st;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
+    const int cand_m[1] = {params->m};
+    return tune_loop(ctx, nmax, n_seeds, infos, params, cand_m, 1, true,
+                     [&](const xkp_params &P) {
+                         return xkp_seed_build(ctx, n_seeds, seeds, bases, &P, infos);
+                     },
+                     out);
 }
 
 size_t xkp_cnn_param_count(int32_t k) {

@@ -231,7 +231,9 @@ class Batch:
     def autotune(self, steps=2):
         """Advance `steps` timesteps eagerly, then time the target call of the next timestep
         over the candidates of xkp_autotune on its real inputs; the chosen polish restart length
-        goes into the params, the workgroup count into the context.  Resets the chain."""
+        goes into the params, the workgroup count into the context.  With a seed context of
+        its own (pipelined chains), the seed call of that timestep is tuned too
+        (xkp_autotune_seeds; the result is in `self.seed_tuning`).  Resets the chain."""
         import torch
         self.reset()
         for _ in range(steps):
@@ -239,9 +241,15 @@ class Batch:
         par = self.step_no & 1
         bases = self.bases.ptrs[par * self.S:(par + 1) * self.S]
         inf_s, inf_t = self._info_slices(self.step_no % self.T)
+        self.seed_tuning = None
         if self.with_seeds:
             self.ctx_seed.build_rhs(self.seed_desc[par], self.S)
-            self.ctx_seed.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
+            if self.ctx_seed is not self.ctx:
+                torch.cuda.synchronize(self.dev)
+                self.seed_tuning = self.ctx_seed.autotune_seeds(self.seed_desc[par], self.S,
+                                                                bases, self.params, inf_s)
+            else:
+                self.ctx_seed.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
         self.ctx.build_rhs(self.tgt_desc[par], self.N)
         torch.cuda.synchronize(self.dev)
         t = self.ctx.autotune(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)

@@ -78,6 +78,8 @@ def load():
         lib.xkp_build_rhs.argtypes = [P, ct.c_int32, P]
         lib.xkp_autotune.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(Params), P,
                                      ct.POINTER(Tuning)]
+        lib.xkp_autotune_seeds.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P,
+                                           ct.POINTER(Tuning)]
         lib.xkp_cnn_param_count.argtypes = [ct.c_int32]
         lib.xkp_cnn_param_count.restype = ct.c_size_t
         lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
@@ -95,7 +97,7 @@ def load():
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
-                  "xkp_autotune", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
+                  "xkp_autotune", "xkp_autotune_seeds", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
@@ -233,6 +235,15 @@ class Context:
         t = Tuning()
         _check(load().xkp_autotune(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
                                    ct.byref(params), _ptr(infos), ct.byref(t)), "xkp_autotune")
+        return t
+
+    def autotune_seeds(self, systems, n_sys, bases_ptrs, params, infos) -> Tuning:
+        """Times the seed call over the kernel variants and workgroup counts (host-synchronous);
+        the choice is kept by the context (one that serves seed calls)."""
+        t = Tuning()
+        _check(load().xkp_autotune_seeds(self._h, n_sys, _ptr(systems), _ptr(bases_ptrs),
+                                         ct.byref(params), _ptr(infos), ct.byref(t)),
+               "xkp_autotune_seeds")
         return t
 
     def learned_solve(self, systems, n_sys, n_bases, bases_ptrs, params, alpha, alpha_ld,

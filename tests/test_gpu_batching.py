@@ -278,6 +278,25 @@ def test_autotune_picks_a_converging_candidate(X):
     assert np.all(ch.verify_last() <= 1e-8 * (1 + 1e-6))
 
 
+def test_seed_autotune_keeps_results(X):
+    """xkp_autotune_seeds on the seeds of an uneven batch: the chosen workgroup size leaves the
+    seed iterations within one of the default launch's and the chain still verifies."""
+    T, m = 6, 20
+    b, groups = uneven_batch(T, m)
+    b.run()
+    s_ref, _ = b.all_infos()
+    t = b.autotune(steps=2)
+    st = b.seed_tuning
+    assert st is not None and st.waves in (4, 8, 16) and st.wg_per_cu >= 1
+    assert st.n_tried >= 2 and 0 < st.ms_best <= st.ms_default * 1.000001
+    assert st.polish_m == m and t.polish_m in (10, 15, 20)
+    b.run()
+    s_inf, t_inf = b.all_infos()
+    assert np.all(s_inf["status"] == X.OK) and np.all(t_inf["status"] == X.OK)
+    assert np.abs(s_inf["iters"].astype(int) - s_ref["iters"].astype(int)).max() <= 1
+    assert np.all(b.verify_last() <= 1e-8 * (1 + 1e-6))
+
+
 def test_uneven_mixed_precision_chain(X):
     """Mixed precision over an uneven two-size, two-channel batch: every solve meets the FP64
     tolerance and the states stay within the chain bound of the FP64 oracle."""
