@@ -29,8 +29,9 @@
  *     order; they share the context's workspace, so two contexts are needed for overlap.
  *   - All solver arithmetic is FP64 in XKP_FP64 mode.  In XKP_MIXED mode the operator inside
  *     the targets' GMRES cycles is applied in FP32 (FP32 coefficients, operands rounded to FP32,
- *     FP32 row sums); the Krylov vectors are still orthogonalised, rotated and updated in FP64,
- *     every restart recomputes the true residual b - A x with the FP64 operator, and
+ *     FP32 row sums) and their (discarded) Krylov basis is stored in FP32 (each vector rounded
+ *     once when formed); the Gram-Schmidt products, rotations and updates run in FP64 on those
+ *     values, every restart recomputes the true residual b - A x with the FP64 operator, and
  *     convergence is judged on it, so results meet params->tol in FP64.  A cycle ends early
  *     once its residual estimate has fallen by 1e-5 (the reduction the FP32 operator can
  *     deliver).  Seeds keep the FP64 operator (a seed is one system per timestep on the

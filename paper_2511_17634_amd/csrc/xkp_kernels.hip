@@ -172,6 +172,31 @@ __device__ __forceinline__ void load_buf(rsrc_t b, double (&r)[RMAX]) {
     }
 }
 
+// FP32 columns (the discarded Krylov basis of mixed-precision solves): a row pair is one 8-byte
+// access; values are widened to FP64 on load and rounded to FP32 on store.
+template <int RMAX>
+__device__ __forceinline__ void load_buf_f32(rsrc_t b, double (&r)[RMAX]) {
+    const unsigned lo = threadIdx.x * 8u;
+#pragma unroll
+    for (int k = 0; k < RMAX; k += 2) {
+        const f32x2_t v = bldf2(b, lo, (unsigned)(k * kNT * 4));
+        r[k] = (double)v[0];
+        r[k + 1] = (double)v[1];
+    }
+}
+
+template <int RMAX>
+__device__ __forceinline__ void store_col_f32(float *__restrict__ v, int ldv,
+                                              const double (&r)[RMAX]) {
+    const rsrc_t b = mkbuf32(v, ldv);
+    const unsigned lo = threadIdx.x * 8u;
+#pragma unroll
+    for (int k = 0; k < RMAX; k += 2)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(u32x2, f32x2_t{(float)r[k], (float)r[k + 1]}), b, lo,
+            (unsigned)(k * kNT * 4), 0);
+}
+
 template <int RMAX>
 __device__ __forceinline__ void load_col(const double *__restrict__ v, int ldv, double (&r)[RMAX]) {
     load_buf<RMAX>(mkbuf(v, ldv), r);
@@ -193,14 +218,24 @@ __device__ __forceinline__ void store_col(double *__restrict__ v, int ldv, const
 // a zero-size descriptor, which returns zeros without touching memory -- so every path through
 // the loop has the same loads outstanding and the waits stay partial.  f(q, column) must not
 // access global memory.
-template <int RMAX, int D, typename F>
-__device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int ldv, int ncols,
+template <int RMAX, bool F32>
+__device__ __forceinline__ void load_col_any(const void *V, int c, int ldv, bool live,
+                                             double (&r)[RMAX]) {
+    if constexpr (F32)
+        load_buf_f32<RMAX>(mkbuf32((const float *)V + (size_t)c * ldv, live ? ldv : 0), r);
+    else
+        load_buf<RMAX>(mkbuf((const double *)V + (size_t)c * ldv, live ? ldv : 0), r);
+}
+
+// F32: the columns are stored in FP32 (mixed-precision Krylov basis).
+template <int RMAX, int D, bool F32 = false, typename F>
+__device__ __forceinline__ void sweep_cols(const void *__restrict__ V, int ldv, int ncols,
                                            int nvisit, F &&f) {
     double buf[D][RMAX];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int c = d < ncols ? d : d % ncols;
-        load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, d < nvisit ? ldv : 0), buf[d]);
+        load_col_any<RMAX, F32>(V, c, ldv, d < nvisit, buf[d]);
     }
     for (int q0 = 0; q0 < nvisit; q0 += D) {
 #pragma unroll
@@ -209,7 +244,7 @@ __device__ __forceinline__ void sweep_cols(const double *__restrict__ V, int ldv
             if (q < nvisit) f(q, buf[d]);
             const int qn = q + D;
             const int c = qn < ncols ? qn : (qn < 2 * ncols ? qn - ncols : 0);
-            load_buf<RMAX>(mkbuf(V + (size_t)c * ldv, qn < nvisit ? ldv : 0), buf[d]);
+            load_col_any<RMAX, F32>(V, c, ldv, qn < nvisit, buf[d]);
         }
     }
 }
@@ -414,8 +449,10 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
     const int n = o.n, m = (keep || P.polish_m <= 0) ? P.m : P.polish_m;
     const int tid = threadIdx.x, ldv = ldv_for(o.n);
     BlockRed br{L.red, 0};
-    // mixed precision: FP32 operator inside the Krylov cycles, FP64 everywhere else
+    // mixed precision: FP32 operator inside the Krylov cycles and the (discarded) Krylov basis
+    // stored in FP32; Gram-Schmidt, rotations, updates and the restart residual in FP64
     constexpr bool mixed = MIXED;
+    constexpr bool vf32 = MIXED;   // mixed-precision solves never keep their basis
     // a mixed-precision seed (solved with the FP64 operator) also writes the BF16 basis copy
     unsigned short *Vb = (keep && P.precision == XKP_MIXED)
                              ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
@@ -460,10 +497,14 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
         if (beta > P.tol * bnorm) {
             for (;;) {
                 double *V = first ? Vfirst : Vws;
-                // v_0 = r / beta; the LDS copy feeds the stencil
+                // v_0 = r / beta (as stored); the LDS copy feeds the stencil
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k) cur[k] = cur[k] / beta;
-                store_col<RMAX>(V, ldv, cur);
+                for (int k = 0; k < RMAX; ++k)
+                    cur[k] = vf32 ? (double)(float)(cur[k] / beta) : cur[k] / beta;
+                if constexpr (vf32)
+                    store_col_f32<RMAX>((float *)V, ldv, cur);
+                else
+                    store_col<RMAX>(V, ldv, cur);
                 if (Vb && first) store_col_bf16<RMAX>(Vb, ldv, cur);
                 store_rows_lds<RMAX>(L.vbuf, cur);
                 if (first) beta_first = beta;
@@ -497,7 +538,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     // column visits while the basis is kept (the second pass re-orthogonalises
                     // and completes h_{i,j}), else one pass
                     const int nc = j + 1, nvis = two_pass ? 2 * nc : nc;
-                    sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, nc, nvis,
+                    sweep_cols<RMAX, Depth<RMAX>::value, vf32>(V, ldv, nc, nvis,
                         [&](int q, const double(&col)[RMAX]) {
                         const int i = q < nc ? q : q - nc;
                         double part = 0.0;
@@ -546,8 +587,14 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     const double hn = sqrt(br.sum(dot_rows<RMAX>(w, w)));
                     const bool brk = !(hn > 1e-14 * wn0);
 #pragma unroll
-                    for (int k = 0; k < RMAX; ++k) w[k] = brk ? 0.0 : w[k] / hn;
-                    store_col<RMAX>(V + (size_t)(j + 1) * ldv, ldv, w);
+                    for (int k = 0; k < RMAX; ++k) {
+                        w[k] = brk ? 0.0 : w[k] / hn;
+                        if constexpr (vf32) w[k] = (double)(float)w[k];
+                    }
+                    if constexpr (vf32)
+                        store_col_f32<RMAX>((float *)V + (size_t)(j + 1) * ldv, ldv, w);
+                    else
+                        store_col<RMAX>(V + (size_t)(j + 1) * ldv, ldv, w);
                     if (Vb && first) store_col_bf16<RMAX>(Vb + (size_t)(j + 1) * ldv, ldv, w);
                     store_rows_lds<RMAX>(L.vbuf, w);
                     if (keep && first) {
@@ -581,7 +628,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 lds_barrier();
                 // x += V_k y
                 load_rows<RMAX>(s.x, n, w);
-                sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, kk, kk,
+                sweep_cols<RMAX, Depth<RMAX>::value, vf32>(V, ldv, kk, kk,
                     [&](int c, const double(&col)[RMAX]) {
                     const double yc = L.yv[c];
 #pragma unroll
