@@ -37,6 +37,7 @@
 #define XKP_DEPTH32 2
 #endif
 
+
 namespace xkp {
 namespace XKP_VARIANT {
 
@@ -518,21 +519,12 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 const bool two_pass = (keep && first) || P.reorth == XKP_REORTH_ALWAYS;
                 int kk = 0;
                 for (int j = 0; j < m; ++j) {
-                    // With many rows per thread the Krylov vector w lives in the LDS copy of
-                    // v_j (free once the operator has read it) instead of registers.
-                    constexpr bool kWL = RMAX >= 32;
-                    double *wl = L.vbuf + tid;
                     if constexpr (mixed)
                         stencil_lds_f32<RMAX>(L.vbuf, C, o, w);
                     else
                         stencil_lds<RMAX>(L.vbuf, C, o, w);
                     ++iters;
                     const double wsq = dot_rows<RMAX>(w, w);
-                    if constexpr (kWL) {
-                        lds_barrier();   // every thread has read its neighbours of v_j
-#pragma unroll
-                        for (int k = 0; k < RMAX; ++k) wl[k * kNT] = w[k];
-                    }
                     double wn0 = 0.0, t = 0.0;
                     // modified Gram-Schmidt over v_0..v_j: two passes as one sweep of 2(j+1)
                     // column visits while the basis is kept (the second pass re-orthogonalises
@@ -541,13 +533,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     sweep_cols<RMAX, Depth<RMAX>::value, vf32>(V, ldv, nc, nvis,
                         [&](int q, const double(&col)[RMAX]) {
                         const int i = q < nc ? q : q - nc;
-                        double part = 0.0;
-                        if constexpr (kWL) {
-#pragma unroll
-                            for (int k = 0; k < RMAX; ++k) part += wl[k * kNT] * col[k];
-                        } else {
-                            part = dot_rows<RMAX>(w, col);
-                        }
+                        const double part = dot_rows<RMAX>(w, col);
                         double d;
                         if (q == 0) {
                             double two[2] = {part, wsq};
@@ -557,13 +543,8 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                         } else {
                             d = br.sum(part);
                         }
-                        if constexpr (kWL) {
 #pragma unroll
-                            for (int k = 0; k < RMAX; ++k) wl[k * kNT] -= d * col[k];
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
-                        }
+                        for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
                         if (q < nvis - nc) {
                             if (tid == 0) L.h1[i] = d;
                         } else {
@@ -580,10 +561,6 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                             }
                         }
                     });
-                    if constexpr (kWL) {
-#pragma unroll
-                        for (int k = 0; k < RMAX; ++k) w[k] = wl[k * kNT];
-                    }
                     const double hn = sqrt(br.sum(dot_rows<RMAX>(w, w)));
                     const bool brk = !(hn > 1e-14 * wn0);
 #pragma unroll
