@@ -46,11 +46,12 @@ TRAFFIC = {"csrc_digest": "5f26416d6960b8f1", "fetch_kib": 333210.5, "write_kib"
 
 
 def csrc_digest():
-    """Digest of the HIP sources, to tell whether stored counter figures still apply."""
+    """Digest of the sources the solve kernel is built from, to tell whether stored counter
+    figures still apply."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2511_17634_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in ("xkp_device.h", "xkp_internal.h", "xkp_kernels.hip"):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
@@ -182,6 +183,19 @@ def mixed_leg(args):
                   reorth=args.reorth)
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.mixed_steps, 1, graph)
+        roof = None
+        if name == "plain_fp64":
+            # the same kernel roofline as the 64x64 record, here on the HBM-bound size
+            lm = target_call_ms(b)
+            n3 = H3 * H3
+            passes = 1 if args.reorth == "auto" else 2
+            byts = gmres_bytes(n3, r["polish_m"], r["iters"], r["restarts"], passes) / cfg3.T
+            ls = sum(lm) / 1e3 / cfg3.T
+            roof = {"kernel": f"solve_kernel (plain GMRES, {len(t3)} systems per launch)",
+                    "bound": "hbm", "achieved": round(byts / ls / 1e9, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(byts / ls / 1e9 / HBM_PEAK_GBS, 4),
+                    "bytes_per_launch": int(byts), "launch_ms": round(ls * 1e3, 4)}
         e, eok = err_vs_fp64(b)
         mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
@@ -193,6 +207,8 @@ def mixed_leg(args):
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
                     "err_vs_fp64_max": float(f"{e.max():.3e}"),
                     "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
+        if roof is not None:
+            mx[name]["roofline"] = roof
         print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
               f"mean iters {r['iters_mean']:.1f}, max err vs fp64 {e.max():.2e}",
               file=sys.stderr, flush=True)
