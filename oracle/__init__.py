@@ -71,6 +71,7 @@ def lib():
         _lib.xo_gmres.argtypes = [ct.POINTER(_Op), P, P] + gm
         _lib.xo_gmres_dense.argtypes = [ct.c_int, P, P, P] + gm
         _lib.xo_project.argtypes = [ct.POINTER(_Op), P, P, ct.c_int, P, P, ct.c_int, ct.c_int, P, P]
+        _lib.xo_accumulate.argtypes = [ct.c_int, ct.c_int, P, P, ct.c_int, ct.c_int, P]
     return _lib
 
 
@@ -244,3 +245,19 @@ def project(At: Operator, b, V, Hbar, mode=TARGET_GALERKIN, x_base=None):
     st = lib().xo_project(At.ref, _p(b), _p(xb), k, _p(Vc), _p(Hc), k + 1, mode, _p(x0),
                           _p(alpha))
     return x0, alpha[:k], st
+
+
+def accumulate(sources, per_source, cap):
+    """Krylov subspace expansion over an image cycle: `sources` is a list of (n, k_s) arrays of
+    orthonormal columns (the seeds' first-cycle bases V_k, in cycle order); returns the (n, kd)
+    orthonormal basis gathered from them (two modified Gram-Schmidt passes per column, norm left
+    > 1e-8 to append, at most per_source columns per source and cap in total)."""
+    srcs = [np.asfortranarray(_f64(V)) for V in sources]
+    n = srcs[0].shape[0]
+    if any(V.shape[0] != n for V in srcs):
+        raise ValueError("every source needs the same number of rows")
+    ptrs = (ct.c_void_p * len(srcs))(*[V.ctypes.data for V in srcs])
+    ks = (ct.c_int * len(srcs))(*[V.shape[1] for V in srcs])
+    out = np.zeros((cap, n))                      # row c = column c
+    kd = lib().xo_accumulate(n, len(srcs), ptrs, ks, int(per_source), int(cap), _p(out))
+    return out[:kd].T.copy()

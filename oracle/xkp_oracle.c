@@ -22,6 +22,9 @@
  *       Hessenberg matrix are returned: that is the per-timestep seed basis V_a^n of Section 3,
  *       Phase 1.
  *   xo_project  -- Section 3, Phase 2: A_proj alpha = b_proj in the seed basis, x0 = V alpha.
+ *   xo_accumulate  -- Krylov subspace expansion over an image cycle (Experiment 2: a new seed
+ *       every 50 images, subspace dimension capped): the seeds' basis vectors, in order,
+ *       orthogonalised against the vectors gathered so far and appended.
  *
  * Conventions: a grid is square (H == W, h = 1/H, Section 2.3 sets dx = dy = h); unknown
  * p = i*H + j with i the x (width) index and j the y (height) index; values outside the grid
@@ -520,4 +523,40 @@ int xo_project(const xo_op *At, const double *b, const double *x_base, int k, co
     }
     free(rb); free(w); free(Ap); free(z);
     return status;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/*
+ * Krylov subspace accumulation over an image cycle.  Sources s = 0..nsrc-1 in order; source s
+ * holds ks[s] orthonormal columns (column-major, leading dimension n) at src[s].  Each source
+ * column c = 0, 1, ... is made orthogonal to the columns gathered so far by two passes of
+ * modified Gram-Schmidt (Saad Alg. 6.2, repeated); if the norm left exceeds 1e-8 the column is
+ * normalised and appended.  At most per_source columns are appended from one source and cap in
+ * total.  out: n x cap, column-major, ld n.  Returns the number of columns gathered.
+ */
+int xo_accumulate(int n, int nsrc, const double *const *src, const int *ks, int per_source,
+                  int cap, double *out)
+{
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    int kd = 0;
+    for (int s = 0; s < nsrc && kd < cap; ++s) {
+        int taken = 0;
+        for (int c = 0; c < ks[s] && taken < per_source && kd < cap; ++c) {
+            memcpy(w, src[s] + (size_t)c * n, sizeof(double) * (size_t)n);
+            for (int pass = 0; pass < 2; ++pass)
+                for (int i = 0; i < kd; ++i) {
+                    const double *vi = out + (size_t)i * n;
+                    const double d = dot(n, w, vi);
+                    for (int p = 0; p < n; ++p) w[p] -= d * vi[p];
+                }
+            const double nw = nrm2(n, w);
+            if (nw > 1e-8) {
+                for (int p = 0; p < n; ++p) out[(size_t)kd * n + p] = w[p] / nw;
+                ++kd;
+                ++taken;
+            }
+        }
+    }
+    free(w);
+    return kd;
 }
