@@ -138,13 +138,21 @@ typedef struct {
  *   then             Vb: (m+1) columns of ldv bf16 values (XKP_MIXED copies of V, 256-aligned;
  *                    header field bf16 = 1 when written).  A mixed-precision target-Galerkin
  *                    projection on a basis without it gives that target XKP_EINVAL.
+ * An accumulated basis (xkp_basis_accumulate) has the same layout with k orthonormal columns,
+ * no Hessenberg matrix and kind = XKP_BASIS_ACCUMULATED.
  */
+typedef enum {
+    XKP_BASIS_ARNOLDI = 0,     /* a seed's first GMRES cycle: V_{k+1} and Hbar_k             */
+    XKP_BASIS_ACCUMULATED = 1  /* orthonormal columns gathered from several seeds, no Hbar   */
+} xkp_basis_kind;
+
 typedef struct {
     int32_t n, m, k, status;
     double beta;          /* ||r0|| of the seed's first cycle                               */
     int32_t ldv;          /* leading dimension of V in doubles                              */
     int32_t bf16;         /* 1 if the BF16 copy Vb was written (seed built with XKP_MIXED)  */
-    int32_t pad[56];
+    int32_t kind;         /* xkp_basis_kind                                                 */
+    int32_t pad[55];
 } xkp_basis_header;
 
 typedef struct xkp_ctx xkp_ctx;
@@ -194,7 +202,9 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
  * bases[targets[i].basis_id]; x0 = x_base + V_k alpha; then GMRES(m) from x0 to params->tol.
  * The result goes to targets[i].x.  Mode XKP_PROJ_NONE skips the projection (plain GMRES from
  * x_base) and ignores `bases` (may be NULL).  A basis with a different n than the target, or
- * a basis_id outside [0, n_bases), sets that target's status to XKP_EINVAL.
+ * a basis_id outside [0, n_bases), sets that target's status to XKP_EINVAL; so does a seed mode
+ * (XKP_PROJ_SEED_GALERKIN, XKP_PROJ_SEED_LSQ) on an accumulated basis, which has no Hessenberg
+ * matrix.
  */
 xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
                                     int32_t n_bases, const void *const *bases,
@@ -209,8 +219,9 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
  * a = argmin || beta * alpha_scale * zeta - Hbar_k a || (Givens least squares).  If
  * ||b - A x0_L|| / ||b|| (FP64) <= gate the polish starts from x0_L (info.guess_source = 2);
  * otherwise the target falls back to xkp_target_project_solve's path for params->mode
- * (projection then polish, or plain GMRES from x_base for XKP_PROJ_NONE).  One persistent
- * launch, as xkp_target_project_solve.
+ * (projection then polish, or plain GMRES from x_base for XKP_PROJ_NONE); so does a target on
+ * an accumulated basis (no Hessenberg matrix).  One persistent launch, as
+ * xkp_target_project_solve.
  */
 xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
                              int32_t n_bases, const void *const *bases, const xkp_params *params,
@@ -220,8 +231,8 @@ xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *
 /* kind 0: alpha[i][c] = v_c . x_i (FP64) for c < k of the basis bases[systems[i].basis_id], 0
  * for k <= c < m_out (1 <= m_out <= 64): the coordinates of systems[i].x in the seed subspace.
  * kind 1: alpha[i][r] = (Hbar_k (V_k^T x_i))_r / beta for r <= k, 0 past (m_out <= 65): the
- * residual coordinates a learned guess predicts (xkp_learned_solve).  A descriptor or basis
- * that does not fit writes NaN. */
+ * residual coordinates a learned guess predicts (xkp_learned_solve; an Arnoldi basis only).
+ * A descriptor or basis that does not fit writes NaN. */
 xkp_status xkp_basis_coeffs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems,
                             int32_t n_bases, const void *const *bases, int32_t m_out,
                             int32_t kind, double *alpha);
@@ -275,6 +286,30 @@ xkp_status xkp_cnn_backward(xkp_ctx *ctx, int32_t batch, int32_t k, const float 
  * t >= 1 the step number (bias correction). */
 xkp_status xkp_cnn_adam(xkp_ctx *ctx, int32_t count, float *params, const float *grad, float *m,
                         float *v, int32_t t, float lr, float beta1, float beta2, float eps);
+
+/*
+ * Krylov subspace accumulation over an image cycle (Section 3: the seed basis V^n of each
+ * timestep is reused for the targets; Experiment 2: a new seed every 50 images expands the
+ * subspace, capped at a vectors).  For j = 0..n_src-1, out_bases[j] receives the orthonormal
+ * basis gathered from the first-cycle bases src_bases[0..j], in that order: each source's
+ * columns v_0, v_1, ... (its Krylov order) are orthogonalised by two passes of modified
+ * Gram-Schmidt against the columns gathered so far and appended, normalised, when the norm
+ * left exceeds 1e-8; at most per_source columns are appended per source and cap in total.
+ *   n:          unknowns of every source (grid H x H); sources with another n, a missing basis
+ *               or an accumulated kind give out_k[j] = -1 and leave out_bases[j] unset
+ *   src_bases:  device array of n_src pointers to seed bases (xkp_seed_build results)
+ *   out_bases:  device array of n_src pointers to caller buffers of xkp_basis_bytes(n, cap)
+ *               bytes; header n, m = cap, k = columns gathered, ldv, bf16 = 1 (the BF16 copy is
+ *               written), kind = XKP_BASIS_ACCUMULATED.  Only the target-Galerkin projection
+ *               (FP64 or mixed, with params->m = cap) and xkp_basis_coeffs kind 0 accept it.
+ *   out_k:      device array of n_src int32 (columns gathered), or NULL
+ * Returns XKP_EINVAL for null arrays, n_src < 1, per_source < 1, cap < 1, cap above the
+ * context's max_m or n above its max_n.  Enqueued on the context's stream; out_j is computed
+ * from scratch by workgroup j (the sources are read, never written).
+ */
+xkp_status xkp_basis_accumulate(xkp_ctx *ctx, int32_t n, int32_t n_src,
+                                const void *const *src_bases, void *const *out_bases,
+                                int32_t per_source, int32_t cap, int32_t *out_k);
 
 /* Outcome of xkp_autotune. */
 typedef struct {

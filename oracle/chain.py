@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import TARGET_GALERKIN, Operator, banded_solve, gmres, project, residual, rhs
+from . import TARGET_GALERKIN, Operator, accumulate, banded_solve, gmres, project, residual, rhs
 
 
 @dataclass
@@ -82,4 +82,49 @@ def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
         mt = new
         st.iters.append(it_row); st.restarts.append(rs_row); st.status.append(stt_row)
         st.res_true.append(res_row); st.guess_res.append(g_row)
+    return ms, mt, st
+
+
+def run_cycle_chain(blocks, H, T, m, per_source, g=0.5, tol=1e-8, steps=None,
+                    max_restarts=1000):
+    """The image-cycle protocol (Experiment 2): `blocks` is a list of (seed_m0 (n,), targets_m0
+    (N_g, n)); per timestep every block's seed is solved (first-cycle basis kept, two
+    Gram-Schmidt passes), the basis of block g is gathered from the seeds of blocks 0..g
+    (`accumulate`, at most per_source columns each, m in total), and block g's targets are
+    projected on it (target Galerkin) and polished by GMRES(m) with one pass.
+    Returns (seed states, target states per block, stats with iters[step][target])."""
+    dt = 1.0 / T
+    ms = [np.array(s0, dtype=np.float64).reshape(-1) for s0, _ in blocks]
+    mt = [np.array(t0, dtype=np.float64).reshape(len(t0), -1) for _, t0 in blocks]
+    st = ChainStats()
+    for _ in range(T if steps is None else steps):
+        srcs, new_s = [], []
+        for b in range(len(blocks)):
+            As = Operator(H, dt, g, ms[b])
+            sr = gmres(As, rhs(As, ms[b]), m=m, tol=tol, keep_basis=True,
+                       max_restarts=max_restarts)
+            srcs.append(sr.V[:, :sr.basis_dim])
+            new_s.append(sr.x)
+            st.seed_iters.append(sr.iters)
+        it_row, res_row, g_row = [], [], []
+        new_t = []
+        for b in range(len(blocks)):
+            V = accumulate(srcs[:b + 1], per_source, m)
+            k = V.shape[1]
+            Vp = np.concatenate([V, np.zeros((V.shape[0], 1))], axis=1)
+            out = np.empty_like(mt[b])
+            for t in range(mt[b].shape[0]):
+                At = Operator(H, dt, g, mt[b][t])
+                bt = rhs(At, mt[b][t])
+                x0, _, _ = project(At, bt, Vp, np.zeros((k + 1, k)), mode=TARGET_GALERKIN)
+                g_row.append(residual(At, bt, x0))
+                r = gmres(At, bt, x0=x0, m=m, tol=tol, max_restarts=max_restarts, passes=1)
+                out[t] = r.x
+                it_row.append(r.iters)
+                res_row.append(r.res_true)
+            new_t.append(out)
+        ms, mt = new_s, new_t
+        st.iters.append(it_row)
+        st.res_true.append(res_row)
+        st.guess_res.append(g_row)
     return ms, mt, st

@@ -35,13 +35,13 @@ struct Variant {
     decltype(&xkp::v512::launch_residual) residual;
     decltype(&xkp::v512::launch_rhs) rhs;
     decltype(&xkp::v512::launch_apply) apply;
+    decltype(&xkp::v512::launch_accum) accum;
 };
 #define XKP_VARIANT_TABLE(NS)                                                          \
     Variant {                                                                          \
         xkp::NS::threads, xkp::NS::rmax_for, xkp::NS::lds_vec_len, xkp::NS::solve_per_cu, \
             xkp::NS::launch_solve, xkp::NS::launch_coeffs, xkp::NS::launch_residual,   \
-            xkp::NS::launch_rhs,                                                       \
-            xkp::NS::launch_apply                                                      \
+            xkp::NS::launch_rhs, xkp::NS::launch_apply, xkp::NS::launch_accum          \
     }
 // Kernel variants by workgroup size: 8 wave64s (2, 8 or 32 rows per thread for up to 1024, 4096,
 // 16384 unknowns), 16 (4 or 16 rows per thread for up to 4096, 16384) and 4 (4 or 16 rows per
@@ -253,6 +253,19 @@ xkp_status xkp_residual(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, 
     const Variant *v = choose(ctx->max_n);
     return from_hip(v->residual(ctx->stream, grid, v->rmax_for(ctx->max_n),
                                 v->lds_vec_len(ctx->max_n), systems, n_sys, rel_res, ctx->max_n));
+}
+
+xkp_status xkp_basis_accumulate(xkp_ctx *ctx, int32_t n, int32_t n_src,
+                                const void *const *src_bases, void *const *out_bases,
+                                int32_t per_source, int32_t cap, int32_t *out_k) {
+    if (!ctx || !src_bases || !out_bases || n_src < 1 || per_source < 1 || cap < 1 ||
+        cap > ctx->max_m || n < 1 || n > ctx->max_n)
+        return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const Variant *v = choose(n);
+    if (!v) return XKP_EINVAL;
+    return from_hip(v->accum(ctx->stream, v->rmax_for(n), n, n_src, src_bases, out_bases,
+                             per_source, cap, out_k));
 }
 
 xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {

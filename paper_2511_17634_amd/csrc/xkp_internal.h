@@ -68,6 +68,8 @@ struct Learned {
                           int nmax);                                                             \
     hipError_t launch_apply(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys, \
                             int nsys, int nmax);                                                 \
+    hipError_t launch_accum(hipStream_t st, int rmax, int n, int nsrc, const void *const *srcs,  \
+                            void *const *outs, int per_source, int cap, int *out_k);             \
     }
 
 XKP_DECLARE_VARIANT(v512)

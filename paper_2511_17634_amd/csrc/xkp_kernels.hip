@@ -643,6 +643,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
             hdr->beta = beta_first;
             hdr->ldv = ldv;
             hdr->bf16 = Vb ? 1 : 0;
+            hdr->kind = XKP_BASIS_ARNOLDI;
         }
         int st = status;
         if (st == XKP_OK && (flags & kTarget) && prestatus == XKP_ESINGULAR) st = XKP_ESINGULAR;
@@ -943,6 +944,8 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
         if (ok) {
             hdr = (const xkp_basis_header *)bases[s.basis_id];
             ok = hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m;
+            // the seed modes use the Hessenberg matrix: an accumulated basis has none
+            if (ok && P.mode != XKP_PROJ_TARGET_GALERKIN) ok = hdr->kind == XKP_BASIS_ARNOLDI;
             // the mixed target-Galerkin contraction needs the seed's BF16 basis copy
             if (ok && P.precision == XKP_MIXED && P.mode == XKP_PROJ_TARGET_GALERKIN)
                 ok = hdr->bf16 == 1;
@@ -1274,7 +1277,8 @@ __device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const vo
     const int n = s.H * s.H, tid = threadIdx.x;
     if (!(s.basis_id >= 0 && s.basis_id < n_bases)) return -1.0;
     const xkp_basis_header *hdr = (const xkp_basis_header *)bases[s.basis_id];
-    if (!(hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m))
+    if (!(hdr != nullptr && hdr->n == n && hdr->m == P.m && hdr->k >= 0 && hdr->k <= P.m &&
+          hdr->kind == XKP_BASIS_ARNOLDI))
         return -1.0;
     const int m = P.m, k = hdr->k;
     if (ka < k + 1) return -1.0;
@@ -1468,7 +1472,8 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
         const xkp_basis_header *hdr = nullptr;
         if (ok) {
             hdr = (const xkp_basis_header *)bases[s.basis_id];
-            ok = hdr != nullptr && hdr->n == n && hdr->k >= 0 && hdr->k <= hdr->m;
+            ok = hdr != nullptr && hdr->n == n && hdr->k >= 0 && hdr->k <= hdr->m &&
+                 (kind == 0 || hdr->kind == XKP_BASIS_ARNOLDI);
         }
         if (!ok) {
             for (int c = threadIdx.x; c < m_out; c += kNT) out[c] = __builtin_nan("");
@@ -1507,6 +1512,74 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
             }
         }
         __syncthreads();
+    }
+}
+
+// Krylov subspace accumulation over an image cycle: workgroup j gathers out_bases[j] from the
+// first-cycle bases of sources 0..j in order, each column orthogonalised by two modified
+// Gram-Schmidt passes against the columns gathered so far (read back through the prefetch ring)
+// and appended, normalised, when the norm left exceeds 1e-8; at most per_source columns per
+// source and cap in total.  Rows are owned as in the solve, so the columns a thread writes are
+// the ones it reads back.
+template <int RMAX>
+__global__ __launch_bounds__(kNT) void accum_kernel(int n, int nsrc, const void *const *srcs,
+                                                     void *const *outs, int per_source, int cap,
+                                                     int *out_k) {
+    extern __shared__ __attribute__((aligned(16))) double lds[];
+    const int j = blockIdx.x;
+    if (j >= nsrc) return;
+    const int ldv = ldv_for(n);
+    bool ok = outs[j] != nullptr;
+    for (int s = 0; s <= j && ok; ++s) {
+        const xkp_basis_header *h = (const xkp_basis_header *)srcs[s];
+        ok = h != nullptr && h->n == n && h->ldv == ldv && h->kind == XKP_BASIS_ARNOLDI &&
+             h->k >= 0 && h->k <= h->m;
+    }
+    if (!ok) {
+        if (threadIdx.x == 0 && out_k) out_k[j] = -1;
+        return;
+    }
+    BlockRed br{lds, 0};
+    xkp_basis_header *oh = (xkp_basis_header *)outs[j];
+    double *Vo = (double *)((char *)oh + 256);
+    unsigned short *Vob = (unsigned short *)((char *)oh + basis_off_vb(n, cap));
+    int kd = 0;
+    double w[RMAX];
+    for (int s = 0; s <= j && kd < cap; ++s) {
+        const xkp_basis_header *h = (const xkp_basis_header *)srcs[s];
+        const double *Vs = (const double *)((const char *)h + 256);
+        const int ks = h->k;
+        int taken = 0;
+        for (int c = 0; c < ks && taken < per_source && kd < cap; ++c) {
+            load_col<RMAX>(Vs + (size_t)c * ldv, ldv, w);
+            if (kd > 0)
+                sweep_cols<RMAX, Depth<RMAX>::value>(Vo, ldv, kd, 2 * kd,
+                    [&](int, const double(&col)[RMAX]) {
+                    const double d = br.sum(dot_rows<RMAX>(w, col));
+#pragma unroll
+                    for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
+                });
+            const double nw = sqrt(br.sum(dot_rows<RMAX>(w, w)));
+            if (nw > 1e-8) {
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) w[k] = w[k] / nw;
+                store_col<RMAX>(Vo + (size_t)kd * ldv, ldv, w);
+                store_col_bf16<RMAX>(Vob + (size_t)kd * ldv, ldv, w);
+                ++kd;
+                ++taken;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        oh->n = n;
+        oh->m = cap;
+        oh->k = kd;
+        oh->status = XKP_OK;
+        oh->beta = 0.0;
+        oh->ldv = ldv;
+        oh->bf16 = 1;
+        oh->kind = XKP_BASIS_ACCUMULATED;
+        if (out_k) out_k[j] = kd;
     }
 }
 
@@ -1760,6 +1833,16 @@ hipError_t launch_rhs(hipStream_t st, int grid, int rmax, const xkp_system *sys,
                       int nmax) {
     XKP_DISPATCH(rmax, {
         hipLaunchKernelGGL(rhs_kernel<R>, dim3(grid), dim3(kNT), 0, st, sys, nsys, nmax);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(hipStream_t st, int rmax, int n, int nsrc, const void *const *srcs,
+                        void *const *outs, int per_source, int cap, int *out_k) {
+    const size_t lds = sizeof(double) * 2 * kRedSlots * kNW;
+    XKP_DISPATCH(rmax, {
+        hipLaunchKernelGGL(accum_kernel<R>, dim3(nsrc), dim3(kNT), lds, st, n, nsrc, srcs, outs,
+                           per_source, cap, out_k);
     });
     return hipGetLastError();
 }

@@ -49,13 +49,16 @@ class Batch:
     def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
                  mode="target_galerkin", warm=False, max_restarts=1000, device=0,
                  precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None,
-                 reorth="auto"):
+                 reorth="auto", accumulate=None):
         """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
         (the network's guess behind the residual gate, projection as fallback; `learned` =
         dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
         gate=residual gate), single 64x64 group of one channel).  with_seeds: also solve the
         seeds with plain targets.  reorth: "auto" (two Gram-Schmidt passes only while a seed's
-        basis is kept) or "always"."""
+        basis is kept) or "always".  accumulate: per-source column count a of the image-cycle
+        subspace expansion: the groups (one grid size, one channel) are consecutive blocks of
+        one image cycle, and the targets of block g are projected on the basis gathered from
+        the seeds of blocks 0..g (at most a columns each, m in total) at every timestep."""
         import torch
         self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
         self.T, self.m, self.g, self.tol = T, m, g, tol
@@ -111,6 +114,12 @@ class Batch:
             steps = np.repeat(np.arange(1, T + 1, dtype=np.int32)[:, None], self.N, axis=1)
             self.steps_all = torch.from_numpy(steps).to(self.dev)
             self.alpha_l = torch.empty((self.N, k), dtype=torch.float32, device=self.dev)
+        self.acc = None
+        if accumulate is not None:
+            assert method == "project" and mode == "target_galerkin"
+            assert len({gr.H for gr in self.groups}) == 1 and all(gr.C == 1 for gr in self.groups)
+            self.acc = int(accumulate)
+            self.acc_bases = xkp.Bases(2 * self.S, self.nmax, m, device=device)
         self.params = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
                                          precision=precision, mode=mode_id,
                                          batch_max_n=self.nmax, polish_m=polish_m,
@@ -176,6 +185,7 @@ class Batch:
                 self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
             cs.build_rhs(self.seed_desc[par], self.S)
             cs.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
+            bases = self._accumulate(par, bases)
             if self.pipeline:
                 self.ev_seed[par].record(self.s_seed)
                 c.stream.wait_event(self.ev_seed[par])
@@ -196,6 +206,15 @@ class Batch:
         if self.pipeline:
             self.ev_tgt[par].record(c.stream)
         self.step_no += 1
+
+    def _accumulate(self, par, bases):
+        """The targets' bases of this step: the seeds' own, or (image cycle) the bases gathered
+        from the seeds of blocks 0..g, built on the seed context's stream."""
+        if self.acc is None:
+            return bases
+        acc = self.acc_bases.ptrs[par * self.S:(par + 1) * self.S]
+        self.ctx_seed.basis_accumulate(self.nmax, self.S, bases, acc, self.acc, self.m)
+        return acc
 
     def run(self):
         """One full chain, eagerly enqueued."""
@@ -250,6 +269,7 @@ class Batch:
                                                                 bases, self.params, inf_s)
             else:
                 self.ctx_seed.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
+            bases = self._accumulate(par, bases)
         self.ctx.build_rhs(self.tgt_desc[par], self.N)
         torch.cuda.synchronize(self.dev)
         t = self.ctx.autotune(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)

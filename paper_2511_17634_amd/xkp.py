@@ -80,6 +80,8 @@ def load():
                                      ct.POINTER(Tuning)]
         lib.xkp_autotune_seeds.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P,
                                            ct.POINTER(Tuning)]
+        lib.xkp_basis_accumulate.argtypes = [P, ct.c_int32, ct.c_int32, P, P, ct.c_int32,
+                                             ct.c_int32, P]
         lib.xkp_cnn_param_count.argtypes = [ct.c_int32]
         lib.xkp_cnn_param_count.restype = ct.c_size_t
         lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
@@ -97,7 +99,8 @@ def load():
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
-                  "xkp_autotune", "xkp_autotune_seeds", "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
+                  "xkp_autotune", "xkp_autotune_seeds", "xkp_basis_accumulate",
+                  "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
@@ -237,6 +240,13 @@ class Context:
                                    ct.byref(params), _ptr(infos), ct.byref(t)), "xkp_autotune")
         return t
 
+    def basis_accumulate(self, n, n_src, src_ptrs, out_ptrs, per_source, cap, out_k=None):
+        """out_j = orthonormal basis gathered from source bases 0..j (int64 CUDA tensors of basis
+        buffer addresses); out_k: optional int32 CUDA tensor of n_src column counts."""
+        _check(load().xkp_basis_accumulate(self._h, n, n_src, _ptr(src_ptrs), _ptr(out_ptrs),
+                                           per_source, cap, _ptr(out_k)),
+               "xkp_basis_accumulate")
+
     def autotune_seeds(self, systems, n_sys, bases_ptrs, params, infos) -> Tuning:
         """Times the seed call over the kernel variants and workgroup counts (host-synchronous);
         the choice is kept by the context (one that serves seed calls)."""
@@ -297,9 +307,9 @@ class Bases:
 
     def header(self, i):
         o = self.offsets[i]
-        h = self.buf[o:o + 32].cpu().numpy().view(np.int32)
+        h = self.buf[o:o + 36].cpu().numpy().view(np.int32)
         return {"n": int(h[0]), "m": int(h[1]), "k": int(h[2]), "status": int(h[3]),
-                "ldv": int(h[6]), "bf16": int(h[7])}
+                "ldv": int(h[6]), "bf16": int(h[7]), "kind": int(h[8])}
 
     def V_padded(self, i):
         """(ldv, m+1) view of basis i's FP64 columns including the zero rows."""

@@ -54,6 +54,9 @@ CONFIGS = {
                          Group(128, 341, 24, (0.5, 4.0), (0.9, 1.1)))),
     "c5": Config(5, "grid64_learned_guess_4096train_1024eval_T100_m40", T=100, m=40, channels=1,
                  groups=(Group(64, 4096, 8, 2.0, (0.9, 1.1)),)),
+    # image cycle (Experiment 2's protocol): 100 similar images, a new seed every 50
+    "c6": Config(6, "grid64_100images_cycle50_a20_T100_m40", T=100, m=40, channels=1,
+                 groups=(Group(64, 100, 8, (0.5, 4.0), (0.9, 1.1)),)),
 }
 
 
@@ -85,3 +88,15 @@ def initial_state(image: np.ndarray) -> np.ndarray:
     """Initial log-density m^0 of one channel: the clipped pixel intensities themselves,
     flattened in the unknown ordering p = i*H + j (float64, contiguous)."""
     return np.ascontiguousarray(image, dtype=np.float64).reshape(-1)
+
+
+def cycle_blocks(cfg: Config, cycle: int, count: int | None = None):
+    """Images 0..count-1 of group 0 in blocks of `cycle`: block g is (seed (1, n), targets
+    (cycle - 1, 1, n)) with image g*cycle as its seed and the rest of the block as targets
+    (initial states m^0, flattened)."""
+    _, imgs = config_images(cfg, 0, 0, count)
+    blocks = []
+    for g0 in range(0, imgs.shape[0], cycle):
+        blk = imgs[g0:g0 + cycle, 0].reshape(-1, 1, imgs.shape[-2] * imgs.shape[-1])
+        blocks.append((np.ascontiguousarray(blk[0]), np.ascontiguousarray(blk[1:])))
+    return blocks

@@ -47,8 +47,9 @@ int main(void) {
          offsetof(xkp_system, mt), offsetof(xkp_system, x), sizeof(xkp_info), sizeof(xkp_params));
   printf("%zu %zu %zu\n", sizeof(xkp_basis_header), offsetof(xkp_info, res_est),
          offsetof(xkp_params, tol));
-  printf("%zu %zu %zu %zu\n", offsetof(xkp_params, polish_m), sizeof(xkp_tuning),
-         offsetof(xkp_tuning, ms_default), offsetof(xkp_params, reorth));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(xkp_params, polish_m), sizeof(xkp_tuning),
+         offsetof(xkp_tuning, ms_default), offsetof(xkp_params, reorth),
+         offsetof(xkp_basis_header, kind));
   return 0;
 }''')
     exe = tmp_path / "probe"
@@ -63,6 +64,7 @@ int main(void) {
     assert v[8] == xkp.Params.tol.offset
     assert v[9] == xkp.Params.polish_m.offset and v[10] == ct.sizeof(xkp.Tuning)
     assert v[11] == xkp.Tuning.ms_default.offset and v[12] == xkp.Params.reorth.offset
+    assert v[13] == 32    # Bases.header reads kind as the ninth int32
 
 
 def test_host_side_errors_without_gpu(lib):
@@ -82,6 +84,7 @@ def test_host_side_errors_without_gpu(lib):
                                  None) == xkp.EINVAL
     assert lib.xkp_basis_coeffs(None, 1, None, 1, None, 40, 0, None) == xkp.EINVAL
     assert lib.xkp_autotune_seeds(None, 1, None, None, ct.byref(P), None, ct.byref(t)) == xkp.EINVAL
+    assert lib.xkp_basis_accumulate(None, 4096, 2, None, None, 20, 40, None) == xkp.EINVAL
     # the network's sizes and argument checks
     assert lib.xkp_cnn_param_count(40) == 16 * 9 + 16 + 32 * 144 + 32 + 64 * 288 + 64 + 40 * 97
     assert lib.xkp_cnn_param_count(0) == 0 and lib.xkp_cnn_param_count(65) == 0
