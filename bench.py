@@ -279,6 +279,42 @@ def learned_leg(args):
             "legs": legs}
 
 
+def cycle_leg(args):
+    """Image cycle (Experiment 2's protocol, 64x64): 100 similar images, a new seed every 50
+    images; block 1's targets projected on the basis gathered from both seeds (a = 20 columns
+    per seed), against each block's own seed, one seed for all 99 images, and plain GMRES."""
+    from paper_2511_17634_amd.driver import Batch, Group
+    from synth import CONFIGS, cycle_blocks
+    cfg = CONFIGS["c6"]
+    H, T, m, a, h = cfg.groups[0].H, cfg.T, cfg.m, 20, 50
+    blocks = cycle_blocks(cfg, h)
+    groups = [Group(H, s, t) for s, t in blocks]
+    one = Group(H, blocks[0][0], np.concatenate([blocks[0][1], blocks[1][0][None],
+                                                  blocks[1][1]]))
+    legs = {}
+    for name, gr, kw in (("accumulate", groups, dict(accumulate=a)),
+                         ("seed_per_block", groups, {}),
+                         ("one_seed", [one], {}),
+                         ("plain", groups, dict(method="plain"))):
+        b = Batch(gr, T, m, reorth=args.reorth, **kw)
+        if not args.no_tune:
+            b.autotune()
+        r = time_chain(b, args, 1, 1, not args.eager)
+        _, ti = b.all_infos()
+        legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
+                      "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                      "targets": b.N, "mean_iters": round(r["iters_mean"], 2),
+                      "mean_guess_residual": round(r["guess_res_mean"], 4),
+                      "mean_basis_dim": round(float(ti["basis_dim"].mean()), 2),
+                      "polish_m": r["polish_m"], "verified": r["ok"]}
+        print(f"# cycle {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, mean iters "
+              f"{r['iters_mean']:.1f}, guess residual {r['guess_res_mean']:.4f}",
+              file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg.name, "images": 100, "cycle": h, "a": a, "timesteps": T, "m": m,
+            "unit": "target systems/s", "legs": legs}
+
+
 def time_chain(b, args, steps, warmup, graph=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
     captured graph (or enqueued eagerly), then verify every solve of the last chain."""
@@ -357,7 +393,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 128x128 mixed workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess workload")
     ap.add_argument("--learned-epochs", type=int, default=4)
-    ap.add_argument("--only", choices=("uneven", "mixed", "learned"),
+    ap.add_argument("--no-cycle", action="store_true", help="skip the image-cycle workload")
+    ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle"),
                     help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
@@ -379,7 +416,8 @@ def main():
 
     xkp.load()
     if args.only:
-        rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg}[args.only](args)
+        rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
+               "cycle": cycle_leg}[args.only](args)
         print(json.dumps(rec), flush=True)
         return
     cfg, s0, t0 = build_c2()
@@ -476,6 +514,10 @@ def main():
         out["learned"] = learned_leg(args)
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
+    if not args.no_cycle:
+        out["cycle"] = cycle_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for v in out["cycle"]["legs"].values())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps,
                                            args.reorth)

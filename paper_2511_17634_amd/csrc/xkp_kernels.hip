@@ -1516,15 +1516,20 @@ __global__ __launch_bounds__(kNT) void coeffs_kernel(const xkp_system *__restric
 }
 
 // Krylov subspace accumulation over an image cycle: workgroup j gathers out_bases[j] from the
-// first-cycle bases of sources 0..j in order, each column orthogonalised by two modified
-// Gram-Schmidt passes against the columns gathered so far (read back through the prefetch ring)
-// and appended, normalised, when the norm left exceeds 1e-8; at most per_source columns per
-// source and cap in total.  Rows are owned as in the solve, so the columns a thread writes are
-// the ones it reads back.
+// first-cycle bases of sources 0..j in order; every column is orthogonalised by two modified
+// Gram-Schmidt passes against the columns gathered before it and appended, normalised, when the
+// norm left exceeds 1e-8; at most per_source columns per source and cap in total.  Source
+// columns go in blocks of AccB: the two passes over the columns gathered before the block (read
+// once per pass through the prefetch ring, AccB products per multi-value reduction), then the
+// two passes over the block's own accepted columns, held in registers.  Rows are owned as in
+// the solve, so the columns a thread writes are the ones it reads back.
+template <int R> struct AccB { static constexpr int value = R <= 8 ? 4 : (R <= 16 ? 2 : 1); };
+
 template <int RMAX>
 __global__ __launch_bounds__(kNT) void accum_kernel(int n, int nsrc, const void *const *srcs,
                                                      void *const *outs, int per_source, int cap,
                                                      int *out_k) {
+    constexpr int B = AccB<RMAX>::value;
     extern __shared__ __attribute__((aligned(16))) double lds[];
     const int j = blockIdx.x;
     if (j >= nsrc) return;
@@ -1544,29 +1549,69 @@ __global__ __launch_bounds__(kNT) void accum_kernel(int n, int nsrc, const void 
     double *Vo = (double *)((char *)oh + 256);
     unsigned short *Vob = (unsigned short *)((char *)oh + basis_off_vb(n, cap));
     int kd = 0;
-    double w[RMAX];
+    double w[B][RMAX];
     for (int s = 0; s <= j && kd < cap; ++s) {
         const xkp_basis_header *h = (const xkp_basis_header *)srcs[s];
         const double *Vs = (const double *)((const char *)h + 256);
         const int ks = h->k;
-        int taken = 0;
-        for (int c = 0; c < ks && taken < per_source && kd < cap; ++c) {
-            load_col<RMAX>(Vs + (size_t)c * ldv, ldv, w);
-            if (kd > 0)
-                sweep_cols<RMAX, Depth<RMAX>::value>(Vo, ldv, kd, 2 * kd,
+        int taken = 0, c = 0;
+        while (c < ks && taken < per_source && kd < cap) {
+            // the block: as many columns as the caps can still take, at most B
+            int nb = ks - c;
+            if (nb > per_source - taken) nb = per_source - taken;
+            if (nb > cap - kd) nb = cap - kd;
+            if (nb > B) nb = B;
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (b < nb) {
+                    load_col<RMAX>(Vs + (size_t)(c + b) * ldv, ldv, w[b]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < RMAX; ++k) w[b][k] = 0.0;
+                }
+            }
+            c += nb;
+            const int k0 = kd;
+            if (k0 > 0)
+                sweep_cols<RMAX, Depth<RMAX>::value>(Vo, ldv, k0, 2 * k0,
                     [&](int, const double(&col)[RMAX]) {
-                    const double d = br.sum(dot_rows<RMAX>(w, col));
+                    double d[B];
 #pragma unroll
-                    for (int k = 0; k < RMAX; ++k) w[k] -= d * col[k];
+                    for (int b = 0; b < B; ++b) d[b] = dot_rows<RMAX>(w[b], col);
+                    br.sum_multi<B>(d);
+#pragma unroll
+                    for (int b = 0; b < B; ++b)
+#pragma unroll
+                        for (int k = 0; k < RMAX; ++k) w[b][k] -= d[b] * col[k];
                 });
-            const double nw = sqrt(br.sum(dot_rows<RMAX>(w, w)));
-            if (nw > 1e-8) {
+            // within the block: against the block's columns accepted before, in order
+            int acc[B];
+            int na = 0;
 #pragma unroll
-                for (int k = 0; k < RMAX; ++k) w[k] = w[k] / nw;
-                store_col<RMAX>(Vo + (size_t)kd * ldv, ldv, w);
-                store_col_bf16<RMAX>(Vob + (size_t)kd * ldv, ldv, w);
-                ++kd;
-                ++taken;
+            for (int b = 0; b < B; ++b) {
+                if (b >= nb) break;
+                for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+                    for (int q = 0; q < B; ++q) {
+                        if (q >= na) break;
+#pragma unroll
+                        for (int qq = 0; qq < B; ++qq) {
+                            if (qq != acc[q]) continue;
+                            const double d = br.sum(dot_rows<RMAX>(w[b], w[qq]));
+#pragma unroll
+                            for (int k = 0; k < RMAX; ++k) w[b][k] -= d * w[qq][k];
+                        }
+                    }
+                const double nw = sqrt(br.sum(dot_rows<RMAX>(w[b], w[b])));
+                if (nw > 1e-8) {
+#pragma unroll
+                    for (int k = 0; k < RMAX; ++k) w[b][k] = w[b][k] / nw;
+                    store_col<RMAX>(Vo + (size_t)kd * ldv, ldv, w[b]);
+                    store_col_bf16<RMAX>(Vob + (size_t)kd * ldv, ldv, w[b]);
+                    acc[na++] = b;
+                    ++kd;
+                    ++taken;
+                }
             }
         }
     }
