@@ -30,13 +30,15 @@ class ChainStats:
 
 
 def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
-              mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000, reorth="auto"):
+              mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000, reorth="auto",
+              on_step=None):
     """Advance the seed and every target through `steps` (default T) timesteps.
 
     seed_m0: (n,) initial state of the seed; target_m0: (N, n).  Returns (m_seed, m_targets,
     stats).  With method "plain" or "direct" the seed chain is not solved.  reorth "auto": two
     Gram-Schmidt passes in the seed solves (their first-cycle basis is kept), one in the target
-    solves (their basis is discarded); "always": two passes everywhere.
+    solves (their basis is discarded); "always": two passes everywhere.  on_step(n, ms, mt), if
+    given, sees the states m^{n-1} before the solves of step n (n = 1, 2, ...).
     """
     if reorth not in ("auto", "always"):
         raise ValueError("reorth must be 'auto' or 'always'")
@@ -45,7 +47,9 @@ def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
     ms = np.array(seed_m0, dtype=np.float64).reshape(-1)
     mt = np.array(target_m0, dtype=np.float64).reshape(len(target_m0), -1)
     st = ChainStats()
-    for _ in range(T if steps is None else steps):
+    for step in range(T if steps is None else steps):
+        if on_step is not None:
+            on_step(step + 1, ms, mt)
         basis = None
         if method == "project":
             As = Operator(H, dt, g, ms)
