@@ -311,6 +311,28 @@ xkp_status xkp_basis_accumulate(xkp_ctx *ctx, int32_t n, int32_t n_src,
                                 const void *const *src_bases, void *const *out_bases,
                                 int32_t per_source, int32_t cap, int32_t *out_k);
 
+/*
+ * Score and probability-flow embedding (the step after the solves).  For each system i and grid
+ * point p = i_x*H + j, with h = 1/H and the log-density m taken as zero outside the grid:
+ *   s_x = (m[i_x+1, j] - m[i_x-1, j]) / (2h),   s_y = (m[i_x, j+1] - m[i_x, j-1]) / (2h)
+ * (Section 2.3's central difference of the solution; the 2h divisor is the one of the PDE's
+ * discrete gradient), and one explicit step of the probability-flow ODE that embeds the score
+ * into the image (Section 4, x^n = x^{n-1} + (f - g^2/2 grad m^{n-1}) dt), applied per grid point
+ * to a two-component displacement:  d_x += (f_x - g^2/2 s_x) dt,  d_y += (f_y - g^2/2 s_y) dt.
+ *   field:   XKP_FIELD_MT takes m = systems[i].mt (m^{n-1}, the state before the step's solve:
+ *            the embedding's argument), XKP_FIELD_X takes m = systems[i].x (the solution m^n)
+ *   score:   device array of n_sys pointers to 2n doubles (s_x then s_y), or NULL; a NULL entry
+ *            skips that system's score
+ *   disp:    device array of n_sys pointers to 2n doubles updated in place, or NULL / NULL entry
+ * g, dt, fx, fy (NULL: 0) come from the descriptor.  A descriptor with H < 1, H*H above the
+ * context's max_n, dt <= 0 or a NULL field is skipped.  n_sys <= 65535.  One launch, on the
+ * context's stream.
+ */
+typedef enum { XKP_FIELD_MT = 0, XKP_FIELD_X = 1 } xkp_field;
+
+xkp_status xkp_score_flow(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, int32_t field,
+                          double *const *score, double *const *disp);
+
 /* Outcome of xkp_autotune. */
 typedef struct {
     int32_t polish_m;     /* fastest restart length of the polish (for params->polish_m)    */

@@ -268,6 +268,17 @@ xkp_status xkp_basis_accumulate(xkp_ctx *ctx, int32_t n, int32_t n_src,
                              per_source, cap, out_k));
 }
 
+xkp_status xkp_score_flow(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, int32_t field,
+                          double *const *score, double *const *disp) {
+    if (!ctx || n_sys < 0 || (n_sys > 0 && !systems) ||
+        (field != XKP_FIELD_MT && field != XKP_FIELD_X) || n_sys > 65535)
+        return XKP_EINVAL;
+    if (n_sys == 0) return XKP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    return from_hip(xkp::epi::launch_score_flow(ctx->stream, systems, n_sys, field, score, disp,
+                                                ctx->max_n));
+}
+
 xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {
     if (!ctx || n_sys < 0 || (n_sys > 0 && !systems)) return XKP_EINVAL;
     if (n_sys == 0) return XKP_OK;

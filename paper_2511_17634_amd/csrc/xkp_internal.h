@@ -76,6 +76,12 @@ XKP_DECLARE_VARIANT(v512)
 XKP_DECLARE_VARIANT(v1024)
 XKP_DECLARE_VARIANT(v256)
 
+// Score and probability-flow embedding (xkp_epilogue.hip).
+namespace epi {
+hipError_t launch_score_flow(hipStream_t st, const xkp_system *sys, int nsys, int field,
+                             double *const *score, double *const *disp, int nmax);
+}  // namespace epi
+
 // The learned-guess network (xkp_cnn.hip).
 namespace cnn {
 size_t param_count(int k);

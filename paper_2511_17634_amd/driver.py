@@ -49,7 +49,7 @@ class Batch:
     def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
                  mode="target_galerkin", warm=False, max_restarts=1000, device=0,
                  precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None,
-                 reorth="auto", accumulate=None):
+                 reorth="auto", accumulate=None, embed=False):
         """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
         (the network's guess behind the residual gate, projection as fallback; `learned` =
         dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
@@ -58,7 +58,10 @@ class Batch:
         basis is kept) or "always".  accumulate: per-source column count a of the image-cycle
         subspace expansion: the groups (one grid size, one channel) are consecutive blocks of
         one image cycle, and the targets of block g are projected on the basis gathered from
-        the seeds of blocks 0..g (at most a columns each, m in total) at every timestep."""
+        the seeds of blocks 0..g (at most a columns each, m in total) at every timestep.
+        embed: after each step's target call, the score of every target's state before the
+        step (m^{n-1}) goes to `score_t` and one probability-flow step to the displacement
+        `disp_t` (both (N, 2, n) per target of one grid size; reset with the chain)."""
         import torch
         self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
         self.T, self.m, self.g, self.tol = T, m, g, tol
@@ -114,6 +117,14 @@ class Batch:
             steps = np.repeat(np.arange(1, T + 1, dtype=np.int32)[:, None], self.N, axis=1)
             self.steps_all = torch.from_numpy(steps).to(self.dev)
             self.alpha_l = torch.empty((self.N, k), dtype=torch.float32, device=self.dev)
+        self.embed = bool(embed)
+        if self.embed:
+            assert len({gr.H for gr in self.groups}) == 1
+            self.score_t = torch.zeros((self.N, 2, self.nmax), **f64)
+            self.disp_t = torch.zeros((self.N, 2, self.nmax), **f64)
+            rows = 2 * self.nmax * 8 * np.arange(self.N, dtype=np.int64)
+            self.score_ptrs = torch.tensor(self.score_t.data_ptr() + rows, device=self.dev)
+            self.disp_ptrs = torch.tensor(self.disp_t.data_ptr() + rows, device=self.dev)
         self.acc = None
         if accumulate is not None:
             assert method == "project" and mode == "target_galerkin"
@@ -161,6 +172,8 @@ class Batch:
                 self.s_main.wait_stream(self.s_seed)
             self.ms[0].copy_(self.m0[0])
             self.mt[0].copy_(self.m0[1])
+            if self.embed:
+                self.disp_t.zero_()
             if self.pipeline:
                 self.ev_reset.record(self.s_main)
                 self.s_seed.wait_event(self.ev_reset)
@@ -201,6 +214,9 @@ class Batch:
             c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         if events is not None:
             events[1].record(c.stream)
+        if self.embed:
+            c.score_flow(self.tgt_desc[par], self.N, xkp.FIELD_MT, self.score_ptrs,
+                         self.disp_ptrs)
         if after_targets is not None:
             after_targets(par, bases)
         if self.pipeline:

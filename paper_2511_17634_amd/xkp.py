@@ -20,6 +20,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESINGULAR, EUNSUPPORTED = range(7)
 FP64, MIXED = 0, 1
 TARGET_GALERKIN, SEED_GALERKIN, SEED_LSQ, NONE = 0, 1, 2, 3
 REORTH_AUTO, REORTH_ALWAYS = 0, 1
+FIELD_MT, FIELD_X = 0, 1
 MODES = {"target_galerkin": TARGET_GALERKIN, "seed_galerkin": SEED_GALERKIN,
          "seed_lsq": SEED_LSQ, "none": NONE}
 
@@ -82,6 +83,7 @@ def load():
                                            ct.POINTER(Tuning)]
         lib.xkp_basis_accumulate.argtypes = [P, ct.c_int32, ct.c_int32, P, P, ct.c_int32,
                                              ct.c_int32, P]
+        lib.xkp_score_flow.argtypes = [P, ct.c_int32, P, ct.c_int32, P, P]
         lib.xkp_cnn_param_count.argtypes = [ct.c_int32]
         lib.xkp_cnn_param_count.restype = ct.c_size_t
         lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
@@ -100,6 +102,7 @@ def load():
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
                   "xkp_autotune", "xkp_autotune_seeds", "xkp_basis_accumulate",
+                  "xkp_score_flow",
                   "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
             getattr(lib, f).restype = ct.c_int
@@ -246,6 +249,12 @@ class Context:
         _check(load().xkp_basis_accumulate(self._h, n, n_src, _ptr(src_ptrs), _ptr(out_ptrs),
                                            per_source, cap, _ptr(out_k)),
                "xkp_basis_accumulate")
+
+    def score_flow(self, systems, n_sys, field, score_ptrs=None, disp_ptrs=None):
+        """Score (2n per system) and one probability-flow step of the displacement (2n, in
+        place); pointer arrays are int64 CUDA tensors or None."""
+        _check(load().xkp_score_flow(self._h, n_sys, _ptr(systems), field, _ptr(score_ptrs),
+                                     _ptr(disp_ptrs)), "xkp_score_flow")
 
     def autotune_seeds(self, systems, n_sys, bases_ptrs, params, infos) -> Tuning:
         """Times the seed call over the kernel variants and workgroup counts (host-synchronous);
