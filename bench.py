@@ -315,6 +315,42 @@ def cycle_leg(args):
             "unit": "target systems/s", "legs": legs}
 
 
+def epilogue_leg(args):
+    """Score + probability-flow pass over 255 systems of 128x128 (the size of the mixed
+    workload), timed with HIP events on the context's stream; HBM roofline with algorithmic
+    bytes 8n (read m) + 16n (write the score) + 32n (update the displacement) per system."""
+    import torch
+    from paper_2511_17634_amd import xkp
+    H, N, reps = 128, 255, 20
+    n = H * H
+    st = torch.cuda.Stream()
+    ctx = xkp.Context(n, 8, N, stream=st)
+    rng = np.random.default_rng(5)
+    m = torch.tensor(rng.uniform(0, 1, (N, n)), dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(m)
+    score = torch.zeros((N, 2, n), dtype=torch.float64, device="cuda")
+    disp = torch.zeros_like(score)
+    d = xkp.pack_batch(H, 0.01, 0.5, m, b, m)
+    rows = 2 * n * 8 * np.arange(N, dtype=np.int64)
+    sp = torch.tensor(score.data_ptr() + rows, device="cuda")
+    dp = torch.tensor(disp.data_ptr() + rows, device="cuda")
+    torch.cuda.synchronize()
+    ctx.score_flow(d, N, xkp.FIELD_MT, sp, dp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ctx.score_flow(d, N, xkp.FIELD_MT, sp, dp)
+    e1.record(st)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    byts = 56 * n * N
+    return {"workload": f"{N} systems of {H}x{H}", "launch_us": round(us, 2),
+            "roofline": {"kernel": "score_flow_kernel", "bound": "hbm",
+                         "achieved": round(byts / us / 1e3, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(byts / us / 1e3 / HBM_PEAK_GBS, 4),
+                         "bytes_per_launch": byts}}
+
+
 def time_chain(b, args, steps, warmup, graph=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
     captured graph (or enqueued eagerly), then verify every solve of the last chain."""
@@ -394,7 +430,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess workload")
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--no-cycle", action="store_true", help="skip the image-cycle workload")
-    ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle"),
+    ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle", "epilogue"),
                     help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
@@ -417,7 +453,7 @@ def main():
     xkp.load()
     if args.only:
         rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
-               "cycle": cycle_leg}[args.only](args)
+               "cycle": cycle_leg, "epilogue": epilogue_leg}[args.only](args)
         print(json.dumps(rec), flush=True)
         return
     cfg, s0, t0 = build_c2()
@@ -514,6 +550,7 @@ def main():
         out["learned"] = learned_leg(args)
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
+    out["epilogue"] = epilogue_leg(args)
     if not args.no_cycle:
         out["cycle"] = cycle_leg(args)
         out["verified"] = out["verified"] and all(
