@@ -27,19 +27,27 @@ class ChainStats:
     res_true: list = field(default_factory=list)
     guess_res: list = field(default_factory=list)      # [step][target] ||b-Ax0||/||b||
     basis_dim: list = field(default_factory=list)
+    picard_iters: list = field(default_factory=list)   # [step][k - 2][target]
 
 
 def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
               mode=TARGET_GALERKIN, warm=False, steps=None, max_restarts=1000, reorth="auto",
-              on_step=None):
+              on_step=None, picard=1):
     """Advance the seed and every target through `steps` (default T) timesteps.
 
     seed_m0: (n,) initial state of the seed; target_m0: (N, n).  Returns (m_seed, m_targets,
     stats).  With method "plain" or "direct" the seed chain is not solved.  reorth "auto": two
     Gram-Schmidt passes in the seed solves (their first-cycle basis is kept), one in the target
     solves (their basis is discarded); "always": two passes everywhere.  on_step(n, ms, mt), if
-    given, sees the states m^{n-1} before the solves of step n (n = 1, 2, ...).
+    given, sees the states m^{n-1} before the solves of step n (n = 1, 2, ...).  picard = K > 1
+    repeats each step's linearisation (Section 2.3: m~^{(k)} = m^{(k-1)}): after the first solve,
+    every system is solved K - 1 more times with its operator built from its previous iterate,
+    the right-hand side kept at m^{n-1}/dt - div f, GMRES started from the previous iterate;
+    the result of the K-th solve is m^n.  stats.iters then holds the first solves' counts and
+    stats.picard_iters[step][k][target] those of the later ones.
     """
+    if picard < 1:
+        raise ValueError("picard must be >= 1")
     if reorth not in ("auto", "always"):
         raise ValueError("reorth must be 'auto' or 'always'")
     tpasses = 1 if reorth == "auto" else 2
@@ -81,11 +89,34 @@ def run_chain(seed_m0, target_m0, H, T, m, g=0.5, tol=1e-8, method="project",
                 it_row.append(r.iters); rs_row.append(r.restarts); stt_row.append(r.status)
                 res_row.append(r.res_true)
             new[t] = x
-        if basis is not None:
-            ms = basis.x
+        new_s = basis.x if basis is not None else None
+        pic_rows = []
+        for _ in range(picard - 1):
+            # the linearisation again, around the previous iterate
+            if new_s is not None:
+                As = Operator(H, dt, g, new_s)
+                sr = gmres(As, rhs(As, ms), x0=new_s, m=m, tol=tol, max_restarts=max_restarts,
+                           passes=tpasses)
+                new_s = sr.x
+            row = []
+            for t in range(mt.shape[0]):
+                At = Operator(H, dt, g, new[t])
+                if method == "direct":
+                    new[t], _ = banded_solve(At, rhs(At, mt[t]))
+                    row.append(0)
+                else:
+                    r = gmres(At, rhs(At, mt[t]), x0=new[t], m=m, tol=tol,
+                              max_restarts=max_restarts, passes=tpasses)
+                    new[t] = r.x
+                    row.append(r.iters)
+                    res_row[t] = r.res_true
+            pic_rows.append(row)
+        if new_s is not None:
+            ms = new_s
         mt = new
         st.iters.append(it_row); st.restarts.append(rs_row); st.status.append(stt_row)
         st.res_true.append(res_row); st.guess_res.append(g_row)
+        st.picard_iters.append(pic_rows)
     return ms, mt, st
 
 

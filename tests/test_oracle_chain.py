@@ -66,3 +66,43 @@ def test_chain_routes_agree_with_direct(olib, mode):
     bound = steps * cfg.tol * max(np.linalg.norm(s0), np.linalg.norm(t0))
     assert np.abs(m_proj - m_dir).max() <= bound + 1e-13
     assert np.abs(m_plain - m_dir).max() <= bound + 1e-13
+
+
+def test_picard_one_is_the_plain_chain_and_iterates_contract(olib):
+    """K = 1 is the one-pass chain bitwise; more Picard passes contract to the fixed point of
+    m -> A(m)^{-1} b, so the nonlinear residual ||A(m) m - b|| / ||b|| falls geometrically."""
+    cfg = CONFIGS["c1"]
+    seed, tg = config_images(cfg, 0, 0, 1)
+    H = cfg.groups[0].H
+    s0, t0 = initial_state(seed[0]), initial_state(tg[0, 0])[None]
+    a = run_chain(s0, t0, H, cfg.T, cfg.m, method="direct", steps=2)
+    b = run_chain(s0, t0, H, cfg.T, cfg.m, method="direct", steps=2, picard=1)
+    assert np.array_equal(a[1], b[1])
+    m_prev = run_chain(s0, t0, H, cfg.T, cfg.m, method="direct", steps=1)[1][0]
+    A0 = oracle.Operator(H, 1.0 / cfg.T, cfg.g, m_prev)
+    rhs = oracle.rhs(A0, m_prev)
+    res = []
+    for K in range(1, 8):
+        mK = run_chain(m_prev, m_prev[None], H, cfg.T, cfg.m, method="direct", steps=1,
+                       picard=K)[1][0]
+        AK = oracle.Operator(H, 1.0 / cfg.T, cfg.g, mK)
+        res.append(np.linalg.norm(oracle.apply(AK, mK) - rhs) / np.linalg.norm(rhs))
+    assert all(r2 < 0.5 * r1 for r1, r2 in zip(res[:4], res[1:5])), res
+    assert res[-1] < 1e-9, res
+
+
+def test_picard_limit_keeps_first_order_cole_hopf(olib):
+    """The chain with K = 4 Picard passes (close to the fully implicit nonlinear scheme) also
+    converges at first order to the Cole-Hopf solution (dt = t_end / steps through T = 2 steps)."""
+    def err(steps, K, H=32, g=0.5, eps=0.9):
+        h = 1.0 / H
+        L = 1.0 + h
+        i, j = np.meshgrid(np.arange(H), np.arange(H), indexing="ij")
+        S = (np.sin(np.pi * (i * h + h) / L) * np.sin(np.pi * (j * h + h) / L)).reshape(-1)
+        m0 = np.log1p(eps * S)
+        _, mt, _ = run_chain(m0, m0[None], H, 2 * steps, 30, g=g, method="direct",
+                             steps=steps, picard=K)
+        exact = np.log1p(eps * np.exp(-g * g * np.pi**2 * 0.5 / L**2) * S)
+        return np.abs(mt[0] - exact).max()
+    e = [err(T, 4) for T in (10, 20, 40)]
+    assert 1.7 <= e[0] / e[1] <= 2.3 and 1.7 <= e[1] / e[2] <= 2.3, e
