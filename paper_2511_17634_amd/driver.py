@@ -49,7 +49,7 @@ class Batch:
     def __init__(self, groups, T, m, g=0.5, tol=1e-8, method="project",
                  mode="target_galerkin", warm=False, max_restarts=1000, device=0,
                  precision=xkp.FP64, pipeline=True, polish_m=0, with_seeds=None, learned=None,
-                 reorth="auto", accumulate=None, embed=False):
+                 reorth="auto", accumulate=None, embed=False, picard=1):
         """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
         (the network's guess behind the residual gate, projection as fallback; `learned` =
         dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
@@ -61,7 +61,10 @@ class Batch:
         the seeds of blocks 0..g (at most a columns each, m in total) at every timestep.
         embed: after each step's target call, the score of every target's state before the
         step (m^{n-1}) goes to `score_t` and one probability-flow step to the displacement
-        `disp_t` (both (N, 2, n) per target of one grid size; reset with the chain)."""
+        `disp_t` (both (N, 2, n) per target of one grid size; reset with the chain).
+        picard: K linearisation passes per timestep: after the seed and target calls every
+        system is solved K - 1 more times by plain GMRES, the operator built from its previous
+        iterate (m~ = m^{n,(k-1)}), the right-hand side kept, started from that iterate."""
         import torch
         self.groups = sorted(groups, key=lambda gr: -gr.n)      # largest grid first
         self.T, self.m, self.g, self.tol = T, m, g, tol
@@ -136,14 +139,54 @@ class Batch:
                                          batch_max_n=self.nmax, polish_m=polish_m,
                                          reorth=reorth)
         self.warm = warm
-        self.seed_desc = [self._desc(self.seed_sys, self.ms, self.bs, par) for par in (0, 1)]
-        self.tgt_desc = [self._desc(self.tgt_sys, self.mt, self.bt, par) for par in (0, 1)]
+        self.K = int(picard)
+        assert self.K >= 1
+        if self.K > 1:
+            self.ms_pic = torch.empty_like(self.ms[0])
+            self.mt_pic = torch.empty_like(self.mt[0])
+            self.params_plain = xkp.Context.params(m, tol=tol, max_restarts=max_restarts,
+                                                   precision=precision, mode=xkp.NONE,
+                                                   batch_max_n=self.nmax, polish_m=polish_m,
+                                                   reorth=reorth)
+            self.info_ps = self.ctx.new_infos(T * (self.K - 1) * self.S)
+            self.info_pt = self.ctx.new_infos(T * (self.K - 1) * self.N)
+        self.seed_desc = [self._desc(self.seed_sys, self.ms, self.bs, par,
+                                     x_from=self._out(1, par, True)) for par in (0, 1)]
+        self.tgt_desc = [self._desc(self.tgt_sys, self.mt, self.bt, par,
+                                    x_from=self._out(1, par, False)) for par in (0, 1)]
+        # Picard passes k = 2..K: m~ = x0 = iterate k-1, result into iterate k
+        self.seed_pic = [[self._desc_raw(self.seed_sys, self._out(k - 1, par, True), self.bs,
+                                         self._out(k, par, True), self._out(k - 1, par, True))
+                          for k in range(2, self.K + 1)] for par in (0, 1)]
+        self.tgt_pic = [[self._desc_raw(self.tgt_sys, self._out(k - 1, par, False), self.bt,
+                                        self._out(k, par, False), self._out(k - 1, par, False))
+                         for k in range(2, self.K + 1)] for par in (0, 1)]
         # one info record per system and timestep, so that every solve can be verified
         self.info_s_all = self.ctx.new_infos(T * self.S)
         self.info_t_all = self.ctx.new_infos(T * self.N)
         self.step_no = 0
         self.graph = None
         torch.cuda.synchronize(self.dev)     # inputs copied on the current stream are in place
+
+    def _out(self, k, par, seeds):
+        """Where Picard pass k of a step of parity par writes: passes alternate between the
+        scratch iterate and the next state so that pass K lands in the state."""
+        state = self.ms if seeds else self.mt
+        if (self.K - k) % 2 == 0:
+            return state[1 - par]
+        return self.ms_pic if seeds else self.mt_pic
+
+    def _desc_raw(self, systems, mt, b, x, x0):
+        """Descriptors with explicit m~ (coefficients), b, x and x0 tensors."""
+        import torch
+        a = np.zeros(len(systems), dtype=xkp.SYSTEM_DTYPE)
+        for i, (H, off, bid) in enumerate(systems):
+            o = 8 * off
+            a[i] = (H, bid, self.dt, self.g, mt.data_ptr() + o, 0, 0, b.data_ptr() + o,
+                    x0.data_ptr() + o, x.data_ptr() + o)
+        d = torch.from_numpy(a.view(np.uint8).copy()).to(self.dev)
+        d._xkp_keep = [mt, b, x, x0]
+        return d
 
     def _desc(self, systems, state, b, par, x_from=None):
         """Descriptors of `systems` at a step of parity par: m~ = state[par], solution into
@@ -202,6 +245,12 @@ class Batch:
             if self.pipeline:
                 self.ev_seed[par].record(self.s_seed)
                 c.stream.wait_event(self.ev_seed[par])
+            t = self.step_no % self.T
+            w = xkp.INFO_DTYPE.itemsize
+            for k in range(2, self.K + 1):
+                o = ((t * (self.K - 1) + k - 2) * self.S) * w
+                cs.target_project_solve(self.seed_pic[par][k - 2], self.S, 0, None,
+                                        self.params_plain, self.info_ps[o:o + self.S * w])
         c.build_rhs(self.tgt_desc[par], self.N)
         if events is not None:
             events[0].record(c.stream)
@@ -214,6 +263,12 @@ class Batch:
             c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         if events is not None:
             events[1].record(c.stream)
+        t = self.step_no % self.T
+        w = xkp.INFO_DTYPE.itemsize
+        for k in range(2, self.K + 1):
+            o = ((t * (self.K - 1) + k - 2) * self.N) * w
+            c.target_project_solve(self.tgt_pic[par][k - 2], self.N, 0, None, self.params_plain,
+                                   self.info_pt[o:o + self.N * w])
         if self.embed:
             c.score_flow(self.tgt_desc[par], self.N, xkp.FIELD_MT, self.score_ptrs,
                          self.disp_ptrs)
@@ -309,6 +364,13 @@ class Batch:
         t = xkp.infos_to_numpy(self.info_t_all).reshape(self.T, self.N)
         return s, t
 
+    def picard_infos(self):
+        """(seed infos [T, K-1, S], target infos [T, K-1, N]) of the later Picard passes."""
+        self._join()
+        s = xkp.infos_to_numpy(self.info_ps).reshape(self.T, self.K - 1, self.S)
+        t = xkp.infos_to_numpy(self.info_pt).reshape(self.T, self.K - 1, self.N)
+        return s, t
+
     def infos(self):
         """(seed infos [S], target infos [N]) of the last step."""
         self._join()
@@ -338,11 +400,14 @@ class Batch:
         prev = 1 - par                       # m^{T-1} defined the last solve
         bt = torch.empty_like(self.bt)
         d = self._desc(self.tgt_sys, self.mt, bt, prev)
+        # with Picard passes the last solve's operator came from the iterate before it
+        dr = d if self.K == 1 else self._desc_raw(self.tgt_sys, self._out(self.K - 1, prev, False),
+                                                  bt, self.mt[par], self.mt[par])
         rel = torch.empty(self.N, dtype=torch.float64, device=self.dev)
         self.s_main.wait_stream(torch.cuda.current_stream(self.dev))   # the descriptors' copy
         with torch.cuda.stream(self.s_main):
             self.ctx.build_rhs(d, self.N)
-            self.ctx.residual(d, self.N, rel)
+            self.ctx.residual(dr, self.N, rel)
         self.s_main.synchronize()
         return rel.cpu().numpy()
 
