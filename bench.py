@@ -315,6 +315,33 @@ def cycle_leg(args):
             "unit": "target systems/s", "legs": legs}
 
 
+def picard_leg(args):
+    """64x64 benchmark chain with K = 2 and 3 linearisation passes per timestep (projection for
+    the first pass, plain GMRES from the previous iterate for the later ones)."""
+    from paper_2511_17634_amd.driver import Chain
+    cfg, s0, t0 = build_c2()
+    H, T, m = cfg.groups[0].H, cfg.T, cfg.m
+    legs = {}
+    for K in (2, 3):
+        b = Chain(H, T, m, s0, t0, picard=K, reorth=args.reorth)
+        if not args.no_tune:
+            b.autotune()
+        r = time_chain(b, args, 1, 1, not args.eager)
+        _, pt = b.picard_infos()
+        ok = r["ok"] and bool((pt["status"] == 0).all() and (pt["res_true"] <= args.tol).all())
+        legs[f"K{K}"] = {"value": round(b.N * T / r["per_chain_s"], 2),
+                         "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                         "mean_iters_first_pass": round(r["iters_mean"], 2),
+                         "mean_iters_later_passes": [round(float(pt["iters"][:, k].mean()), 2)
+                                                     for k in range(K - 1)],
+                         "verified": ok}
+        print(f"# picard K={K}: {r['per_chain_s'] * 1e3:.1f} ms/chain, iters {r['iters_mean']:.1f}"
+              f" then {legs[f'K{K}']['mean_iters_later_passes']}", file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg.name, "unit": "target systems/s (one per target and timestep)",
+            "legs": legs}
+
+
 def epilogue_leg(args):
     """Score + probability-flow pass over 255 systems of 128x128 (the size of the mixed
     workload), timed with HIP events on the context's stream; HBM roofline with algorithmic
@@ -430,7 +457,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess workload")
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--no-cycle", action="store_true", help="skip the image-cycle workload")
-    ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle", "epilogue"),
+    ap.add_argument("--no-picard", action="store_true", help="skip the Picard-pass legs")
+    ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle", "epilogue",
+                                       "picard"),
                     help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
@@ -453,7 +482,7 @@ def main():
     xkp.load()
     if args.only:
         rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
-               "cycle": cycle_leg, "epilogue": epilogue_leg}[args.only](args)
+               "cycle": cycle_leg, "epilogue": epilogue_leg, "picard": picard_leg}[args.only](args)
         print(json.dumps(rec), flush=True)
         return
     cfg, s0, t0 = build_c2()
@@ -551,6 +580,10 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
     out["epilogue"] = epilogue_leg(args)
+    if not args.no_picard:
+        out["picard"] = picard_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for v in out["picard"]["legs"].values())
     if not args.no_cycle:
         out["cycle"] = cycle_leg(args)
         out["verified"] = out["verified"] and all(

@@ -305,6 +305,9 @@ class Batch:
             self.reset(join_seed=False)
             for _ in range(self.T):
                 self.step()
+            if self.pipeline:
+                # seed work after the last step's basis event (Picard passes) joins the capture
+                self.s_main.wait_stream(self.s_seed)
         self.graph = g
         return g
 

@@ -57,3 +57,13 @@ def test_picard_chain_matches_oracle(X, K):
         A1x = oracle.Operator(H, 1.0 / cfg.T, cfg.g, x1)
         r1 = np.linalg.norm(oracle.apply(A1x, x1) - b) / np.linalg.norm(b)
         assert r < r1, (r, r1)
+    # the same chain replayed from a captured graph, twice, equals the eager chain bitwise
+    eager = cpu(ch.target_state).copy(), cpu(ch.seed_state).copy()
+    ch.capture()
+    for _ in range(2):
+        ch.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(cpu(ch.target_state), eager[0])
+        assert np.array_equal(cpu(ch.seed_state), eager[1])
+        ch.run()                      # eager work between the replays
+        torch.cuda.synchronize()
