@@ -333,6 +333,27 @@ typedef enum { XKP_FIELD_MT = 0, XKP_FIELD_X = 1 } xkp_field;
 xkp_status xkp_score_flow(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems, int32_t field,
                           double *const *score, double *const *disp);
 
+/*
+ * Clustered seed selection (the paper's remedy for diverse datasets: one seed per group of
+ * similar images).  k-means on block-mean features: each image (H x H, p = i*H + j) averaged
+ * over pool x pool blocks; farthest-first start (centroid 0 = image 0, centroid k = the image
+ * farthest, in squared distance, from its nearest chosen centroid, lowest index on ties); Lloyd
+ * iterations (nearest centroid, lowest cluster on ties; centroids = member means, an empty
+ * cluster keeps its centroid) until no assignment changes or max_iters assignments; a final
+ * assignment; the seed of cluster c is its member nearest to centroid c (lowest index on ties),
+ * -1 for an empty cluster.
+ *   images:  device, n_img x H x H doubles (the initial log-densities m^0)
+ *   assign:  device, n_img int32 (cluster of each image);  seeds: device, K int32
+ *   iters:   host int32, assignments made (may be NULL)
+ * Requires 1 <= K <= min(64, n_img), pool >= 1 dividing H, max_iters >= 1, H*H <= the
+ * context's max_n.  Host-synchronous (it reads distances back between steps) and allocates its
+ * temporary device memory (features, centroids, distances), freed before it returns: not
+ * capturable.  Distances are summed in a fixed order, so results do not depend on scheduling.
+ */
+xkp_status xkp_cluster_seeds(xkp_ctx *ctx, int32_t n_img, int32_t H, const double *images,
+                             int32_t pool, int32_t K, int32_t max_iters, int32_t *assign,
+                             int32_t *seeds, int32_t *iters);
+
 /* Outcome of xkp_autotune. */
 typedef struct {
     int32_t polish_m;     /* fastest restart length of the polish (for params->polish_m)    */

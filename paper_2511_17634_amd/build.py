@@ -27,6 +27,7 @@ UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIAN
          ("xkp_common.hip", "xkp_common.o", []),
          ("xkp_cnn.hip", "xkp_cnn.o", []),
          ("xkp_epilogue.hip", "xkp_epilogue.o", []),
+         ("xkp_cluster.hip", "xkp_cluster.o", []),
          ("xkp_api.hip", "xkp_api.o", [])]
 ARCH = os.environ.get("XKP_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

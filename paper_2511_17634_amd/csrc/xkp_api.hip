@@ -279,6 +279,84 @@ xkp_status xkp_score_flow(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems
                                                 ctx->max_n));
 }
 
+xkp_status xkp_cluster_seeds(xkp_ctx *ctx, int32_t n_img, int32_t H, const double *images,
+                             int32_t pool, int32_t K, int32_t max_iters, int32_t *assign,
+                             int32_t *seeds, int32_t *iters) {
+    if (!ctx || n_img < 1 || H < 1 || (long)H * H > ctx->max_n || !images || pool < 1 ||
+        H % pool != 0 || K < 1 || K > 64 || K > n_img || max_iters < 1 || !assign || !seeds)
+        return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int N = n_img, d = (H / pool) * (H / pool);
+    hipStream_t st = ctx->stream;
+    double *feat = nullptr;
+    const size_t bytes = sizeof(double) * ((size_t)N * d + (size_t)K * d + N) + sizeof(int) * N;
+    if (hipMalloc((void **)&feat, bytes) != hipSuccess) return XKP_ENOMEM;
+    double *cent = feat + (size_t)N * d, *dist = cent + (size_t)K * d;
+    int *asg = (int *)(dist + N);
+    std::vector<double> hd(N);
+    std::vector<int> ha(N), prev(N);
+    int it = 0;
+    auto run = [&]() -> xkp_status {
+        if (xkp::clu::pool(st, images, N, H, pool, feat) != hipSuccess) return XKP_EDEVICE;
+        // farthest-first start
+        if (hipMemcpyAsync(cent, feat, sizeof(double) * d, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess)
+            return XKP_EDEVICE;
+        for (int k = 1; k < K; ++k) {
+            if (xkp::clu::distances(st, feat, N, d, cent, k, nullptr, dist) != hipSuccess ||
+                hipMemcpyAsync(hd.data(), dist, sizeof(double) * N, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return XKP_EDEVICE;
+            int arg = 0;
+            for (int i = 1; i < N; ++i)
+                if (hd[i] > hd[arg]) arg = i;
+            if (hipMemcpyAsync(cent + (size_t)k * d, feat + (size_t)arg * d, sizeof(double) * d,
+                               hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return XKP_EDEVICE;
+        }
+        // Lloyd iterations
+        bool have = false;
+        while (it < max_iters) {
+            if (xkp::clu::distances(st, feat, N, d, cent, K, asg, dist) != hipSuccess ||
+                hipMemcpyAsync(ha.data(), asg, sizeof(int) * N, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return XKP_EDEVICE;
+            ++it;
+            if (have && ha == prev) break;
+            prev = ha;
+            have = true;
+            if (xkp::clu::update(st, feat, N, d, asg, K, cent) != hipSuccess) return XKP_EDEVICE;
+        }
+        // final assignment and the seed of each cluster
+        if (xkp::clu::distances(st, feat, N, d, cent, K, asg, dist) != hipSuccess ||
+            hipMemcpyAsync(ha.data(), asg, sizeof(int) * N, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(hd.data(), dist, sizeof(double) * N, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return XKP_EDEVICE;
+        std::vector<int> hs(K, -1);
+        for (int i = 0; i < N; ++i) {
+            const int c = ha[i];
+            if (hs[c] < 0 || hd[i] < hd[hs[c]]) hs[c] = i;
+        }
+        if (hipMemcpyAsync(assign, ha.data(), sizeof(int) * N, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipMemcpyAsync(seeds, hs.data(), sizeof(int) * K, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return XKP_EDEVICE;
+        return XKP_OK;
+    };
+    const xkp_status r = run();
+    hipStreamSynchronize(st);
+    hipFree(feat);
+    if (r == XKP_OK && iters) *iters = it;
+    return r;
+}
+
 xkp_status xkp_build_rhs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {
     if (!ctx || n_sys < 0 || (n_sys > 0 && !systems)) return XKP_EINVAL;
     if (n_sys == 0) return XKP_OK;

@@ -82,6 +82,15 @@ hipError_t launch_score_flow(hipStream_t st, const xkp_system *sys, int nsys, in
                              double *const *score, double *const *disp, int nmax);
 }  // namespace epi
 
+// Clustered seed selection (xkp_cluster.hip).
+namespace clu {
+hipError_t pool(hipStream_t st, const double *img, int N, int H, int pool, double *feat);
+hipError_t distances(hipStream_t st, const double *feat, int N, int d, const double *cent, int k,
+                     int *assign, double *dist);
+hipError_t update(hipStream_t st, const double *feat, int N, int d, const int *assign, int K,
+                  double *cent);
+}  // namespace clu
+
 // The learned-guess network (xkp_cnn.hip).
 namespace cnn {
 size_t param_count(int k);

@@ -415,6 +415,22 @@ class Batch:
         return rel.cpu().numpy()
 
 
+def cluster_groups(images, H, assign, seeds):
+    """Groups of a clustered image set: for every non-empty cluster c, its seed image
+    images[seeds[c]] and the other members, in index order, as its targets (one channel)."""
+    images = np.asarray(images, dtype=np.float64).reshape(len(images), -1)
+    assign = np.asarray(assign)
+    groups = []
+    for c, s in enumerate(np.asarray(seeds)):
+        if s < 0:
+            continue
+        members = [i for i in np.nonzero(assign == c)[0] if i != s]
+        if not members:
+            continue
+        groups.append(Group(H, images[s][None], images[members][:, None]))
+    return groups
+
+
 class Chain(Batch):
     """One grid size, one channel: seed_m0 (n,), target_m0 (N, n)."""
 

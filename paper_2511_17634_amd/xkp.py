@@ -84,6 +84,8 @@ def load():
         lib.xkp_basis_accumulate.argtypes = [P, ct.c_int32, ct.c_int32, P, P, ct.c_int32,
                                              ct.c_int32, P]
         lib.xkp_score_flow.argtypes = [P, ct.c_int32, P, ct.c_int32, P, P]
+        lib.xkp_cluster_seeds.argtypes = [P, ct.c_int32, ct.c_int32, P, ct.c_int32, ct.c_int32,
+                                          ct.c_int32, P, P, ct.POINTER(ct.c_int32)]
         lib.xkp_cnn_param_count.argtypes = [ct.c_int32]
         lib.xkp_cnn_param_count.restype = ct.c_size_t
         lib.xkp_cnn_workspace_bytes.argtypes = [ct.c_int32, ct.c_int32]
@@ -102,7 +104,7 @@ def load():
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
                   "xkp_target_project_solve", "xkp_residual", "xkp_apply", "xkp_build_rhs",
                   "xkp_autotune", "xkp_autotune_seeds", "xkp_basis_accumulate",
-                  "xkp_score_flow",
+                  "xkp_score_flow", "xkp_cluster_seeds",
                   "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
             getattr(lib, f).restype = ct.c_int
@@ -255,6 +257,19 @@ class Context:
         place); pointer arrays are int64 CUDA tensors or None."""
         _check(load().xkp_score_flow(self._h, n_sys, _ptr(systems), field, _ptr(score_ptrs),
                                      _ptr(disp_ptrs)), "xkp_score_flow")
+
+    def cluster_seeds(self, images, H, pool, K, max_iters=50):
+        """k-means seed selection on (N, H*H) CUDA float64 images: returns (assign (N,) int32,
+        seeds (K,) int32 CUDA tensors, assignment count); host-synchronous."""
+        import torch
+        N = images.shape[0]
+        assign = torch.empty(N, dtype=torch.int32, device=images.device)
+        seeds = torch.empty(K, dtype=torch.int32, device=images.device)
+        it = ct.c_int32(0)
+        _check(load().xkp_cluster_seeds(self._h, N, H, _ptr(images), pool, K, max_iters,
+                                        _ptr(assign), _ptr(seeds), ct.byref(it)),
+               "xkp_cluster_seeds")
+        return assign, seeds, it.value
 
     def autotune_seeds(self, systems, n_sys, bases_ptrs, params, infos) -> Tuning:
         """Times the seed call over the kernel variants and workgroup counts (host-synchronous);

@@ -54,6 +54,9 @@ CONFIGS = {
                          Group(128, 341, 24, (0.5, 4.0), (0.9, 1.1)))),
     "c5": Config(5, "grid64_learned_guess_4096train_1024eval_T100_m40", T=100, m=40, channels=1,
                  groups=(Group(64, 4096, 8, 2.0, (0.9, 1.1)),)),
+    # diverse set: 4 prototypes x 50 images, interleaved (clustered seed selection)
+    "c7": Config(7, "grid64_200images_4prototypes_T100_m40", T=100, m=40, channels=1,
+                 groups=tuple(Group(64, 50, 8, 2.0, (0.9, 1.1)) for _ in range(4))),
     # image cycle (Experiment 2's protocol): 100 similar images, a new seed every 50
     "c6": Config(6, "grid64_100images_cycle50_a20_T100_m40", T=100, m=40, channels=1,
                  groups=(Group(64, 100, 8, (0.5, 4.0), (0.9, 1.1)),)),
@@ -100,3 +103,15 @@ def cycle_blocks(cfg: Config, cycle: int, count: int | None = None):
         blk = imgs[g0:g0 + cycle, 0].reshape(-1, 1, imgs.shape[-2] * imgs.shape[-1])
         blocks.append((np.ascontiguousarray(blk[0]), np.ascontiguousarray(blk[1:])))
     return blocks
+
+
+def interleaved_images(cfg: Config):
+    """The targets of all groups interleaved (image k from group k mod G, index k // G), as
+    (count, H*H) initial states of one channel: a set whose similar images are not adjacent."""
+    per = [config_images(cfg, g)[1][:, 0] for g in range(len(cfg.groups))]
+    G, n = len(per), min(len(p) for p in per)
+    H = cfg.groups[0].H
+    out = np.empty((G * n, H * H))
+    for k in range(G * n):
+        out[k] = per[k % G][k // G].reshape(-1)
+    return out

@@ -86,6 +86,7 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.xkp_autotune_seeds(None, 1, None, None, ct.byref(P), None, ct.byref(t)) == xkp.EINVAL
     assert lib.xkp_basis_accumulate(None, 4096, 2, None, None, 20, 40, None) == xkp.EINVAL
     assert lib.xkp_score_flow(None, 1, None, 0, None, None) == xkp.EINVAL
+    assert lib.xkp_cluster_seeds(None, 8, 16, None, 4, 2, 10, None, None, None) == xkp.EINVAL
     # the network's sizes and argument checks
     assert lib.xkp_cnn_param_count(40) == 16 * 9 + 16 + 32 * 144 + 32 + 64 * 288 + 64 + 40 * 97
     assert lib.xkp_cnn_param_count(0) == 0 and lib.xkp_cnn_param_count(65) == 0
