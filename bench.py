@@ -315,6 +315,45 @@ def cycle_leg(args):
             "unit": "target systems/s", "legs": legs}
 
 
+def cluster_leg(args):
+    """Diverse set: 200 images at 64x64 from 4 prototypes, interleaved.  k-means seed selection
+    (K = 4 on 8x8 block means) against one seed for all images: projected-guess quality, polish
+    iterations and throughput of the chains."""
+    import torch
+    from paper_2511_17634_amd import xkp
+    from paper_2511_17634_amd.driver import Batch, Group, cluster_groups
+    from synth import CONFIGS, interleaved_images
+    cfg = CONFIGS["c7"]
+    H, T, m, K = 64, cfg.T, cfg.m, 4
+    imgs = interleaved_images(cfg)
+    ctx = xkp.Context(H * H, 8, 1)
+    dimg = torch.tensor(imgs, dtype=torch.float64, device="cuda")
+    ctx.cluster_seeds(dimg, H, 8, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, sd, it = ctx.cluster_seeds(dimg, H, 8, K)
+    cl_ms = (time.perf_counter() - t0) * 1e3
+    groups = cluster_groups(imgs, H, a.cpu().numpy(), sd.cpu().numpy())
+    legs = {}
+    for name, gr in (("clustered", groups),
+                     ("one_seed", [Group(H, imgs[0][None], imgs[1:][:, None])])):
+        b = Batch(gr, T, m, reorth=args.reorth)
+        if not args.no_tune:
+            b.autotune()
+        r = time_chain(b, args, 1, 1, not args.eager)
+        legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
+                      "ms_per_chain": round(r["per_chain_s"] * 1e3, 2), "targets": b.N,
+                      "seeds": b.S, "mean_iters": round(r["iters_mean"], 2),
+                      "mean_guess_residual": round(r["guess_res_mean"], 4),
+                      "verified": r["ok"]}
+        print(f"# cluster {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, mean iters "
+              f"{r['iters_mean']:.1f}, guess residual {r['guess_res_mean']:.4f}",
+              file=sys.stderr, flush=True)
+        del b
+    return {"workload": cfg.name, "K": K, "pool": 8, "cluster_ms": round(cl_ms, 2),
+            "lloyd_assignments": it, "unit": "target systems/s", "legs": legs}
+
+
 def picard_leg(args):
     """64x64 benchmark chain with K = 2 and 3 linearisation passes per timestep (projection for
     the first pass, plain GMRES from the previous iterate for the later ones)."""
@@ -458,8 +497,9 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--no-cycle", action="store_true", help="skip the image-cycle workload")
     ap.add_argument("--no-picard", action="store_true", help="skip the Picard-pass legs")
+    ap.add_argument("--no-cluster", action="store_true", help="skip the clustered-seed legs")
     ap.add_argument("--only", choices=("uneven", "mixed", "learned", "cycle", "epilogue",
-                                       "picard"),
+                                       "picard", "cluster"),
                     help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
     ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
@@ -482,7 +522,8 @@ def main():
     xkp.load()
     if args.only:
         rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
-               "cycle": cycle_leg, "epilogue": epilogue_leg, "picard": picard_leg}[args.only](args)
+               "cycle": cycle_leg, "epilogue": epilogue_leg, "picard": picard_leg,
+               "cluster": cluster_leg}[args.only](args)
         print(json.dumps(rec), flush=True)
         return
     cfg, s0, t0 = build_c2()
@@ -580,6 +621,10 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
     out["epilogue"] = epilogue_leg(args)
+    if not args.no_cluster:
+        out["cluster"] = cluster_leg(args)
+        out["verified"] = out["verified"] and all(
+            v["verified"] for v in out["cluster"]["legs"].values())
     if not args.no_picard:
         out["picard"] = picard_leg(args)
         out["verified"] = out["verified"] and all(
