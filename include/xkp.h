@@ -107,8 +107,9 @@ typedef struct {
     int32_t batch_max_n;  /* largest n among this call's systems, or 0 for the context's
                              max_n; smaller values select leaner kernels.  A system with more
                              unknowns than this gets status XKP_EINVAL.                    */
-    int32_t polish_m;     /* targets: restart length of the polish (and of plain GMRES),
-                             1..64, or 0 for m.  The seed basis dimension stays m.          */
+    int32_t polish_m;     /* restart length of every GMRES cycle whose basis is not kept:
+                             the polish, plain GMRES and a seed's cycles after its kept first
+                             one; 1..64, or 0 for m.  The seed basis dimension stays m.     */
     int32_t reorth;       /* xkp_reorth                                                     */
 } xkp_params;
 
@@ -367,7 +368,7 @@ typedef struct {
 /*
  * Launch autotuner for target calls: times xkp_target_project_solve on the given batch (one
  * representative timestep) for each kernel variant covering the batch (workgroups of 8, 16 or 4
- * wave64s), each candidate restart length of the polish (m/2, 3m/4 and m, at least 8) and each
+ * wave64s), each candidate restart length of the polish (m/4, m/2, 3m/4 and m, at least 8) and each
  * workgroup count per compute unit the kernels can hold (1..occupancy), two timed calls each
  * after one untimed call, and keeps the fastest candidate whose every target converged.  The
  * chosen variant and workgroup count are stored in the context and apply to its later seed and

@@ -474,12 +474,12 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int m = params->m;
     const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
-    int cand_m[3] = {m / 2, (3 * m) / 4, m};
+    int cand_m[4] = {m / 4, m / 2, (3 * m) / 4, m};
     for (int &c : cand_m) {
         if (c < 8) c = 8;
         if (c > m) c = m;
     }
-    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 3, false,
+    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 4, false,
                      [&](const xkp_params &P) {
                          return xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
                                                          &P, infos);

@@ -446,8 +446,9 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                           const Coef &C, xkp_info *info, GmresLds &L) {
     const OpConst o = op_const(s);
     const bool keep = hdr != nullptr;
-    // restart length: the kept seed cycle has m steps; targets may polish with another length
-    const int n = o.n, m = (keep || P.polish_m <= 0) ? P.m : P.polish_m;
+    // restart lengths: the kept first cycle of a seed has m = P.m steps (the basis dimension);
+    // every other cycle (targets, plain GMRES, a seed's later cycles) has polish_m (0: m)
+    const int n = o.n, m = P.m, mpol = P.polish_m > 0 ? P.polish_m : P.m;
     const int tid = threadIdx.x, ldv = ldv_for(o.n);
     BlockRed br{L.red, 0};
     // mixed precision: FP32 operator inside the Krylov cycles and the (discarded) Krylov basis
@@ -518,7 +519,8 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     (mixed && !(keep && first)) ? kMixedCycleDrop * beta : 0.0;
                 const bool two_pass = (keep && first) || P.reorth == XKP_REORTH_ALWAYS;
                 int kk = 0;
-                for (int j = 0; j < m; ++j) {
+                const int mc = (keep && first) ? m : mpol;
+                for (int j = 0; j < mc; ++j) {
                     if constexpr (mixed)
                         stencil_lds_f32<RMAX>(L.vbuf, C, o, w);
                     else

@@ -269,7 +269,7 @@ def test_autotune_picks_a_converging_candidate(X):
     t0 = np.stack([blob_pair(H, seed=90, jitter=1.0 + 0.5 * i)[1] for i in range(6)])
     ch = Chain(H, T, m, s0, t0)
     t = ch.autotune(steps=2)
-    assert t.polish_m in (20, 30, 40) and t.wg_per_cu >= 1 and t.n_tried >= 3
+    assert t.polish_m in (10, 20, 30, 40) and t.wg_per_cu >= 1 and t.n_tried >= 4
     assert 0 < t.ms_best <= t.ms_default * 1.000001
     assert ch.params.polish_m == t.polish_m
     ch.run()
@@ -289,7 +289,8 @@ def test_seed_autotune_keeps_results(X):
     st = b.seed_tuning
     assert st is not None and st.waves in (4, 8, 16) and st.wg_per_cu >= 1
     assert st.n_tried >= 2 and 0 < st.ms_best <= st.ms_default * 1.000001
-    assert st.polish_m == m and t.polish_m in (10, 15, 20)
+    assert st.polish_m == m and t.polish_m in (8, 10, 15, 20)
+    b.params.polish_m = 0          # compare the seeds under the restart length of the reference
     b.run()
     s_inf, t_inf = b.all_infos()
     assert np.all(s_inf["status"] == X.OK) and np.all(t_inf["status"] == X.OK)

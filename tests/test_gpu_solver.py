@@ -315,3 +315,30 @@ def test_reorth_modes_agree(X, H, m):
         P = X.Context.params(m, mode="none")
         P.reorth = 2
         ctx.target_project_solve(d, 1, 1, bases.ptrs, P, ctx.new_infos(1))
+
+
+def test_seed_later_cycles_use_the_polish_restart(X):
+    """A seed whose first cycle does not converge: with polish_m set, its kept basis is bitwise
+    the one of the default run (the kept cycle has m steps either way) and the later cycles,
+    restarted every polish_m steps, still reach the tolerance."""
+    import torch
+    H, T, m = 48, 100, 12
+    ms, _ = blob_pair(H, seed=21)
+    out = {}
+    for pm in (0, 6):
+        n = H * H
+        ctx = X.Context(n, m, 1)
+        b = torch.zeros(n, dtype=torch.float64, device=dev())
+        x = torch.zeros(n, dtype=torch.float64, device=dev())
+        d = X.pack_systems([X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=b, x=x)], dev())
+        ctx.build_rhs(d, 1)
+        bases = X.Bases(1, n, m)
+        info = ctx.new_infos(1)
+        ctx.seed_build(d, 1, bases.ptrs, X.Context.params(m, polish_m=pm), info)
+        torch.cuda.synchronize()
+        out[pm] = (X.infos_to_numpy(info)[0], bases.V_padded(0).clone(), bases.Hbar(0).clone())
+    i0, i6 = out[0][0], out[6][0]
+    assert i0["status"] == i6["status"] == X.OK and i6["res_true"] <= 1e-8
+    assert i0["restarts"] >= 1 and i6["restarts"] > i0["restarts"]
+    assert i0["basis_dim"] == i6["basis_dim"] == m
+    assert torch.equal(out[0][1], out[6][1]) and torch.equal(out[0][2], out[6][2])
