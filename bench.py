@@ -36,13 +36,14 @@ sys.path.insert(0, ROOT)
 METRIC = "target systems solved/sec @ rel-residual 1e-8; projected vs plain GMRES"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the roofline kernel (solve_kernel, plain leg, polish restart 20, 63 systems per
+# HBM traffic of the roofline kernel (solve_kernel, plain leg, polish restart 10, 63 systems per
 # launch), from two rocprofv3 --pmc runs of this file (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch averaged over the 200 target launches).  FETCH_SIZE read 131087 KiB for a 262144 KiB
 # device copy in the same runs (WRITE_SIZE read 262144 KiB): fetch figures are scaled by
-# 262144 / 131087.  Valid only for the kernel sources they were taken with (digest below).
-TRAFFIC = {"csrc_digest": "5b9711de28d47848", "fetch_kib": 251151.5, "write_kib": 85797.3,
-           "fetch_scale": 262144.0 / 131086.6, "write_scale": 1.0}
+# 262144 / 131087.  Valid only for the kernel sources they were taken with (digest below) and
+# the restart length they were taken at.
+TRAFFIC = {"csrc_digest": "1c03ee379d774a4f", "fetch_kib": 35976.2, "write_kib": 95944.5,
+           "fetch_scale": 262144.0 / 131086.5, "write_scale": 1.0, "polish_m": 10}
 
 
 def csrc_digest():
@@ -604,7 +605,8 @@ def main():
         "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes() if args.reorth == "auto" else None,
+                     "traffic": traffic_bytes() if args.reorth == "auto"
+                     and pl["polish_m"] == TRAFFIC["polish_m"] else None,
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
     del plain_chain
