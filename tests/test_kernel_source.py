@@ -6,8 +6,9 @@ import re
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_2511_17634_amd", "csrc", "xkp_kernels.hip")
-GLOBAL_ONLY = ("load_rows", "store_rows", "load_col", "store_col", "mkbuf", "stencil_glob",
-               "load_buf")
+GLOBAL_ONLY = ("load_rows", "store_rows", "load_col", "store_col", "mkbuf", "mkbuf32",
+               "mkbuf16", "load_buf", "load_buf_f32", "store_col_f32", "store_col_bf16",
+               "load_col_any", "sweep_cols")
 LDS_NAMES = re.compile(r"^\s*(vbuf|lds|Ap|zv|alpha|red|L\.\w+)\b")
 
 
