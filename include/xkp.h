@@ -327,7 +327,7 @@ xkp_status xkp_basis_accumulate(xkp_ctx *ctx, int32_t n, int32_t n_src,
  *   disp:    device array of n_sys pointers to 2n doubles updated in place, or NULL / NULL entry
  * g, dt, fx, fy (NULL: 0) come from the descriptor.  A descriptor with H < 1, H*H above the
  * context's max_n, dt <= 0 or a NULL field is skipped.  n_sys <= 65535.  One launch, on the
- * context's stream.
+ * context's stream; 16-byte aligned outputs of even-sided grids take the faster paired path.
  */
 typedef enum { XKP_FIELD_MT = 0, XKP_FIELD_X = 1 } xkp_field;
 
