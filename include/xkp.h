@@ -384,7 +384,7 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
 /*
  * Launch autotuner for seed calls: times xkp_seed_build on the given seeds (one representative
  * timestep) for each kernel variant covering them and each workgroup count per compute unit,
- * two timed calls each after one untimed call, and keeps the fastest candidate whose every seed
+ * five timed calls each after one untimed call, and keeps the fastest candidate whose every seed
  * converged; the variant and workgroup count are stored in the context (meant for a context
  * that serves seed calls only: a seed is one workgroup on the chain's critical path, whose best
  * workgroup size can differ from the targets').  out->polish_m is params->m.

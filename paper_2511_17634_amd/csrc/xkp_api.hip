@@ -378,13 +378,13 @@ xkp_status xkp_apply(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems) {
 }
 
 // Shared timing loop of the autotuners: for each kernel variant covering nmax, each candidate
-// restart length and each workgroup count per compute unit, one untimed and two timed calls of
-// `call(P)`; keeps the fastest candidate whose every system ended with an accepted status.  The
-// chosen variant and workgroup count stay in the context.
+// restart length and each workgroup count per compute unit, one untimed and `timed` timed calls
+// of `call(P)`; keeps the fastest candidate whose every system ended with an accepted status.
+// The chosen variant and workgroup count stay in the context.
 extern "C++" template <typename Call>
 static xkp_status tune_loop(xkp_ctx *ctx, int nmax, int nsys, xkp_info *infos,
                             const xkp_params *params, const int *cand_m, int ncand, bool seeds,
-                            Call call, xkp_tuning *out) {
+                            int timed, Call call, xkp_tuning *out) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -413,7 +413,7 @@ static xkp_status tune_loop(xkp_ctx *ctx, int nmax, int nsys, xkp_info *infos,
                 if (!seeds) P.polish_m = cand_m[ci];
                 ctx->per_cu = w;
                 float ms = 0.f;
-                for (int rep = 0; rep < 3 && result == XKP_OK; ++rep) {
+                for (int rep = 0; rep <= timed && result == XKP_OK; ++rep) {
                     if (rep == 1 && hipEventRecord(e0, ctx->stream) != hipSuccess)
                         result = XKP_EDEVICE;
                     xkp_status st = call(P);
@@ -428,7 +428,7 @@ static xkp_status tune_loop(xkp_ctx *ctx, int nmax, int nsys, xkp_info *infos,
                     result = XKP_EDEVICE;
                     break;
                 }
-                ms *= 0.5f;
+                ms /= (float)timed;
                 ++tried;
                 bool ok = true;
                 for (const xkp_info &i : host)
@@ -479,7 +479,7 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
         if (c < 8) c = 8;
         if (c > m) c = m;
     }
-    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 4, false,
+    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 4, false, 2,
                      [&](const xkp_params &P) {
                          return xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
                                                          &P, infos);
@@ -500,7 +500,7 @@ xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *s
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
     const int cand_m[1] = {params->m};
-    return tune_loop(ctx, nmax, n_seeds, infos, params, cand_m, 1, true,
+    return tune_loop(ctx, nmax, n_seeds, infos, params, cand_m, 1, true, 5,
                      [&](const xkp_params &P) {
                          return xkp_seed_build(ctx, n_seeds, seeds, bases, &P, infos);
                      },
