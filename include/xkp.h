@@ -167,8 +167,8 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
 
 /* Launch shape of the context's later solve calls: workgroups of `waves` wave64s (8, 16 or 4;
  * 16 needs max_n <= 16384, 4 needs max_n <= 4096) and up to wg_per_cu workgroups per compute
- * unit.  Results do not
- * depend on it.  XKP_EUNSUPPORTED if no kernel variant of that size covers max_n. */
+ * unit.  Results do not depend on it (up to rounding: the row-to-thread mapping and the
+ * reduction trees change).  XKP_EUNSUPPORTED if no kernel variant of that size covers max_n. */
 xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
 
 /* Size in bytes of one seed basis buffer for n unknowns and restart length m. */

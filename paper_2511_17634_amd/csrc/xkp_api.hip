@@ -46,7 +46,7 @@ struct Variant {
 // Kernel variants by workgroup size: 8 wave64s (2, 8 or 32 rows per thread for up to 1024, 4096,
 // 16384 unknowns), 16 (4 or 16 rows per thread for up to 4096, 16384) and 4 (4 or 16 rows per
 // thread for up to 1024, 4096).  Variant 0 serves every size and the single-pass kernels
-// (residual, rhs, apply).
+// (residual, rhs, apply, accumulation).
 const Variant kVariants[] = {XKP_VARIANT_TABLE(v512), XKP_VARIANT_TABLE(v1024),
                              XKP_VARIANT_TABLE(v256)};
 constexpr int kNumVariants = 3;

@@ -818,11 +818,12 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
 #pragma unroll
             for (int r = 0; r < 4; ++r) tred[wave * 256 + lane * 4 + r] = acc[ta][tb][r];
             lds_barrier();
-            if (threadIdx.x < 256) {
+            // the 256 entries of the tile, strided over the workgroup
+            for (int e = threadIdx.x; e < 256; e += kNT) {
                 double sum = 0.0;
 #pragma unroll
-                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + threadIdx.x];
-                const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + e];
+                const int l = e >> 2, r = e & 3;
                 const int a = ta * 16 + 4 * r + (l >> 4);
                 const int c = (tc0 + tb) * 16 + (l & 15);
                 if (a < k && c <= k) Ap[a * kLdA + c] = sum;
@@ -907,11 +908,11 @@ __device__ __forceinline__ void vtw_bf16(rsrc_t rV, rsrc_t rW, int n, int ldv, i
 #pragma unroll
             for (int r = 0; r < 4; ++r) tred[wave * 256 + lane * 4 + r] = (double)acc[ta][tb][r];
             lds_barrier();
-            if (threadIdx.x < 256) {
+            for (int e = threadIdx.x; e < 256; e += kNT) {
                 double sum = 0.0;
 #pragma unroll
-                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + threadIdx.x];
-                const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+                for (int w2 = 0; w2 < kNW; ++w2) sum += tred[w2 * 256 + e];
+                const int l = e >> 2, r = e & 3;
                 const int a = ta * 16 + 4 * (l >> 4) + r;
                 const int c = (tc0 + tb) * 16 + (l & 15);
                 if (a < k && c < k) Ap[a * kLdA + c] = sum;
