@@ -280,6 +280,27 @@ def learned_leg(args):
             "legs": legs}
 
 
+def copy_gbs():
+    """A plain device copy for scale: torch copying 1 GiB device-to-device (read + write bytes),
+    timed with HIP events, best of five (a lower bound on the achievable HBM bandwidth; the
+    library's own streaming kernels exceed it)."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2 * 8 * (1 << 27) / best / 1e6
+
+
 def cycle_leg(args):
     """Image cycle (Experiment 2's protocol, 64x64): 100 similar images, a new seed every 50
     images; block 1's targets projected on the basis gathered from both seeds (a = 20 columns
@@ -610,12 +631,17 @@ def main():
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
     del plain_chain
+    cg = copy_gbs()
+    out["roofline"]["torch_copy_gbs"] = round(cg, 1)
     if not args.no_uneven:
         out["uneven"] = uneven_leg(args)
         out["verified"] = out["verified"] and all(
             v["verified"] for k, v in out["uneven"].items() if k in ("project", "plain"))
     if not args.no_mixed:
         out["mixed"] = mixed_leg(args)
+        r128 = out["mixed"].get("plain_fp64", {}).get("roofline")
+        if r128:
+            r128["torch_copy_gbs"] = round(cg, 1)
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["mixed"].values() if isinstance(v, dict))
     if not args.no_learned:
@@ -623,6 +649,7 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["learned"]["legs"].values())
     out["epilogue"] = epilogue_leg(args)
+    out["epilogue"]["roofline"]["torch_copy_gbs"] = round(cg, 1)
     if not args.no_cluster:
         out["cluster"] = cluster_leg(args)
         out["verified"] = out["verified"] and all(
