@@ -33,7 +33,8 @@ enum GmresFlags {
     kStartFromX = 1,   // initial guess is the descriptor's x (the projected x0)
     kKeepBasis = 2,    // seed build: write the first cycle into bases[i]
     kTarget = 4,       // project onto the seed basis first, then polish from the projection
-    kLearned = 8       // try the learned guess first; project only if it fails the gate
+    kLearned = 8,      // try the learned guess first; project only if it fails the gate
+    kDcgs = 16         // seeds: the kept cycle by DCGS2 (set by the launcher when the LDS fits)
 };
 
 // Learned-guess inputs of a solve launch: target i's predicted residual coordinates at

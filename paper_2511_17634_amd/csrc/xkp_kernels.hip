@@ -423,7 +423,7 @@ __device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
 // ----------------------------------------------------------------------------------------
 // LDS layout of the GMRES kernel: vbuf[nlds] | Rp[kMMax*(kMMax+1)/2] | cs | sn | gv | h1 | yv | red
 struct GmresLds {
-    double *vbuf, *Rp, *cs, *sn, *gv, *h1, *h2, *yv, *red;
+    double *vbuf, *Rp, *cs, *sn, *gv, *h1, *h2, *yv, *red, *ext;
     __device__ GmresLds(double *base, int nlds, int npad) {
         vbuf = base + (nlds - npad) / 2;   // front pad
         Rp = base + nlds;
@@ -434,10 +434,177 @@ struct GmresLds {
         h2 = h1 + kMMax + 1;
         yv = h2 + kMMax + 1;
         red = yv + kMMax;
+        ext = red + 2 * kRedSlots * kNW;
     }
 };
 
 __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
+
+// LDS of the delayed-reorthogonalisation cycle (arnoldi_dcgs2), after the GMRES layout:
+//   hbar  unrotated Hessenberg matrix of the cycle, column-major, leading dimension kLdH
+//   part  per-wave partial sums of one step's 2j + 2 inner products (value-major, kNW each)
+//   tot   their workgroup sums: tot[2i] = v_i.u, tot[2i+1] = v_i.z (i < j), then u.u, u.z
+//   f     coefficients of the next pending vector; sc: broadcast scalars and flags
+constexpr int kLdH = kMMax + 1;
+constexpr int kDcgsDoubles = kLdH * kMMax + (2 * kMMax + 2) * kNW + (2 * kMMax + 2) + kLdH + 4;
+struct DcgsLds {
+    double *hbar, *part, *tot, *f, *sc;
+    __device__ explicit DcgsLds(double *ext) {
+        hbar = ext;
+        part = hbar + kLdH * kMMax;
+        tot = part + (2 * kMMax + 2) * kNW;
+        f = tot + 2 * kMMax + 2;
+        sc = f + kLdH;
+    }
+};
+
+// The kept first cycle of a seed by Arnoldi with delayed classical Gram-Schmidt and
+// re-orthogonalisation (DCGS2: A. Bielich, J. Langou, S. Thomas, K. Swirydowicz, I. Yamazaki and
+// E. G. Boman, Parallel Computing 112, 2022), which gives the orthonormal basis and Hessenberg
+// matrix of two Gram-Schmidt passes with ONE workgroup reduction per step instead of one per
+// basis column.  Step j holds the pending vector u = A v_{j-1} - V_j g (orthogonalised once,
+// unnormalised; g = its first-pass coefficients) and forms z = A u; one sweep over v_0..v_{j-1}
+// and one reduction give c = V_j^T u, b = V_j^T z, u.u and u.z.  Then
+//   beta = sqrt(u.u - c.c),  v_j = (u - V_j c) / beta,  H[0..j-1][j-1] = g + c,  H[j][j-1] = beta
+// (the second pass of column j-1), and since A V_j = V_{j+1} Hbar_j, with e = Hbar_j c:
+//   A v_j = (z - V_{j+1} e) / beta,   g'_i = (b_i - e_i) / beta (i < j),
+//   g'_j = ((u.z - c.b) / beta - e_j) / beta,   next u = z / beta - V_{j+1} (e / beta + g')
+// (the first pass of column j, without a reduction of its own).  One more sweep updates both
+// vectors.  Step 0 starts from the normalised v_0 (beta = 1, no correction).  Column j-1 gets its
+// Givens rotation as soon as it is final; the cycle stops at the tolerance, a breakdown or mc
+// columns.  u holds v_0 on entry (also in L.vbuf); returns the column count k, with v_0..v_k,
+// Hbar (also in Hb and, for the mixed-precision seed, the BF16 copy) written as gmres_one's own
+// cycle writes them.
+template <int RMAX>
+__device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, double *V, int ldv,
+                                             int mc, int m, double *Hb, unsigned short *Vb,
+                                             double tol_abs, GmresLds &L, double (&u)[RMAX],
+                                             double (&z)[RMAX], double &gcur, int &iters) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const DcgsLds D(L.ext);
+    int *flg = (int *)(D.sc + 2);
+    for (int j = 0;; ++j) {
+        const bool have_z = j < mc;
+        if (have_z) stencil_lds<RMAX>(L.vbuf, C, o, z);
+        // sweep A: the step's inner products, summed per wave (no barrier per column)
+        if (j > 0) {
+            sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, j, j,
+                [&](int i, const double(&col)[RMAX]) {
+                const double pa = wave_sum(dot_rows<RMAX>(col, u));
+                const double pb = have_z ? wave_sum(dot_rows<RMAX>(col, z)) : 0.0;
+                if (lane == 0) {
+                    D.part[(2 * i) * kNW + wave] = pa;
+                    D.part[(2 * i + 1) * kNW + wave] = pb;
+                }
+            });
+        }
+        {
+            const double puu = wave_sum(dot_rows<RMAX>(u, u));
+            const double puz = have_z ? wave_sum(dot_rows<RMAX>(u, z)) : 0.0;
+            if (lane == 0) {
+                D.part[(2 * j) * kNW + wave] = puu;
+                D.part[(2 * j + 1) * kNW + wave] = puz;
+            }
+        }
+        lds_barrier();
+        for (int t = tid; t < 2 * j + 2; t += kNT) D.tot[t] = tree_sum<kNW>(D.part + t * kNW);
+        lds_barrier();
+        if (wave == 0) {
+            const double uu = D.tot[2 * j], uz = D.tot[2 * j + 1];
+            double beta = 1.0;
+            int stop = 0, brk = 0;
+            // lane l < j holds c_l, b_l and the first-pass g_l of column j-1 (j <= 64)
+            const double cl = lane < j ? D.tot[2 * lane] : 0.0;
+            const double bl = lane < j ? D.tot[2 * lane + 1] : 0.0;
+            const double gl = lane < j ? L.h1[lane] : 0.0;
+            if (j > 0) {
+                const double cc = wave_sum(cl * cl), gg = wave_sum(gl * gl);
+                const double gc = wave_sum(gl * cl);
+                beta = sqrt(fmax(uu - cc, 0.0));
+                const double wn0 = sqrt(fmax(uu + gg + 2.0 * gc, 0.0));   // ||A v_{j-1}||
+                brk = !(beta > 1e-14 * wn0);
+                // column j-1 of Hbar: rows < j from both passes, row j the new norm
+                const double hl = gl + cl;
+                if (lane < j) D.hbar[(j - 1) * kLdH + lane] = hl;
+                if (lane == 0) D.hbar[(j - 1) * kLdH + j] = beta;
+                for (int r = lane; r <= m; r += 64)
+                    Hb[(size_t)(j - 1) * (m + 1) + r] = r < j ? hl : (r == j ? beta : 0.0);
+                // Givens rotations of the earlier columns, then the new one
+                double t = readlane_d(hl, 0);
+                for (int i = 1; i < j; ++i) {
+                    const double c = L.cs[i - 1], sn = L.sn[i - 1], hi = readlane_d(hl, i);
+                    const double rr = c * t + sn * hi;
+                    t = -sn * t + c * hi;
+                    if (lane == 0) L.Rp[tri(j - 1) + i - 1] = rr;
+                }
+                const double den = sqrt(t * t + beta * beta);
+                const double cj = t / den, sj = beta / den;
+                if (lane == 0) {
+                    L.Rp[tri(j - 1) + j - 1] = den;
+                    L.cs[j - 1] = cj;
+                    L.sn[j - 1] = sj;
+                    L.gv[j - 1] = cj * gcur;
+                }
+                gcur = -sj * gcur;
+                stop = (fabs(gcur) <= tol_abs || brk || j == mc) ? 1 : 0;
+            }
+            wave_lds_sync();   // hbar column j-1 and h1 reads before the writes below
+            if (!stop) {
+                // e = Hbar_j c (upper Hessenberg: row i starts at column i - 1), then g' and f
+                const double cb = wave_sum(cl * bl);
+                for (int i = lane; i <= j; i += 64) {
+                    double e = 0.0;
+                    for (int l = i > 0 ? i - 1 : 0; l < j; ++l)
+                        e += D.hbar[l * kLdH + i] * D.tot[2 * l];
+                    const double bi = i < j ? D.tot[2 * i + 1] : 0.0;
+                    const double gp = i < j ? (bi - e) / beta : ((uz - cb) / beta - e) / beta;
+                    L.h1[i] = gp;
+                    D.f[i] = e / beta + gp;
+                }
+            }
+            if (lane == 0) {
+                D.sc[0] = beta;
+                D.sc[1] = gcur;
+                flg[0] = stop;
+                flg[1] = brk;
+            }
+        }
+        lds_barrier();
+        const double beta = D.sc[0];
+        gcur = D.sc[1];
+        const bool stop = __builtin_amdgcn_readfirstlane(flg[0]) != 0;
+        const bool brk = __builtin_amdgcn_readfirstlane(flg[1]) != 0;
+        if (j > 0) ++iters;
+        // sweep B: u - V_j c (-> v_j) and z / beta - V_j f (-> the next pending vector)
+        if (!stop) {
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) z[k] = z[k] / beta;
+        }
+        if (j > 0) {
+            sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, j, j,
+                [&](int i, const double(&col)[RMAX]) {
+                const double ci = D.tot[2 * i];
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) u[k] -= ci * col[k];
+                if (!stop) {
+                    const double fi = D.f[i];
+#pragma unroll
+                    for (int k = 0; k < RMAX; ++k) z[k] -= fi * col[k];
+                }
+            });
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) u[k] = brk ? 0.0 : u[k] / beta;
+            store_col<RMAX>(V + (size_t)j * ldv, ldv, u);
+            if (Vb) store_col_bf16<RMAX>(Vb + (size_t)j * ldv, ldv, u);
+        }
+        if (stop) return j;
+        const double fj = D.f[j];
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) u[k] = z[k] - fj * u[k];
+        store_rows_lds<RMAX>(L.vbuf, u);
+        lds_barrier();
+    }
+}
 
 template <int RMAX, bool MIXED>
 __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags,
@@ -520,7 +687,18 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 const bool two_pass = (keep && first) || P.reorth == XKP_REORTH_ALWAYS;
                 int kk = 0;
                 const int mc = (keep && first) ? m : mpol;
-                for (int j = 0; j < mc; ++j) {
+                // the kept cycle of a launch flagged for it (systems of up to 4096 unknowns,
+                // whose LDS has room for the Hessenberg copy) runs by DCGS2
+                bool dcgs = false;
+                if constexpr (!MIXED && RMAX * kNT <= 4096) {
+                    if (keep && first && (flags & kDcgs)) {
+                        kk = arnoldi_dcgs2<RMAX>(C, o, V, ldv, mc, m, Hb, Vb, P.tol * bnorm, L,
+                                                 cur, w, gcur, iters);
+                        res_est = fabs(gcur) / bnorm;
+                        dcgs = true;
+                    }
+                }
+                for (int j = 0; !dcgs && j < mc; ++j) {
                     if constexpr (mixed)
                         stencil_lds_f32<RMAX>(L.vbuf, C, o, w);
                     else
@@ -1808,7 +1986,13 @@ hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_
                         void *const *keep_bases, xkp_info *infos, double *ws, WsLayout L,
                         int nmax, unsigned *queue, Learned lg) {
     const bool proj = (flags & kTarget) != 0;
-    const SolvePlan sp = solve_plan(nlds, proj || (flags & kLearned) != 0);
+    SolvePlan sp = solve_plan(nlds, proj || (flags & kLearned) != 0);
+    // seeds of up to 4096 unknowns: the kept cycle by DCGS2, its LDS after the GMRES layout
+    if ((flags & kKeepBasis) && !proj && rmax * kNT <= 4096) {
+        const size_t need = gmres_lds_bytes(nlds) + sizeof(double) * kDcgsDoubles;
+        if (need > sp.lds) sp.lds = need;
+        flags |= kDcgs;
+    }
 #define XKP_LAUNCH_SOLVE(PJ)                                                                   \
     {                                                                                          \
         hipError_t e = set_lds(solve_kernel<R, PJ>, sp.lds);                                   \

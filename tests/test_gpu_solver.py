@@ -256,6 +256,53 @@ def test_noconvergence_and_bad_descriptors(X):
         ctx.target_project_solve(d, 2, 0, None, X.Context.params(m, mode="target_galerkin"), inf)
 
 
+@pytest.mark.parametrize("H,m,tol", [(64, 40, 1e-300), (3, 20, 1e-300), (28, 30, 1e-8),
+                                     (80, 30, 1e-300)])
+def test_kept_cycle_basis(X, H, m, tol):
+    """The kept first cycle (delayed re-orthogonalisation with one reduction per step up to 4096
+    unknowns, two modified Gram-Schmidt passes above) against the oracle's two-pass MGS: the
+    whole cycle (tolerance unreachable), a 3x3 grid whose Krylov space is exhausted (breakdown
+    at k <= 9), and a cycle that converges.  Same Hessenberg matrix and basis to rounding,
+    orthonormal, Arnoldi relation, zeros past column k."""
+    import torch
+    T = 100
+    n = H * H
+    ms, _ = blob_pair(H, seed=5 * H + 2) if H > 3 else (np.linspace(0.1, 0.9, n), None)
+    ctx = X.Context(n, m, 1)
+    b = torch.zeros(n, dtype=torch.float64, device=dev())
+    x = torch.zeros(n, dtype=torch.float64, device=dev())
+    d = X.pack_systems([X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=b, x=x)], dev())
+    ctx.build_rhs(d, 1)
+    bases = X.Bases(1, n, m)
+    info = ctx.new_infos(1)
+    ctx.seed_build(d, 1, bases.ptrs, X.Context.params(m, tol=tol, max_restarts=0), info)
+    torch.cuda.synchronize()
+    i = X.infos_to_numpy(info)[0]
+    A = oracle.Operator(H, 1.0 / T, 0.5, ms)
+    bo = oracle.rhs(A, ms)
+    ro = oracle.gmres(A, bo, m=m, max_restarts=0, tol=tol, keep_basis=True)
+    k = int(bases.header(0)["k"])
+    assert k == ro.basis_dim == int(i["basis_dim"]) == int(i["iters"])
+    if H == 3:
+        assert k <= n < m
+    elif tol < 1e-100:
+        assert k == m and i["status"] == X.ENOCONV
+    else:
+        assert k < m and i["status"] == X.OK
+    V = cpu(bases.V(0))
+    Hb = cpu(bases.Hbar(0))
+    scale = np.abs(ro.Hbar).max()
+    assert np.abs(Hb[:k + 1, :k] - ro.Hbar[:k + 1, :k]).max() <= 1e-9 * scale
+    for c in range(min(8, k + 1)):
+        assert np.abs(V[:, c] - ro.V[:, c]).max() <= 1e-10
+    if H != 3:   # past a breakdown the last column is zero on both sides
+        assert np.abs(V[:, :k + 1].T @ V[:, :k + 1] - np.eye(k + 1)).max() <= 1e-12
+    AV = np.stack([oracle.apply(A, V[:, c]) for c in range(k)], axis=1)
+    assert np.abs(AV - V[:, :k + 1] @ Hb[:k + 1, :k]).max() <= 1e-12 * row_norm(A)
+    assert np.all(Hb[k + 1:, :] == 0) and np.all(Hb[:, k:] == 0)
+    assert abs(i["res_true"] - ro.res_true) <= 1e-12
+
+
 @pytest.mark.parametrize("reorth,passes", [("auto", 1), ("always", 2)])
 def test_gram_schmidt_passes_match_oracle(X, reorth, passes):
     """One cycle of eight Arnoldi steps from x_base = 0 (tolerance unreachable, no restart): the
