@@ -929,10 +929,13 @@ __device__ bool lsq_hessenberg_wave(double *A, int lda, int kk, double *z, doubl
     return false;
 }
 
-// Partial [V_k^T W] over the 4-row groups g = wave, wave + kNW, ... for KTR row tiles and NTC
+// Partial [V_k^T W] over the 8-row groups g = wave, wave + kNW, ... for KTR row tiles and NTC
 // column tiles starting at column tile tc0, FP64 matrix cores (v_mfma_f64_16x16x4: A 16x4 from
-// lane i + 16 kk, B 4x16 from lane j + 16 kk).  Each wave keeps all KTR x NTC accumulators;
-// the operands of the next group are loaded before the current group's products.
+// lane i + 16 kk, B 4x16 from lane j + 16 kk).  Lane l loads rows 8g + 2(l/16) and the next one
+// of its column in one 16-byte access; the group's first product takes the first of each pair
+// (rows 8g, 8g+2, 8g+4, 8g+6 as kk = 0..3), the second the other rows: the same row for A and
+// B in every product, 8 rows per load.  Each wave keeps all KTR x NTC accumulators; the
+// operands of the next group are loaded before the current group's products.
 template <int KTR, int NTC>
 __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, int k, int tc0,
                                           double *Ap, double *tred) {
@@ -956,36 +959,47 @@ __device__ __forceinline__ void vtw_chunk(rsrc_t rV, rsrc_t rW, int n, int ldv, 
     for (int a = 0; a < KTR; ++a)
 #pragma unroll
         for (int b = 0; b < NTC; ++b) acc[a][b] = double4_t{0.0, 0.0, 0.0, 0.0};
-    const int ngroups = (n + 3) / 4;
-    double an[KTR], bn[NTC];
+    // rows p, p + 1 lie inside the column (ldv is a multiple of 8 above n); rows at or past n
+    // are zeroed
+    const int ngroups = (n + 7) / 8;
+    double2_t an[KTR], bn[NTC];
     int g = wave;
     {
-        const unsigned p = 4u * g + (lane >> 4), po = p * 8u;
+        const unsigned po = (8u * g + 2u * (lane >> 4)) * 8u;
 #pragma unroll
-        for (int t = 0; t < KTR; ++t) an[t] = bld(rV, offA[t] + po);
+        for (int t = 0; t < KTR; ++t) an[t] = bld2(rV, offA[t] + po);
 #pragma unroll
-        for (int t = 0; t < NTC; ++t) bn[t] = bld(rW, offB[t] + po);
+        for (int t = 0; t < NTC; ++t) bn[t] = bld2(rW, offB[t] + po);
     }
     for (; g < ngroups; g += kNW) {
-        const unsigned p = 4u * g + (lane >> 4);
-        const bool pin = p < (unsigned)n;
-        double av[KTR], bv[NTC];
+        const unsigned p = 8u * g + 2u * (lane >> 4);
+        const bool pin0 = p < (unsigned)n, pin1 = p + 1u < (unsigned)n;
+        double2_t av[KTR], bv[NTC];
 #pragma unroll
-        for (int t = 0; t < KTR; ++t) av[t] = (okA[t] && pin) ? an[t] : 0.0;
+        for (int t = 0; t < KTR; ++t) {
+            av[t][0] = (okA[t] && pin0) ? an[t][0] : 0.0;
+            av[t][1] = (okA[t] && pin1) ? an[t][1] : 0.0;
+        }
 #pragma unroll
-        for (int t = 0; t < NTC; ++t) bv[t] = (okB[t] && pin) ? bn[t] : 0.0;
+        for (int t = 0; t < NTC; ++t) {
+            bv[t][0] = (okB[t] && pin0) ? bn[t][0] : 0.0;
+            bv[t][1] = (okB[t] && pin1) ? bn[t][1] : 0.0;
+        }
         // next group's operands (past the end: clamped to the last group, never used)
         const int gn = g + kNW < ngroups ? g + kNW : g;
-        const unsigned pon = (4u * gn + (lane >> 4)) * 8u;
+        const unsigned pon = (8u * gn + 2u * (lane >> 4)) * 8u;
 #pragma unroll
-        for (int t = 0; t < KTR; ++t) an[t] = bld(rV, offA[t] + pon);
+        for (int t = 0; t < KTR; ++t) an[t] = bld2(rV, offA[t] + pon);
 #pragma unroll
-        for (int t = 0; t < NTC; ++t) bn[t] = bld(rW, offB[t] + pon);
+        for (int t = 0; t < NTC; ++t) bn[t] = bld2(rW, offB[t] + pon);
 #pragma unroll
-        for (int a = 0; a < KTR; ++a)
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int b = 0; b < NTC; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < KTR; ++a)
+#pragma unroll
+                for (int b = 0; b < NTC; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a][h], bv[b][h],
+                                                                      acc[a][b], 0, 0, 0);
     }
     // reduce each tile over the waves in a fixed order; lane l, register r holds
     // D[4r + l/16][l%16] of the 16x16 tile
