@@ -56,11 +56,17 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // Sum over the 64 lanes, same fixed order on every call (deterministic); every lane gets it.
 // quad_perm [1,0,3,2] and [2,3,0,1] give quad sums, row_ror 4 and 8 give 16-lane row sums,
 // then the four row sums are read out and added.
-__device__ __forceinline__ double wave_sum(double v) {
+// Sum over each 16-lane row, every lane of the row getting it: the first four steps below.
+__device__ __forceinline__ double row_sum16(double v) {
     v += dpp_d<0xB1>(v);
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x124>(v);
     v += dpp_d<0x128>(v);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_sum16(v);
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 

@@ -442,17 +442,20 @@ __device__ __forceinline__ int tri(int c) { return c * (c + 1) / 2; }
 
 // LDS of the delayed-reorthogonalisation cycle (arnoldi_dcgs2), after the GMRES layout:
 //   hbar  unrotated Hessenberg matrix of the cycle, column-major, leading dimension kLdH
-//   part  per-wave partial sums of one step's 2j + 2 inner products (value-major, kNW each)
+//   part  per-row partial sums of one step's 2j + 2 inner products (value-major, 4 kNW each:
+//         the 16-lane rows of every wave)
 //   tot   their workgroup sums: tot[2i] = v_i.u, tot[2i+1] = v_i.z (i < j), then u.u, u.z
 //   f     coefficients of the next pending vector; sc: broadcast scalars and flags
 constexpr int kLdH = kMMax + 1;
-constexpr int kDcgsDoubles = kLdH * kMMax + (2 * kMMax + 2) * kNW + (2 * kMMax + 2) + kLdH + 4;
+constexpr int kDcgsParts = 4 * kNW;   // partial sums per value
+constexpr int kDcgsDoubles =
+    kLdH * kMMax + (2 * kMMax + 2) * kDcgsParts + (2 * kMMax + 2) + kLdH + 4;
 struct DcgsLds {
     double *hbar, *part, *tot, *f, *sc;
     __device__ explicit DcgsLds(double *ext) {
         hbar = ext;
         part = hbar + kLdH * kMMax;
-        tot = part + (2 * kMMax + 2) * kNW;
+        tot = part + (2 * kMMax + 2) * kDcgsParts;
         f = tot + 2 * kMMax + 2;
         sc = f + kLdH;
     }
@@ -471,8 +474,8 @@ struct DcgsLds {
 //   g'_j = ((u.z - c.b) / beta - e_j) / beta,   next u = z / beta - V_{j+1} (e / beta + g')
 // (the first pass of column j, without a reduction of its own).  One more sweep updates both
 // vectors.  Step 0 starts from the normalised v_0 (beta = 1, no correction).  Column j-1 gets its
-// Givens rotation as soon as it is final; the cycle stops at the tolerance, a breakdown or mc
-// columns.  u holds v_0 on entry (also in L.vbuf); returns the column count k, with v_0..v_k,
+// Givens rotation as soon as it is final (wave 1, while wave 0 forms e and the coefficients);
+// the cycle stops at the tolerance, a breakdown or mc columns.  u holds v_0 on entry (also in L.vbuf); returns the column count k, with v_0..v_k,
 // Hbar (also in Hb and, for the mixed-precision seed, the BF16 copy) written as gmres_one's own
 // cycle writes them.
 template <int RMAX>
@@ -483,90 +486,120 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const DcgsLds D(L.ext);
     int *flg = (int *)(D.sc + 2);
+    // wave 1, lane i: the rotation of row i (set when column i is final)
+    double cs_r = 1.0, sn_r = 0.0;
+    const int slot = wave * 4 + (lane >> 4);   // this lane's row partial, written by row lane 0
+    const bool row_lead = (lane & 15) == 0;
     for (int j = 0;; ++j) {
         const bool have_z = j < mc;
         if (have_z) stencil_lds<RMAX>(L.vbuf, C, o, z);
-        // sweep A: the step's inner products, summed per wave (no barrier per column)
+        // sweep A: the step's inner products, summed per 16-lane row (no barrier per column)
         if (j > 0) {
             sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, j, j,
                 [&](int i, const double(&col)[RMAX]) {
-                const double pa = wave_sum(dot_rows<RMAX>(col, u));
-                const double pb = have_z ? wave_sum(dot_rows<RMAX>(col, z)) : 0.0;
-                if (lane == 0) {
-                    D.part[(2 * i) * kNW + wave] = pa;
-                    D.part[(2 * i + 1) * kNW + wave] = pb;
+                const double pa = row_sum16(dot_rows<RMAX>(col, u));
+                const double pb = have_z ? row_sum16(dot_rows<RMAX>(col, z)) : 0.0;
+                if (row_lead) {
+                    D.part[(2 * i) * kDcgsParts + slot] = pa;
+                    D.part[(2 * i + 1) * kDcgsParts + slot] = pb;
                 }
             });
         }
         {
-            const double puu = wave_sum(dot_rows<RMAX>(u, u));
-            const double puz = have_z ? wave_sum(dot_rows<RMAX>(u, z)) : 0.0;
-            if (lane == 0) {
-                D.part[(2 * j) * kNW + wave] = puu;
-                D.part[(2 * j + 1) * kNW + wave] = puz;
+            const double puu = row_sum16(dot_rows<RMAX>(u, u));
+            const double puz = have_z ? row_sum16(dot_rows<RMAX>(u, z)) : 0.0;
+            if (row_lead) {
+                D.part[(2 * j) * kDcgsParts + slot] = puu;
+                D.part[(2 * j + 1) * kDcgsParts + slot] = puz;
             }
         }
         lds_barrier();
-        for (int t = tid; t < 2 * j + 2; t += kNT) D.tot[t] = tree_sum<kNW>(D.part + t * kNW);
+        for (int t = tid; t < 2 * j + 2; t += kNT)
+            D.tot[t] = tree_sum<kDcgsParts>(D.part + t * kDcgsParts);
         lds_barrier();
-        if (wave == 0) {
+        if (wave < 2) {
+            // waves 0 and 1 both form beta and the breakdown test from the same sums (the
+            // same values); wave 0 then builds e, g' and f, wave 1 the rotations
             const double uu = D.tot[2 * j], uz = D.tot[2 * j + 1];
             double beta = 1.0;
-            int stop = 0, brk = 0;
-            // lane l < j holds c_l, b_l and the first-pass g_l of column j-1 (j <= 64)
+            int brk = 0;
+            // lane l < j holds c_l, b_l and the first-pass g_l of column j-1 (j <= 64); the
+            // first-pass coefficients alternate between h1 and h2 by step, so that wave 0's
+            // new ones never overwrite those wave 1 still reads
+            double *g_in = (j & 1) ? L.h2 : L.h1, *g_out = (j & 1) ? L.h1 : L.h2;
             const double cl = lane < j ? D.tot[2 * lane] : 0.0;
             const double bl = lane < j ? D.tot[2 * lane + 1] : 0.0;
-            const double gl = lane < j ? L.h1[lane] : 0.0;
+            const double gl = lane < j ? g_in[lane] : 0.0;
+            const double hl = gl + cl;
             if (j > 0) {
                 const double cc = wave_sum(cl * cl), gg = wave_sum(gl * gl);
                 const double gc = wave_sum(gl * cl);
                 beta = sqrt(fmax(uu - cc, 0.0));
                 const double wn0 = sqrt(fmax(uu + gg + 2.0 * gc, 0.0));   // ||A v_{j-1}||
                 brk = !(beta > 1e-14 * wn0);
-                // column j-1 of Hbar: rows < j from both passes, row j the new norm
-                const double hl = gl + cl;
-                if (lane < j) D.hbar[(j - 1) * kLdH + lane] = hl;
-                if (lane == 0) D.hbar[(j - 1) * kLdH + j] = beta;
-                for (int r = lane; r <= m; r += 64)
-                    Hb[(size_t)(j - 1) * (m + 1) + r] = r < j ? hl : (r == j ? beta : 0.0);
-                // Givens rotations of the earlier columns, then the new one
-                double t = readlane_d(hl, 0);
-                for (int i = 1; i < j; ++i) {
-                    const double c = L.cs[i - 1], sn = L.sn[i - 1], hi = readlane_d(hl, i);
-                    const double rr = c * t + sn * hi;
-                    t = -sn * t + c * hi;
-                    if (lane == 0) L.Rp[tri(j - 1) + i - 1] = rr;
-                }
-                const double den = sqrt(t * t + beta * beta);
-                const double cj = t / den, sj = beta / den;
-                if (lane == 0) {
-                    L.Rp[tri(j - 1) + j - 1] = den;
-                    L.cs[j - 1] = cj;
-                    L.sn[j - 1] = sj;
-                    L.gv[j - 1] = cj * gcur;
-                }
-                gcur = -sj * gcur;
-                stop = (fabs(gcur) <= tol_abs || brk || j == mc) ? 1 : 0;
             }
-            wave_lds_sync();   // hbar column j-1 and h1 reads before the writes below
-            if (!stop) {
-                // e = Hbar_j c (upper Hessenberg: row i starts at column i - 1), then g' and f
+            if (wave == 0) {
+                if (j > 0) {
+                    // column j-1 of Hbar: rows < j from both passes, row j the new norm
+                    if (lane < j) D.hbar[(j - 1) * kLdH + lane] = hl;
+                    if (lane == 0) D.hbar[(j - 1) * kLdH + j] = beta;
+                }
+                wave_lds_sync();   // the column above before the reads below
+                // e = Hbar_j c in four independent partial sums (lane i holds row i: j < 64
+                // unless the cycle stops at this step, when e is not used; entries of column
+                // l below row l + 1 are not read), then g' and f
                 const double cb = wave_sum(cl * bl);
-                for (int i = lane; i <= j; i += 64) {
-                    double e = 0.0;
-                    for (int l = i > 0 ? i - 1 : 0; l < j; ++l)
-                        e += D.hbar[l * kLdH + i] * D.tot[2 * l];
-                    const double bi = i < j ? D.tot[2 * i + 1] : 0.0;
-                    const double gp = i < j ? (bi - e) / beta : ((uz - cb) / beta - e) / beta;
-                    L.h1[i] = gp;
+                const int i = lane;
+                double e4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int l0 = 0; l0 < j; l0 += 4) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int l = l0 + q;
+                        if (l < j && l + 1 >= i) e4[q] += D.hbar[l * kLdH + i] * D.tot[2 * l];
+                    }
+                }
+                const double e = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+                if (i <= j) {
+                    const double gp = i < j ? (bl - e) / beta : ((uz - cb) / beta - e) / beta;
+                    g_out[i] = gp;
                     D.f[i] = e / beta + gp;
                 }
-            }
-            if (lane == 0) {
-                D.sc[0] = beta;
-                D.sc[1] = gcur;
-                flg[0] = stop;
-                flg[1] = brk;
+                if (lane == 0) {
+                    D.sc[0] = beta;
+                    flg[1] = brk;
+                }
+            } else {
+                int stop = 0;
+                if (j > 0) {
+                    for (int r = lane; r <= m; r += 64)
+                        Hb[(size_t)(j - 1) * (m + 1) + r] = r < j ? hl : (r == j ? beta : 0.0);
+                    // Givens rotations of the earlier columns (lane-held), then the new one;
+                    // lane i - 1 writes the rotated entry of row i - 1
+                    double t = readlane_d(hl, 0);
+                    for (int i = 1; i < j; ++i) {
+                        const double c = readlane_d(cs_r, i - 1), sn = readlane_d(sn_r, i - 1);
+                        const double hi = readlane_d(hl, i);
+                        const double rr = c * t + sn * hi;
+                        t = -sn * t + c * hi;
+                        if (lane == i - 1) L.Rp[tri(j - 1) + i - 1] = rr;
+                    }
+                    const double den = sqrt(t * t + beta * beta);
+                    const double cj = t / den, sj = beta / den;
+                    if (lane == j - 1) {
+                        cs_r = cj;
+                        sn_r = sj;
+                    }
+                    if (lane == 0) {
+                        L.Rp[tri(j - 1) + j - 1] = den;
+                        L.gv[j - 1] = cj * gcur;
+                    }
+                    gcur = -sj * gcur;
+                    stop = (fabs(gcur) <= tol_abs || brk || j == mc) ? 1 : 0;
+                }
+                if (lane == 0) {
+                    D.sc[1] = gcur;
+                    flg[0] = stop;
+                }
             }
         }
         lds_barrier();
@@ -581,13 +614,18 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
             for (int k = 0; k < RMAX; ++k) z[k] = z[k] / beta;
         }
         if (j > 0) {
+            // each column's two coefficients are read one column ahead
+            double cn = D.tot[0], fn = stop ? 0.0 : D.f[0];
             sweep_cols<RMAX, Depth<RMAX>::value>(V, ldv, j, j,
                 [&](int i, const double(&col)[RMAX]) {
-                const double ci = D.tot[2 * i];
+                const double ci = cn, fi = fn;
+                if (i + 1 < j) {
+                    cn = D.tot[2 * (i + 1)];
+                    if (!stop) fn = D.f[i + 1];
+                }
 #pragma unroll
                 for (int k = 0; k < RMAX; ++k) u[k] -= ci * col[k];
                 if (!stop) {
-                    const double fi = D.f[i];
 #pragma unroll
                     for (int k = 0; k < RMAX; ++k) z[k] -= fi * col[k];
                 }
