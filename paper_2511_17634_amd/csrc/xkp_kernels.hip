@@ -891,6 +891,7 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
 // <= 1e-13 max|A| reports singular.  The solution goes to out[0..kk).
 __device__ bool lu_solve_wave(double *A, int lda, int kk, double zr, double *out, int *pivl) {
     const int r = threadIdx.x;
+    kk = __builtin_amdgcn_readfirstlane(kk);
     double rowmax = 0.0;
     if (r < kk)
         for (int q = 0; q < kk; ++q) rowmax = fmax(rowmax, fabs(A[r * lda + q]));
@@ -914,7 +915,20 @@ __device__ bool lu_solve_wave(double *A, int lda, int kk, double zr, double *out
         if (active) {
             const double l = A[r * lda + c] / piv;
             A[r * lda + c] = 0.0;
-            for (int q = c + 1; q < kk; ++q) A[r * lda + q] -= l * A[pl * lda + q];
+            // eight entries per round trip: all reads of a chunk before its writes, so the
+            // reads do not wait for the previous entry's write
+            for (int q0 = c + 1; q0 < kk; q0 += 8) {
+                double pr[8], own[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int q = q0 + t < kk ? q0 + t : kk - 1;
+                    pr[t] = A[pl * lda + q];
+                    own[t] = A[r * lda + q];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (q0 + t < kk) A[r * lda + q0 + t] = own[t] - l * pr[t];
+            }
             zr -= l * zp;
         }
         wave_lds_sync();
@@ -1182,7 +1196,9 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
             // the mixed target-Galerkin contraction needs the seed's BF16 basis copy
             if (ok && P.precision == XKP_MIXED && P.mode == XKP_PROJ_TARGET_GALERKIN)
                 ok = hdr->bf16 == 1;
-            if (ok) k = hdr->k;
+            // the same header for the whole workgroup: a scalar basis dimension keeps every
+            // loop over the columns on scalar branches
+            if (ok) k = __builtin_amdgcn_readfirstlane(hdr->k);
         }
         if (!ok) {
             if (tid == 0) {
