@@ -607,11 +607,12 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
         gcur = D.sc[1];
         const bool stop = __builtin_amdgcn_readfirstlane(flg[0]) != 0;
         const bool brk = __builtin_amdgcn_readfirstlane(flg[1]) != 0;
+        const double rbeta = 1.0 / beta;   // one division, then products per row
         if (j > 0) ++iters;
         // sweep B: u - V_j c (-> v_j) and z / beta - V_j f (-> the next pending vector)
         if (!stop) {
 #pragma unroll
-            for (int k = 0; k < RMAX; ++k) z[k] = z[k] / beta;
+            for (int k = 0; k < RMAX; ++k) z[k] = z[k] * rbeta;
         }
         if (j > 0) {
             // each column's two coefficients are read one column ahead
@@ -631,7 +632,7 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
                 }
             });
 #pragma unroll
-            for (int k = 0; k < RMAX; ++k) u[k] = brk ? 0.0 : u[k] / beta;
+            for (int k = 0; k < RMAX; ++k) u[k] = brk ? 0.0 : u[k] * rbeta;
             store_col<RMAX>(V + (size_t)j * ldv, ldv, u);
             if (Vb) store_col_bf16<RMAX>(Vb + (size_t)j * ldv, ldv, u);
         }
@@ -781,9 +782,10 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     });
                     const double hn = sqrt(br.sum(dot_rows<RMAX>(w, w)));
                     const bool brk = !(hn > 1e-14 * wn0);
+                    const double rhn = 1.0 / hn;   // one division, then products per row
 #pragma unroll
                     for (int k = 0; k < RMAX; ++k) {
-                        w[k] = brk ? 0.0 : w[k] / hn;
+                        w[k] = brk ? 0.0 : w[k] * rhn;
                         if constexpr (vf32) w[k] = (double)(float)w[k];
                     }
                     if constexpr (vf32)
