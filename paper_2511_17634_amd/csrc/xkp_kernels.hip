@@ -560,9 +560,10 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
                 }
                 const double e = (e4[0] + e4[1]) + (e4[2] + e4[3]);
                 if (i <= j) {
-                    const double gp = i < j ? (bl - e) / beta : ((uz - cb) / beta - e) / beta;
+                    const double rb = 1.0 / beta;
+                    const double gp = i < j ? (bl - e) * rb : ((uz - cb) * rb - e) * rb;
                     g_out[i] = gp;
-                    D.f[i] = e / beta + gp;
+                    D.f[i] = e * rb + gp;
                 }
                 if (lane == 0) {
                     D.sc[0] = beta;
@@ -583,8 +584,8 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
                         t = -sn * t + c * hi;
                         if (lane == i - 1) L.Rp[tri(j - 1) + i - 1] = rr;
                     }
-                    const double den = sqrt(t * t + beta * beta);
-                    const double cj = t / den, sj = beta / den;
+                    const double den = sqrt(t * t + beta * beta), rden = 1.0 / den;
+                    const double cj = t * rden, sj = beta * rden;
                     if (lane == j - 1) {
                         cs_r = cj;
                         sn_r = sj;
@@ -800,7 +801,8 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                             Hb[(size_t)j * (m + 1) + r] = r <= j ? L.h2[r] : (r == j + 1 ? hn : 0.0);
                     }
                     const double den = sqrt(t * t + hn * hn);
-                    const double cj = t / den, sj = hn / den;
+                    const double rden = 1.0 / den;
+                    const double cj = t * rden, sj = hn * rden;
                     if (tid == 0) {
                         L.Rp[tri(j) + j] = den;
                         L.cs[j] = cj;
@@ -809,15 +811,16 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                     }
                     gcur = -sj * gcur;
                     kk = j + 1;
-                    res_est = fabs(gcur) / bnorm;
                     lds_barrier();
                     if (fabs(gcur) <= fmax(P.tol * bnorm, gfloor) || brk) break;
                 }
-                // y = R^{-1} g by one wavefront (lane c holds g_c), column-oriented
+                if (!dcgs) res_est = fabs(gcur) / bnorm;
+                // y = R^{-1} g by one wavefront (lane c holds g_c and 1 / R_cc), column-oriented
                 if (tid < 64) {
                     double gl = (tid < kk) ? L.gv[tid] : 0.0;
+                    const double rdiag = (tid < kk) ? 1.0 / L.Rp[tri(tid) + tid] : 0.0;
                     for (int c = kk - 1; c >= 0; --c) {
-                        const double yc = readlane_d(gl, c) / L.Rp[tri(c) + c];
+                        const double yc = readlane_d(gl, c) * readlane_d(rdiag, c);
                         if (tid < c) gl -= L.Rp[tri(c) + tid] * yc;
                         if (tid == 0) L.yv[c] = yc;
                     }
@@ -935,9 +938,11 @@ __device__ bool lu_solve_wave(double *A, int lda, int kk, double zr, double *out
         }
         wave_lds_sync();
     }
+    // the reciprocal of each pivot, in its row's lane (rows that were no pivot hold 0)
+    const double rpiv = pc < kk ? 1.0 / A[r * lda + pc] : 0.0;
     for (int c = kk - 1; c >= 0; --c) {
         const int pl = __builtin_amdgcn_readfirstlane(pivl[c]);
-        const double xc = readlane_d(zr, pl) / A[pl * lda + c];
+        const double xc = readlane_d(zr, pl) * readlane_d(rpiv, pl);
         if (pc < c) zr -= A[r * lda + c] * xc;
         if (r == 0) out[c] = xc;
     }
