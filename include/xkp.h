@@ -77,11 +77,12 @@ typedef enum {
  * modified Gram-Schmidt passes give; a GMRES cycle whose basis is discarded (target polish, plain
  * GMRES, the seed's later cycles) converges as well with one pass, GMRES with modified
  * Gram-Schmidt being backward stable (Paige, Rozloznik and Strakos, SIAM J. Matrix Anal. Appl.
- * 28, 2006), at half the basis traffic and half the sequential reductions.  For systems of up to
- * 4096 unknowns the kept cycle gets its two passes by delayed classical Gram-Schmidt with
- * re-orthogonalisation (DCGS2, Bielich et al., Parallel Computing 112, 2022): the same basis and
- * Hessenberg matrix to rounding, with one workgroup reduction per Arnoldi step instead of one per
- * basis column; larger systems use two modified Gram-Schmidt passes.
+ * 28, 2006), at half the basis traffic and half the sequential reductions.  In a seed call whose
+ * largest system (params->batch_max_n, or the context's max_n) has at most 4096 unknowns the
+ * kept cycle gets its two passes by delayed classical Gram-Schmidt with re-orthogonalisation
+ * (DCGS2, Bielich et al., Parallel Computing 112, 2022): the same basis and Hessenberg matrix to
+ * rounding, with one workgroup reduction per Arnoldi step instead of one per basis column;
+ * larger calls use two modified Gram-Schmidt passes.
  */
 typedef enum {
     XKP_REORTH_AUTO = 0,   /* two passes while a basis is kept, one pass elsewhere          */

@@ -303,6 +303,36 @@ def test_kept_cycle_basis(X, H, m, tol):
     assert abs(i["res_true"] - ro.res_true) <= 1e-12
 
 
+def test_kept_cycle_paths_agree(X):
+    """The same 64x64 seed in a launch for systems of at most 4096 unknowns (the kept cycle by
+    delayed re-orthogonalisation) and in one sized for 128x128 (two modified Gram-Schmidt
+    passes): same basis dimension and steps, basis, Hessenberg matrix and solution equal to
+    rounding."""
+    import torch
+    H, T, m = 64, 100, 40
+    n = H * H
+    ms, _ = blob_pair(H, seed=11)
+    ctx = X.Context(128 * 128, m, 1)
+    out = []
+    for batch_max_n in (n, 0):
+        b = torch.zeros(n, dtype=torch.float64, device=dev())
+        x = torch.zeros(n, dtype=torch.float64, device=dev())
+        d = X.pack_systems([X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=b, x=x)], dev())
+        ctx.build_rhs(d, 1)
+        bases = X.Bases(1, n, m)
+        info = ctx.new_infos(1)
+        ctx.seed_build(d, 1, bases.ptrs, X.Context.params(m, batch_max_n=batch_max_n), info)
+        torch.cuda.synchronize()
+        out.append((X.infos_to_numpy(info)[0], bases.header(0)["k"], cpu(bases.V(0)),
+                    cpu(bases.Hbar(0)), cpu(x)))
+    (i1, k1, V1, H1, x1), (i2, k2, V2, H2, x2) = out
+    assert i1["status"] == i2["status"] == X.OK
+    assert k1 == k2 and i1["iters"] == i2["iters"]
+    assert np.abs(H1 - H2).max() <= 1e-9 * np.abs(H2).max()
+    assert np.abs(V1[:, :8] - V2[:, :8]).max() <= 1e-10
+    assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x2).max()
+
+
 @pytest.mark.parametrize("reorth,passes", [("auto", 1), ("always", 2)])
 def test_gram_schmidt_passes_match_oracle(X, reorth, passes):
     """One cycle of eight Arnoldi steps from x_base = 0 (tolerance unreachable, no restart): the
