@@ -57,7 +57,7 @@ typedef enum {
     XKP_EDEVICE = 3,       /* HIP runtime error                                           */
     XKP_ENOCONV = 4,       /* GMRES hit max_restarts; x holds the last iterate            */
     XKP_ESINGULAR = 5,     /* projected k x k system had a zero pivot; x0 = x_base used   */
-    XKP_EUNSUPPORTED = 6   /* valid but not supported by this build (e.g. m > 64)        */
+    XKP_EUNSUPPORTED = 6   /* valid but not supported by this library (e.g. m > 64)      */
 } xkp_status;
 
 typedef enum { XKP_FP64 = 0, XKP_MIXED = 1 } xkp_precision;
