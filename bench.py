@@ -46,6 +46,13 @@ TRAFFIC = {"csrc_digest": "298c3feb44a194ae", "fetch_kib": 35233.5, "write_kib":
            "fetch_scale": 262144.0 / 131086.8, "write_scale": 1.0, "polish_m": 10}
 
 
+# The same for the projected target launch of the headline chain (target Galerkin, polish
+# restart 10, 8 waves, 63 systems), from two more --pmc runs of this file (--legs project).
+TRAFFIC_PROJECTED = {"csrc_digest": TRAFFIC["csrc_digest"], "fetch_kib": 88935.4,
+                     "write_kib": 196923.1, "fetch_scale": 262144.0 / 131085.1,
+                     "write_scale": 1.0, "polish_m": 10}
+
+
 def csrc_digest():
     """Digest of the sources the solve kernel is built from, to tell whether stored counter
     figures still apply."""
@@ -59,12 +66,14 @@ def csrc_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes():
-    """HBM bytes per launch of the roofline kernel, or None if the sources have changed."""
-    if csrc_digest() != TRAFFIC["csrc_digest"]:
+def traffic_bytes(tr=None):
+    """HBM bytes per launch of the roofline kernel (or of the launch `tr` describes), or None
+    if the sources have changed."""
+    tr = TRAFFIC if tr is None else tr
+    if csrc_digest() != tr["csrc_digest"]:
         return None
-    return int(1024 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
-                       + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]))
+    return int(1024 * (tr["fetch_kib"] * tr["fetch_scale"]
+                       + tr["write_kib"] * tr["write_scale"]))
 
 
 def gmres_bytes(n, m, iters, restarts, passes=1):
@@ -83,6 +92,29 @@ def gmres_bytes(n, m, iters, restarts, passes=1):
             total += sum(8 * passes * n * (j + 1) + 8 * n + 24 * n for j in range(k))
             total += 8 * n * k + 48 * n
     return total
+
+
+def projected_bytes_flops(n, polish_m, inf, ntc_max=2):
+    """Algorithmic HBM bytes and FP64 matrix-core flops of the projected target launches
+    (target Galerkin, FP64, x_base = 0), summed over the solves in `inf` (target infos of a
+    chain).  Per target with a kept basis of k columns: A'V_k reads V_k (8 n k) and writes
+    W = [A'V_k | r_base] (8 n (k+1)); the Gram reads V_k once per pass over at most ntc_max
+    16-wide column tiles of W and W once (8 n k passes + 8 n (k+1)); x0 = V_k alpha reads V_k and
+    writes x0 (8 n k + 8 n); then the polish's GMRES bytes (gmres_bytes, one Gram-Schmidt pass).
+    Flops: one 16x16x4 product (2048 flops) per 4 rows for every pair of 16-wide row tiles of
+    V_k and column tiles of W, as executed (tiles padded)."""
+    byts, flops = 0, 0
+    ngroups = (n + 7) // 8
+    for k in np.asarray(inf["basis_dim"], dtype=np.int64).ravel():
+        k = int(k)
+        if k <= 0:
+            continue
+        ktr, ktc = (k + 15) // 16, (k + 16) // 16
+        passes = (ktc + ntc_max - 1) // ntc_max
+        byts += 8 * n * (k + (k + 1) + passes * k + (k + 1) + k + 1)
+        flops += 2048 * 2 * ngroups * ktr * ktc
+    byts += gmres_bytes(n, polish_m, inf["iters"], inf["restarts"], 1)
+    return byts, flops
 
 
 def build_c2():
@@ -577,6 +609,9 @@ def main():
         if name == "plain":
             launch_ms = target_call_ms(ch)
             plain_chain = ch
+        if name == "project":
+            proj_launch_ms = target_call_ms(ch)
+            proj_infos = ch.all_infos()[1]
         print(f"# {name}: {legs[name]['per_chain_s'] * 1e3:.1f} ms/chain, ok={legs[name]['ok']}, "
               f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
               file=sys.stderr, flush=True)
@@ -630,6 +665,20 @@ def main():
                      and pl["polish_m"] == TRAFFIC["polish_m"] else None,
                      "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
     }
+    # the headline chain's own target launch (projection + polish, 63 systems), the same
+    # kernel: HBM roofline of its algorithmic bytes, and its FP64 matrix-core flops
+    pb, pf = projected_bytes_flops(n, legs["project"]["polish_m"], proj_infos)
+    pls = sum(proj_launch_ms) / 1e3 / T
+    pach = pb / T / pls / 1e9
+    out["roofline_projected"] = {
+        "kernel": "solve_kernel (projection + polish, target Galerkin, 63 systems per launch)",
+        "bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(pach / HBM_PEAK_GBS, 4),
+        "traffic": traffic_bytes(TRAFFIC_PROJECTED) if args.reorth == "auto"
+        and legs["project"]["polish_m"] == TRAFFIC_PROJECTED["polish_m"] else None,
+        "bytes_per_launch": int(pb / T), "launch_ms": round(pls * 1e3, 4),
+        "mfma_f64_flops_per_launch": int(pf / T),
+        "mfma_f64_tflops": round(pf / T / pls / 1e12, 3), "mfma_f64_peak_tflops": 78.6}
     del plain_chain
     cg = copy_gbs()
     out["roofline"]["torch_copy_gbs"] = round(cg, 1)
