@@ -9,7 +9,9 @@ this module only marshals numpy arrays.  Each function names the part of the pap
 
 Parity status: every function here is pinned by the non-GPU tests (closed-form eigenpairs, row
 sums, the Cole-Hopf exact solution, brute-force least squares, dense LU, Galerkin orthogonality,
-the Arnoldi relation), except the end-to-end agreement with the paper's own timings, which the
+the Arnoldi relation; the verification residual by the eigenpairs, the explicit matrix and a
+planted residual of known norm; the image-cycle chain by its one-block, repeated-block and
+two-seed reductions), except the end-to-end agreement with the paper's own timings, which the
 paper does not print at this tolerance (parity unpinned there).
 """
 from __future__ import annotations

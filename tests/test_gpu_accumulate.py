@@ -147,5 +147,12 @@ def test_cycle_chain_matches_oracle(X):
         assert np.abs(mt_g[g] - mt_o[g]).max() <= bound, g
     it_g = t_inf["iters"].reshape(T, 9).astype(int)
     assert np.abs(it_g - np.array(st.iters)).max() <= 2
+    # the guess of every target, the one quantity that sees which columns were gathered and in
+    # which order, against the oracle's guess on its own gathered basis
+    g_gpu = t_inf["guess_res"].reshape(T, 9)
+    g_o = np.array(st.guess_res)
+    # (the states they are formed from agree to the chain's tolerance; a wrong source set or
+    # column order moves a guess residual by 1e-1 on these images)
+    assert np.all(np.abs(g_gpu - g_o) <= 1e-6 + 1e-5 * g_o), np.abs(g_gpu - g_o).max()
     # the blocks after the first see the larger gathered bases
     assert np.all(t_inf["basis_dim"].reshape(T, 3, 3)[:, 1:] > a)
