@@ -400,6 +400,31 @@ xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *s
                               void *const *bases, const xkp_params *params, xkp_info *infos,
                               xkp_tuning *out);
 
+/*
+ * Target solve that allocates nothing, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as xkp_target_project_solve with the default 8-wave launch, without a
+ * context.  Its workspace (per-workgroup Krylov basis, coefficient arrays, projection block) and
+ * work-queue counters live in a fixed device array of XKP_NOALLOC_SCRATCH_MIB MiB inside the
+ * library, one per GPU it runs on, held until the process ends; the call itself calls no
+ * allocator.  The array holds as many workgroup slots as fit for the call's size (n at most
+ * params->batch_max_n, or XKP_NOALLOC_MAX_N when 0; restart length the larger of m and
+ * polish_m), so larger systems run on fewer workgroups; a size of which not even one slot fits
+ * returns XKP_EINVAL.  `device` is the GPU (made current by the call), `hip_stream` a stream on
+ * it (NULL: the null stream); the other arguments are those of xkp_target_project_solve, whose
+ * checks apply (with m, polish_m <= 64 and batch_max_n <= XKP_NOALLOC_MAX_N).  Argument errors
+ * return before any device call.  Every call on one GPU uses the same array and leaves its last
+ * contents there (the queue counters are cleared by a small kernel at the start of each call):
+ * calls that overlap in time on one GPU race, so callers serialise them, e.g. on one stream.
+ */
+#define XKP_NOALLOC_SCRATCH_MIB 64
+#define XKP_NOALLOC_MAX_N 16384
+
+xkp_status xkp_target_project_solve_noalloc(int device, void *hip_stream, int32_t n_targets,
+                                            const xkp_system *targets, int32_t n_bases,
+                                            const void *const *bases, const xkp_params *params,
+                                            xkp_info *infos);
+
 /* Static description of a status code. */
 const char *xkp_status_string(xkp_status s);
 

@@ -1,6 +1,7 @@
 // C ABI of libxkp: context, workspace and argument checks around the kernels.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -69,16 +70,24 @@ int npad_for(int nmax) {
     return best;
 }
 
-// Shared host checks of a batched call; fills the effective n limit and kernel variant.
-xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const xkp_params *P,
-                      int *nmax, int *rmax, const Variant **var) {
-    if (!ctx || count < 0 || (count > 0 && !arr) || !P) return XKP_EINVAL;
-    if (P->m < 1 || P->m > ctx->max_m || !(P->tol >= 0.0) || P->max_restarts < 0 ||
-        P->polish_m < 0 || P->polish_m > ctx->max_m || P->batch_max_n < 0 || P->batch_max_n > ctx->max_n ||
+// Host checks of a call's parameters against the restart and size limits of its workspace.
+xkp_status check_params(const xkp_params *P, int max_m, int max_n) {
+    if (!P) return XKP_EINVAL;
+    if (P->m < 1 || P->m > max_m || !(P->tol >= 0.0) || P->max_restarts < 0 ||
+        P->polish_m < 0 || P->polish_m > max_m || P->batch_max_n < 0 || P->batch_max_n > max_n ||
         (P->reorth != XKP_REORTH_AUTO && P->reorth != XKP_REORTH_ALWAYS))
         return XKP_EINVAL;
     if (P->precision != XKP_FP64 && P->precision != XKP_MIXED) return XKP_EINVAL;
     if (P->mode < XKP_PROJ_TARGET_GALERKIN || P->mode > XKP_PROJ_NONE) return XKP_EINVAL;
+    return XKP_OK;
+}
+
+// Shared host checks of a batched call; fills the effective n limit and kernel variant.
+xkp_status check_call(const xkp_ctx *ctx, int32_t count, const void *arr, const xkp_params *P,
+                      int *nmax, int *rmax, const Variant **var) {
+    if (!ctx || count < 0 || (count > 0 && !arr) || !P) return XKP_EINVAL;
+    const xkp_status pst = check_params(P, ctx->max_m, ctx->max_n);
+    if (pst != XKP_OK) return pst;
     *nmax = P->batch_max_n > 0 ? P->batch_max_n : ctx->max_n;
     *var = choose_solve(ctx, *nmax);
     if (!*var) return XKP_EUNSUPPORTED;
@@ -91,6 +100,36 @@ int solve_grid(const xkp_ctx *ctx, int count) {
     int g = ctx->per_cu * ctx->cus;
     if (g > ctx->slots) g = ctx->slots;
     return count < g ? count : g;
+}
+
+// Workspace of the allocation-free target solve: one fixed device array per GPU, held until the
+// process ends.  Bytes [0, 256) hold the work-queue counters, the per-workgroup solve slots
+// follow.  Host code never passes `scratch` itself to a kernel (in host code it names a host-side
+// stand-in); it uses the device address hipGetSymbolAddress returns on each device.
+constexpr size_t kScratchBytes = (size_t)XKP_NOALLOC_SCRATCH_MIB << 20;
+constexpr size_t kScratchHead = 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device, once set up
+
+// The device address of this device's `scratch` (the device must be current).
+xkp_status scratch_on(int device, unsigned char **out) {
+    if (device < 0 || device >= kMaxDevices) return XKP_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return XKP_EDEVICE;
+        g_scratch_ptr[device] = p;
+    }
+    *out = (unsigned char *)g_scratch_ptr[device];
+    return XKP_OK;
+}
+
+// Clears the work-queue counters before a launch (a kernel node, so the call can be captured).
+__global__ void clear_queue_kernel(unsigned *q) {
+    if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
 
 }  // namespace
@@ -549,6 +588,51 @@ xkp_status xkp_cnn_adam(xkp_ctx *ctx, int32_t count, float *params, const float 
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     return from_hip(xkp::cnn::adam(ctx->stream, count, params, grad, m, v, t, lr, beta1, beta2,
                                    eps));
+}
+
+xkp_status xkp_target_project_solve_noalloc(int device, void *hip_stream, int32_t n_targets,
+                                            const xkp_system *targets, int32_t n_bases,
+                                            const void *const *bases, const xkp_params *params,
+                                            xkp_info *infos) {
+    // host checks first: nothing is enqueued and no device call is made for a bad argument
+    constexpr int kMaxN = XKP_NOALLOC_MAX_N;
+    if (n_targets < 0 || (n_targets > 0 && (!targets || !infos))) return XKP_EINVAL;
+    xkp_status st = check_params(params, 64, kMaxN);
+    if (st != XKP_OK) return st;
+    if (params->mode != XKP_PROJ_NONE && n_targets > 0 && (n_bases < 1 || !bases))
+        return XKP_EINVAL;
+    // the 8-wave kernels cover every size up to kMaxN
+    const int nmax = params->batch_max_n > 0 ? params->batch_max_n : kMaxN;
+    const int rmax = xkp::v512::rmax_for(nmax);
+    if (!rmax) return XKP_EUNSUPPORTED;
+    const int mm = params->polish_m > params->m ? params->polish_m : params->m;
+    const xkp::WsLayout L = xkp::ws_layout(nmax, mm, rmax * xkp::v512::threads());
+    const size_t slot_bytes = sizeof(double) * L.stride;
+    const size_t fit = (kScratchBytes - kScratchHead) / slot_bytes;
+    if (fit < 1) return XKP_EINVAL;   // one system of this size does not fit the array
+    if (n_targets == 0) return XKP_OK;
+    if (hipSetDevice(device) != hipSuccess) return XKP_EDEVICE;
+    unsigned char *base = nullptr;
+    st = scratch_on(device, &base);
+    if (st != XKP_OK) return st;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return XKP_EDEVICE;
+    const int per_cu = xkp::v512::solve_per_cu(nmax);
+    if (per_cu < 1) return XKP_EDEVICE;
+    long grid = (long)per_cu * cus;
+    if ((long)fit < grid) grid = (long)fit;
+    if (n_targets < grid) grid = n_targets;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    unsigned *queue = (unsigned *)base;
+    hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(64), 0, stream, queue);
+    if (hipGetLastError() != hipSuccess) return XKP_EDEVICE;
+    const int flags = params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0;
+    return from_hip(xkp::v512::launch_solve(stream, (int)grid, rmax,
+                                            xkp::v512::lds_vec_len(nmax), targets, n_targets,
+                                            *params, flags, n_bases, bases, nullptr, infos,
+                                            (double *)(base + kScratchHead), L, nmax, queue,
+                                            xkp::Learned{nullptr, 0, 0.0, 0.0}));
 }
 
 const char *xkp_status_string(xkp_status s) {

@@ -99,6 +99,8 @@ def load():
                                           P, ct.c_int32, ct.c_double, ct.c_double, P]
         lib.xkp_basis_coeffs.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.c_int32, ct.c_int32,
                                          P]
+        lib.xkp_target_project_solve_noalloc.argtypes = [ct.c_int, P, ct.c_int32, P, ct.c_int32,
+                                                         P, ct.POINTER(Params), P]
         lib.xkp_status_string.argtypes = [ct.c_int]
         lib.xkp_status_string.restype = ct.c_char_p
         for f in ("xkp_ctx_create", "xkp_ctx_destroy", "xkp_seed_build",
@@ -106,7 +108,8 @@ def load():
                   "xkp_autotune", "xkp_autotune_seeds", "xkp_basis_accumulate",
                   "xkp_score_flow", "xkp_cluster_seeds",
                   "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
-                  "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch"):
+                  "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch",
+                  "xkp_target_project_solve_noalloc"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -119,6 +122,18 @@ def status_string(code: int) -> str:
 def _check(code: int, what: str):
     if code != OK:
         raise XkpError(f"{what}: {status_string(code)} ({code})")
+
+
+def target_project_solve_noalloc(systems, n_sys, n_bases, bases_ptrs, params, infos, stream=None,
+                                 device=0):
+    """xkp_target_project_solve without a context: the library's fixed per-GPU workspace, no
+    allocation (calls on one GPU must not overlap)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    _check(load().xkp_target_project_solve_noalloc(device, ct.c_void_p(st.cuda_stream), n_sys,
+                                                   _ptr(systems), n_bases, _ptr(bases_ptrs),
+                                                   ct.byref(params), _ptr(infos)),
+           "xkp_target_project_solve_noalloc")
 
 
 def basis_bytes(n: int, m: int) -> int:

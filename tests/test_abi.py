@@ -87,6 +87,15 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.xkp_basis_accumulate(None, 4096, 2, None, None, 20, 40, None) == xkp.EINVAL
     assert lib.xkp_score_flow(None, 1, None, 0, None, None) == xkp.EINVAL
     assert lib.xkp_cluster_seeds(None, 8, 16, None, 4, 2, 10, None, None, None) == xkp.EINVAL
+    # the allocation-free target solve: argument errors before any device call
+    noalloc = lib.xkp_target_project_solve_noalloc
+    assert noalloc(0, None, 1, None, 0, None, ct.byref(P), None) == xkp.EINVAL
+    assert noalloc(0, None, -1, None, 0, None, ct.byref(P), None) == xkp.EINVAL
+    assert noalloc(0, None, 0, None, 0, None, None, None) == xkp.EINVAL
+    for bad in (xkp.Context.params(65), xkp.Context.params(40, polish_m=65),
+                xkp.Context.params(40, batch_max_n=16385), xkp.Context.params(40, tol=-1.0)):
+        assert noalloc(0, None, 0, None, 0, None, ct.byref(bad), None) == xkp.EINVAL
+    assert noalloc(0, None, 0, None, 0, None, ct.byref(P), None) == xkp.OK
     # the network's sizes and argument checks
     assert lib.xkp_cnn_param_count(40) == 16 * 9 + 16 + 32 * 144 + 32 + 64 * 288 + 64 + 40 * 97
     assert lib.xkp_cnn_param_count(0) == 0 and lib.xkp_cnn_param_count(65) == 0
