@@ -36,21 +36,12 @@ sys.path.insert(0, ROOT)
 METRIC = "target systems solved/sec @ rel-residual 1e-8; projected vs plain GMRES"
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the roofline kernel (solve_kernel, plain leg, polish restart 10, 63 systems per
-# launch), from two rocprofv3 --pmc runs of this file (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch averaged over the 200 target launches).  FETCH_SIZE read 131087 KiB for a 262144 KiB
-# device copy in the same runs (WRITE_SIZE read 262144 KiB): fetch figures are scaled by
-# 262144 / 131087.  Valid only for the kernel sources they were taken with (digest below) and
-# the restart length they were taken at.
-TRAFFIC = {"csrc_digest": "298c3feb44a194ae", "fetch_kib": 35233.5, "write_kib": 95945.5,
-           "fetch_scale": 262144.0 / 131086.8, "write_scale": 1.0, "polish_m": 10}
-
-
-# The same for the projected target launch of the headline chain (target Galerkin, polish
-# restart 10, 8 waves, 63 systems), from two more --pmc runs of this file (--legs project).
-TRAFFIC_PROJECTED = {"csrc_digest": TRAFFIC["csrc_digest"], "fetch_kib": 88935.4,
-                     "write_kib": 196923.1, "fetch_scale": 262144.0 / 131085.1,
-                     "write_scale": 1.0, "polish_m": 10}
+# HBM traffic of target launches (solve_kernel), from two rocprofv3 --pmc runs of this file per
+# launch kind (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch averaged over the chain's target
+# launches), each scaled by what the same counter reads for a plain device copy of known size in
+# the same run (--copy-probe).  A record applies only to the kernel sources it was taken with
+# (digest) and the restart length it was taken at.
+TRAFFIC = {}
 
 
 def csrc_digest():
@@ -66,21 +57,32 @@ def csrc_digest():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(tr=None):
-    """HBM bytes per launch of the roofline kernel (or of the launch `tr` describes), or None
-    if the sources have changed."""
-    tr = TRAFFIC if tr is None else tr
-    if csrc_digest() != tr["csrc_digest"]:
+def traffic_bytes(name, polish_m):
+    """HBM bytes per launch of the launch kind `name` from its stored counter record, or None if
+    there is none, the sources have changed or the restart length differs."""
+    tr = TRAFFIC.get(name)
+    if tr is None or csrc_digest() != tr["csrc_digest"] or tr["polish_m"] != polish_m:
         return None
     return int(1024 * (tr["fetch_kib"] * tr["fetch_scale"]
                        + tr["write_kib"] * tr["write_scale"]))
 
 
-def gmres_bytes(n, m, iters, restarts, passes=1):
-    """Algorithmic HBM bytes of restarted GMRES(m) with `passes` Gram-Schmidt passes, FP64:
-    Arnoldi step j reads v_0..v_j once per pass (8 n (j+1) each), writes v_{j+1} (8 n) and
-    applies the operator (read u and m~, write w: 24 n); each cycle end forms x += V y (8 n k)
-    and the true residual (48 n)."""
+def roofline(kernel, byts, launch_s, traffic=None, **extra):
+    """HBM roofline object of one launch kind: algorithmic bytes per launch over its measured
+    duration against the 8 TB/s peak."""
+    ach = byts / launch_s / 1e9
+    r = {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)}
+    r.update(extra)
+    return r
+
+
+def gmres_bytes(n, m, iters, restarts, passes=1, sv=8, sop=24):
+    """Algorithmic HBM bytes of restarted GMRES(m) with `passes` Gram-Schmidt passes: Arnoldi
+    step j reads v_0..v_j once per pass (sv n (j+1) each, sv = bytes per basis element), writes
+    v_{j+1} (sv n) and applies the operator (read u and m~, write w: sop n); each cycle end forms
+    x += V y (sv n k) and the FP64 true residual (48 n)."""
     iters = np.asarray(iters, dtype=np.int64)
     restarts = np.asarray(restarts, dtype=np.int64)
     total = 0
@@ -89,32 +91,40 @@ def gmres_bytes(n, m, iters, restarts, passes=1):
         for k in cycles:
             if k <= 0:
                 continue
-            total += sum(8 * passes * n * (j + 1) + 8 * n + 24 * n for j in range(k))
-            total += 8 * n * k + 48 * n
+            total += passes * sv * n * k * (k + 1) // 2 + k * (sv * n + sop * n)
+            total += sv * n * k + 48 * n
     return total
 
 
-def projected_bytes_flops(n, polish_m, inf, ntc_max=2):
-    """Algorithmic HBM bytes and FP64 matrix-core flops of the projected target launches
-    (target Galerkin, FP64, x_base = 0), summed over the solves in `inf` (target infos of a
-    chain).  Per target with a kept basis of k columns: A'V_k reads V_k (8 n k) and writes
-    W = [A'V_k | r_base] (8 n (k+1)); the Gram reads V_k once per pass over at most ntc_max
-    16-wide column tiles of W and W once (8 n k passes + 8 n (k+1)); x0 = V_k alpha reads V_k and
-    writes x0 (8 n k + 8 n); then the polish's GMRES bytes (gmres_bytes, one Gram-Schmidt pass).
-    Flops: one 16x16x4 product (2048 flops) per 4 rows for every pair of 16-wide row tiles of
-    V_k and column tiles of W, as executed (tiles padded)."""
-    byts, flops = 0, 0
-    ngroups = (n + 7) // 8
-    for k in np.asarray(inf["basis_dim"], dtype=np.int64).ravel():
-        k = int(k)
-        if k <= 0:
-            continue
-        ktr, ktc = (k + 15) // 16, (k + 16) // 16
-        passes = (ktc + ntc_max - 1) // ntc_max
-        byts += 8 * n * (k + (k + 1) + passes * k + (k + 1) + k + 1)
-        flops += 2048 * 2 * ngroups * ktr * ktc
-    byts += gmres_bytes(n, polish_m, inf["iters"], inf["restarts"], 1)
-    return byts, flops
+def launch_alg_bytes(ns, bids, inf, polish_m, project, warm=False, sv=8, sop=24, sbv=0,
+                     passes=1):
+    """Algorithmic HBM bytes of one target launch, averaged over a chain's launches (inf: target
+    infos [T, N]; ns, bids: unknowns and basis id of each target).  Per target: its GMRES bytes
+    (gmres_bytes); projected targets also read m~' and b' and write x0 (24 n, + 8 n for x_base
+    with a warm start); per launch every seed basis V_k used is read once (8 n k, + sbv n k for
+    its low-precision copy)."""
+    iters, rest, kd = inf["iters"], inf["restarts"], inf["basis_dim"]
+    T, N = iters.shape
+    total = 0
+    for i in range(N):
+        total += gmres_bytes(ns[i], polish_m, iters[:, i], rest[:, i], passes, sv, sop)
+        if project:
+            total += T * (24 + (8 if warm else 0)) * ns[i]
+    if project:
+        for t in range(T):
+            used = {}
+            for i in range(N):
+                used[bids[i]] = (ns[i], int(kd[t, i]))
+            total += sum((8 + sbv) * n * k for n, k in used.values())
+    return total / T
+
+
+def projection_flops(ns, inf):
+    """Algorithmic flops of the target-Galerkin products V_k^T [A'V_k | r_base] per launch,
+    averaged over a chain: 2 n k (k + 1) per target."""
+    kd = np.asarray(inf["basis_dim"], dtype=np.int64)
+    n = np.asarray(ns, dtype=np.int64)[None, :]
+    return float((2 * n * kd * (kd + 1)).sum()) / kd.shape[0]
 
 
 def build_c2():
@@ -146,31 +156,39 @@ def build_c3():
     return cfg, initial_state(seed[0]), np.stack([initial_state(t[0]) for t in tg])
 
 
-def err_vs_fp64(b, tol=1e-12):
-    """Per-target max |x - x64| / max |x64| of the chain's last solutions against the same
-    systems solved again by the FP64 path (plain GMRES to `tol`)."""
-    import torch
-    from paper_2511_17634_amd import xkp
-    par = b.step_no & 1
-    prev = 1 - par
-    bt = torch.empty_like(b.bt)
-    x64 = torch.empty_like(b.bt)
-    d = b._desc(b.tgt_sys, b.mt, bt, prev, x_from=x64)
-    ctx = xkp.Context(b.nmax, b.m, b.N, stream=b.s_main)
-    info = ctx.new_infos(b.N)
-    b.s_main.wait_stream(torch.cuda.current_stream())
-    P = xkp.Context.params(b.m, tol=tol, mode="none", batch_max_n=b.nmax)
-    ctx.build_rhs(d, b.N)
-    ctx.target_project_solve(d, b.N, 0, None, P, info)
-    b.s_main.synchronize()
-    x = b.state()[1]
-    errs = []
-    for H, off, _ in b.tgt_sys:
-        n = H * H
-        ref = x64[off:off + n]
-        errs.append(float((x[off:off + n] - ref).abs().max() / ref.abs().max()))
-    ok = bool((xkp.infos_to_numpy(info)["status"] == 0).all())
-    return np.array(errs), ok
+class OracleRecord:
+    """The FP64 oracle chain (seed chain, then projection + polish chains) of a few sampled
+    targets over all T timesteps, computed in background threads while the GPU legs run; its
+    states [T, picks, n] are the reference of the per-target error of the GPU legs."""
+
+    def __init__(self, H, T, m, s0, t0, picks):
+        from concurrent.futures import ThreadPoolExecutor
+        self.H, self.T, self.m, self.picks = H, T, m, list(picks)
+        self._ex = ThreadPoolExecutor(1)
+        self._fut = self._ex.submit(self._run, np.array(s0), np.array(t0[self.picks]))
+
+    def _run(self, s0, tp):
+        H, T, m = self.H, self.T, self.m
+        bases = oracle_seed_chain(H, T, m, s0, T)
+
+        def one(t):
+            rec = np.empty((T, H * H))
+            oracle_target_chain(H, T, m, t, bases, T, "project",
+                                record=lambda k, x: rec.__setitem__(k, x))
+            return rec
+        return np.stack(_pool(one, list(tp), len(tp)), axis=1)
+
+    def result(self):
+        return self._fut.result()
+
+
+def err_vs_oracle(rec_gpu, rec_o):
+    """Per sampled target: max over timesteps of max|x - x_o| / max|x_o|, and of max|x - x_o|
+    (states after each timestep, GPU against the FP64 oracle chain)."""
+    g = rec_gpu[:, :, :rec_o.shape[2]]
+    num = np.abs(g - rec_o).max(axis=2)
+    den = np.abs(rec_o).max(axis=2)
+    return (num / den).max(axis=0), num.max(axis=0)
 
 
 def uneven_leg(args):
@@ -184,15 +202,24 @@ def uneven_leg(args):
                   reorth=args.reorth)
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.uneven_steps, 1, graph)
+        lm = target_call_ms(b)
+        ns, bids = chain_shape(b)
+        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], method == "project")
         un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
+                    "target_phase_value": round(b.N * cfg4.T / (sum(lm) / 1e3), 2),
                     "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
+                    "verified_solves": r["verified_solves"],
                     "polish_m": r["polish_m"],
                     "wg_per_cu": None if tu is None else tu.wg_per_cu,
                     "waves": None if tu is None else tu.waves,
                     "seed_waves": None if tu is None or b.seed_tuning is None
-                    else b.seed_tuning.waves}
-        print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}",
+                    else b.seed_tuning.waves,
+                    "roofline": roofline(f"solve_kernel ({name}, {b.N} systems of three sizes "
+                                         f"per launch)", byts, np.mean(lm) / 1e3,
+                                         traffic_bytes(f"uneven_{name}", r["polish_m"]))}
+        print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
+              f"launch {np.mean(lm):.3f} ms, frac {un[name]['roofline']['frac']}",
               file=sys.stderr, flush=True)
         del b
     return {"workload": cfg4.name, "targets": sum(g.N * g.C for g in groups),
@@ -200,13 +227,18 @@ def uneven_leg(args):
             "unit": "target systems/s", **un}
 
 
-def mixed_leg(args):
-    """128x128, 1 seed + 255 targets, m = 60, mixed and FP64 precision."""
+def mixed_leg(args, orc=None):
+    """128x128, 1 seed + 255 targets, m = 60, mixed and FP64 precision: throughput, launch
+    rooflines, and each sampled target's error against the FP64 oracle chain at every
+    timestep."""
     from paper_2511_17634_amd import xkp
     from paper_2511_17634_amd.driver import Chain
     graph = not args.eager
     cfg3, s3, t3 = build_c3()
     H3 = cfg3.groups[0].H
+    picks = [0, 127, 254]
+    if orc is None and not args.no_oracle_mixed:
+        orc = OracleRecord(H3, cfg3.T, cfg3.m, s3, t3, picks)
     mx = {}
     for name, method, prec in (("project_mixed", "project", xkp.MIXED),
                                ("project_fp64", "project", xkp.FP64),
@@ -216,40 +248,51 @@ def mixed_leg(args):
                   reorth=args.reorth)
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.mixed_steps, 1, graph)
-        roof = None
-        if name == "plain_fp64":
-            # the same kernel roofline as the 64x64 record, here on the HBM-bound size
-            lm = target_call_ms(b)
-            n3 = H3 * H3
-            passes = 1 if args.reorth == "auto" else 2
-            byts = gmres_bytes(n3, r["polish_m"], r["iters"], r["restarts"], passes) / cfg3.T
-            ls = sum(lm) / 1e3 / cfg3.T
-            roof = {"kernel": f"solve_kernel (plain GMRES, {len(t3)} systems per launch)",
-                    "bound": "hbm", "achieved": round(byts / ls / 1e9, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(byts / ls / 1e9 / HBM_PEAK_GBS, 4),
-                    "bytes_per_launch": int(byts), "launch_ms": round(ls * 1e3, 4)}
-        e, eok = err_vs_fp64(b)
+        lm = target_call_ms(b)
+        ns, bids = chain_shape(b)
+        mixed = prec == xkp.MIXED
+        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], method == "project",
+                                sv=4 if mixed else 8, sop=12 if mixed else 24,
+                                sbv=2 if mixed else 0)
+        rec = b.record_chain(picks).cpu().numpy() if orc is not None else None
         mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
-                    "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"] and eok,
+                    "target_phase_value": round(b.N * cfg3.T / (sum(lm) / 1e3), 2),
+                    "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
+                    "verified_solves": r["verified_solves"],
                     "polish_m": r["polish_m"],
                     "waves": None if tu is None else tu.waves,
                     "seed_waves": None if tu is None or b.seed_tuning is None
                     else b.seed_tuning.waves,
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
-                    "err_vs_fp64_max": float(f"{e.max():.3e}"),
-                    "err_vs_fp64_median": float(f"{np.median(e):.3e}")}
-        if roof is not None:
-            mx[name]["roofline"] = roof
+                    "roofline": roofline(f"solve_kernel ({name}, {b.N} systems per launch)",
+                                         byts, np.mean(lm) / 1e3,
+                                         traffic_bytes(f"c3_{name}", r["polish_m"]))}
+        if method == "project":
+            fl = projection_flops(ns, r["infos"])
+            mx[name]["roofline"]["projection_flops_per_launch"] = int(fl)
+        if rec is not None:
+            mx[name]["_rec"] = rec
         print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
-              f"mean iters {r['iters_mean']:.1f}, max err vs fp64 {e.max():.2e}",
-              file=sys.stderr, flush=True)
+              f"mean iters {r['iters_mean']:.1f}, launch {np.mean(lm):.3f} ms, "
+              f"frac {mx[name]['roofline']['frac']}", file=sys.stderr, flush=True)
         del b
+    if orc is not None:
+        ro = orc.result()
+        # each step's solution is within dt ||r||_inf <= tol ||m^{n-1}||_2 of the exact one
+        # (Varah), and the step map does not amplify differences in the max norm
+        bound = cfg3.T * args.tol * max(np.linalg.norm(s3), np.linalg.norm(t3, axis=1).max())
+        for name, v in mx.items():
+            e, ea = err_vs_oracle(v.pop("_rec"), ro)
+            v["err_vs_oracle"] = [float(f"{x:.3e}") for x in e]
+            v["verified"] = v["verified"] and bool((ea <= bound).all())
     return {"workload": cfg3.name, "targets": len(t3), "seeds": 1,
             "timesteps": cfg3.T, "m": cfg3.m, "unit": "target systems/s",
-            "err_note": "per-target max |x - x_fp64| / max |x_fp64| at the last timestep, "
-                        "x_fp64 = the same systems re-solved by the FP64 path to 1e-12", **mx}
+            "err_note": f"targets {picks}: max over the {cfg3.T} timesteps of "
+                        "max|x - x_oracle| / max|x_oracle|, x_oracle = the FP64 CPU oracle's "
+                        "own chain (seed chain, target-Galerkin projection, GMRES(m) polish); "
+                        "both solve every step to 1e-8, so they agree to about T x 1e-8",
+            **mx}
 
 
 def learned_leg(args):
@@ -283,6 +326,7 @@ def learned_leg(args):
     legs, polish_m = {}, 0
     for name, kw in (("project", dict(method="project")), ("plain", dict(method="plain")),
                      ("learned_gate_1e-6", dict(method="learned", gate=1e-6)),
+                     ("learned_gate_1e-4", dict(method="learned", gate=1e-4)),
                      ("learned_gate_1e-2", dict(method="learned", gate=1e-2)),
                      ("learned_gate_inf", dict(method="learned", gate=1e300))):
         if kw["method"] == "learned":
@@ -471,9 +515,12 @@ def epilogue_leg(args):
                          "bytes_per_launch": byts}}
 
 
-def time_chain(b, args, steps, warmup, graph=True):
+def time_chain(b, args, steps, warmup, graph=True, verify_all=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
-    captured graph (or enqueued eagerly), then verify every solve of the last chain."""
+    captured graph (or enqueued eagerly); then verify every solve: the kernels' own statuses and
+    FP64 true residuals of the last timed chain, and (verify_all) one more eager chain in which
+    every target solution of every timestep is re-checked through xkp_residual, whose operator
+    is rebuilt from m~ independently of the solve kernel's coefficient arrays."""
     import torch
     for _ in range(warmup):
         b.run()
@@ -492,16 +539,22 @@ def time_chain(b, args, steps, warmup, graph=True):
     ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
     if b.with_seeds:
         ok = ok and bool((seed_inf["status"] == 0).all())
-    # independent FP64 check of the last timestep through the residual entry point
-    rel = b.verify_last()
+    if verify_all and b.K == 1:
+        rel = b.verify_chain()
+        _, tgt2 = b.all_infos()
+        # the eager chain repeats the replayed one: same iteration counts
+        ok = ok and bool(np.array_equal(tgt2["iters"], tgt_inf["iters"]))
+    else:
+        rel = b.verify_last()[None]
     ok = ok and bool((rel <= args.tol * (1 + 1e-6)).all())
     return {
         "elapsed": elapsed, "ok": ok, "per_chain_s": elapsed / steps,
         "iters_mean": float(tgt_inf["iters"].mean()),
-        "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"],
+        "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"], "infos": tgt_inf,
         "seed_iters_total": int(seed_inf["iters"].sum()) if b.with_seeds else 0,
         "guess_res_mean": float(np.mean(tgt_inf["guess_res"])),
         "max_res": float(max(tgt_inf["res_true"].max(), rel.max())),
+        "verified_solves": int(rel.size),
         "N": b.N, "polish_m": int(b.params.polish_m) or b.m,
     }
 
@@ -519,18 +572,135 @@ def target_call_ms(b):
     return [a.elapsed_time(e) for a, e in ev]
 
 
-def cpu_baseline(H, T, m, s0, t0, n_targets, steps, reorth="auto"):
-    """The oracle (single-threaded C, FP64) on a bounded sample of the same chain."""
-    from oracle.chain import run_chain
-    t = time.perf_counter()
-    _, _, st = run_chain(s0, t0[:n_targets], H, T, m, method="project", steps=steps,
-                         reorth=reorth)
-    el = time.perf_counter() - t
-    return {"value": n_targets * steps / el, "unit": "target systems/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_targets} of 63 targets x {steps} of {T} timesteps of the same "
-                      f"64x64 chain (seed chain included), target-Galerkin projection + "
-                      f"GMRES({m}) polish, {el:.1f} s"}
+def chain_shape(b):
+    """(unknowns, basis id) of every target of a driver Batch."""
+    return [H * H for H, _, _ in b.tgt_sys], [bid for _, _, bid in b.tgt_sys]
+
+
+def per_step_log(inf, digits=4):
+    """Mean guess residual and mean iterations of every timestep (rows of infos [T, N])."""
+    return {"guess_res_mean": [float(f"{v:.{digits}g}") for v in inf["guess_res"].mean(axis=1)],
+            "iters_mean": [round(float(v), 2) for v in inf["iters"].mean(axis=1)]}
+
+
+def _pool(fn, items, workers):
+    """map fn over items with `workers` threads (the oracle's C calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    if workers <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, items))
+
+
+def oracle_seed_chain(H, T, m, s0, steps, g=0.5, tol=1e-8):
+    """The seed chain on the oracle (Section 3, Phase 1): per timestep the seed's GMRES(m) solve
+    from 0 and its kept first-cycle basis; returns [(V, Hbar)] per step."""
+    import oracle
+    dt, ms, out = 1.0 / T, np.array(s0, dtype=np.float64), []
+    for _ in range(steps):
+        A = oracle.Operator(H, dt, g, ms)
+        r = oracle.gmres(A, oracle.rhs(A, ms), m=m, tol=tol, keep_basis=True)
+        out.append((r.V, r.Hbar))
+        ms = r.x
+    return out
+
+
+def oracle_target_chain(H, T, m, t0, bases, steps, method, g=0.5, tol=1e-8, record=None):
+    """One target through `steps` timesteps on the oracle: target-Galerkin projection on the
+    step's seed basis then GMRES(m) polish (one Gram-Schmidt pass), or plain GMRES(m) from 0.
+    Returns (final state, polish iterations per step); record(step, x) sees every solution."""
+    import oracle
+    dt, mt, its = 1.0 / T, np.array(t0, dtype=np.float64), []
+    for n in range(steps):
+        A = oracle.Operator(H, dt, g, mt)
+        b = oracle.rhs(A, mt)
+        x0 = None
+        if method == "project":
+            V, Hb = bases[n]
+            x0, _, _ = oracle.project(A, b, V, Hb)
+        r = oracle.gmres(A, b, x0=x0, m=m, tol=tol, passes=1)
+        its.append(r.iters)
+        mt = r.x
+        if record is not None:
+            record(n, mt)
+    return mt, its
+
+
+def scipy_matrix(A):
+    """The five-point matrix of an oracle operator as a scipy CSR matrix (coefficients from the
+    oracle; the paper's Python direct-solver baseline factorises such a matrix)."""
+    import scipy.sparse as sp
+    import oracle
+    cd, ce, cw, cn, cs = oracle.coeffs(A)
+    n, H = A.n, A.H
+    j = np.arange(n) % H
+    cn = np.where(j + 1 < H, cn, 0.0)[:n - 1]
+    cs = np.where(j >= 1, cs, 0.0)[1:]
+    return sp.diags([cd, ce[:n - H], cw[H:], cn, cs], [0, H, -H, 1, -1], format="csc")
+
+
+def cpu_baseline(H, T, m, s0, t0, one_core_targets, steps):
+    """The oracle (plain C, FP64) timed on this host's cores on bounded samples of the 64x64
+    chain: the projection chain (seed chain, then every target's chain; targets in a thread pool
+    over all cores, and on one core for a subset), and per-system times of the banded LU (the
+    direct-solver analogue of the paper's SpSolve), plain GMRES(m), projection + polish, and
+    scipy's sparse direct solve single-threaded."""
+    import oracle
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(ncores, 16))
+    tic = time.perf_counter()
+    bases = oracle_seed_chain(H, T, m, s0, steps)
+    t_seed = time.perf_counter() - tic
+    tic = time.perf_counter()
+    _pool(lambda t: oracle_target_chain(H, T, m, t, bases, steps, "project"), list(t0), workers)
+    t_all = time.perf_counter() - tic
+    sub = t0[:one_core_targets]
+    tic = time.perf_counter()
+    for t in sub:
+        oracle_target_chain(H, T, m, t, bases, steps, "project")
+    t_one = time.perf_counter() - tic
+    # per-system times at timestep 1, one thread
+    dt, per = 1.0 / T, {}
+    systems = []
+    for t in t0[:16]:
+        A = oracle.Operator(H, dt, 0.5, t)
+        systems.append((A, oracle.rhs(A, t)))
+
+    def timed(fn):
+        tic = time.perf_counter()
+        for A, b in systems:
+            fn(A, b)
+        return (time.perf_counter() - tic) / len(systems) * 1e3
+    per["banded_lu_ms"] = timed(lambda A, b: oracle.banded_solve(A, b))
+    per["plain_gmres_ms"] = timed(lambda A, b: oracle.gmres(A, b, m=m, passes=1))
+    V0, H0 = bases[0]
+    per["projection_polish_ms"] = timed(
+        lambda A, b: oracle.gmres(A, b, x0=oracle.project(A, b, V0, H0)[0], m=m, passes=1))
+    try:
+        import scipy.sparse.linalg as spl
+        mats = [(scipy_matrix(A), b) for A, b in systems[:8]]
+        tic = time.perf_counter()
+        for M, b in mats:
+            spl.spsolve(M, b)
+        per["scipy_spsolve_ms"] = (time.perf_counter() - tic) / len(mats) * 1e3
+    except ImportError:
+        per["scipy_spsolve_ms"] = None
+    N = len(t0)
+    value = N * steps / (t_seed + t_all)
+    return {"value": round(value, 2), "unit": "target systems/s", "cores": workers,
+            "kind": "oracle", "nproc": ncores,
+            "sample": f"all {N} targets x {steps} of {T} timesteps of the 64x64 chain: the seed "
+                      f"chain ({t_seed:.1f} s, one core), then the targets' projection + "
+                      f"GMRES({m}) chains in {workers} threads ({t_all:.1f} s)",
+            "one_core": {"value": round(len(sub) * steps / (t_seed + t_one), 2),
+                         "sample": f"{len(sub)} targets x {steps} timesteps, seed chain "
+                                   f"included, {t_seed + t_one:.1f} s"},
+            "per_system_ms_one_core": {k: (None if v is None else round(v, 3))
+                                       for k, v in per.items()},
+            "per_system_note": "timestep 1 of 16 targets (8 for scipy), 64x64, one thread: "
+                               "banded LU with partial pivoting (the paper's SpSolve analogue), "
+                               "GMRES(m) from 0, target-Galerkin projection + GMRES(m), "
+                               "scipy.sparse.linalg.spsolve (SuperLU)"}
 
 
 def main():
@@ -556,13 +726,16 @@ def main():
                                        "picard", "cluster"),
                     help="run one of the other workloads alone and print its record (profiling)")
     ap.add_argument("--mixed-steps", type=int, default=1)
-    ap.add_argument("--legs", default="project,project_seed_galerkin,plain",
+    ap.add_argument("--no-oracle-mixed", action="store_true",
+                    help="skip the 128x128 oracle chain (per-target error of the mixed legs)")
+    ap.add_argument("--legs", default="project,project_seed_galerkin,plain,project_warm,plain_warm",
                     help="comma list of the 64x64 legs to run (profiling runs take one)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--reorth", choices=("auto", "always"), default="auto",
                     help="Gram-Schmidt passes: two only while a seed basis is kept, or always")
-    ap.add_argument("--cpu-targets", type=int, default=20)
+    ap.add_argument("--cpu-targets", type=int, default=6,
+                    help="targets of the one-core oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -584,6 +757,11 @@ def main():
     H, T, m = cfg.groups[0].H, cfg.T, cfg.m
     n = H * H
     graph = not args.eager
+    # the FP64 oracle of the 128x128 workload's sampled targets runs on the host meanwhile
+    orc = None
+    if not args.no_mixed and not args.no_oracle_mixed:
+        cfg3, s3, t3 = build_c3()
+        orc = OracleRecord(cfg3.groups[0].H, cfg3.T, cfg3.m, s3, t3, [0, 127, 254])
 
     if args.copy_probe:
         import torch
@@ -595,26 +773,25 @@ def main():
         print(f"# copy probe: 3 copies of {args.copy_probe} MiB", file=sys.stderr, flush=True)
         del src, dst
     wanted = args.legs.split(",")
-    legs, tunings = {}, {}
-    for name, method, mode in (("project", "project", "target_galerkin"),
-                               ("project_seed_galerkin", "project", "seed_galerkin"),
-                               ("plain", "plain", "none")):
+    legs, tunings, launch = {}, {}, {}
+    for name, method, mode, warm in (("project", "project", "target_galerkin", False),
+                                     ("project_seed_galerkin", "project", "seed_galerkin", False),
+                                     ("plain", "plain", "none", False),
+                                     ("project_warm", "project", "target_galerkin", True),
+                                     ("plain_warm", "plain", "none", True)):
         if name not in wanted:
             continue
         ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m,
-                   reorth=args.reorth)
+                   reorth=args.reorth, warm=warm)
         if not args.no_tune and not args.polish_m:
             tunings[name] = (ch.autotune(), ch.seed_tuning)
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
-        if name == "plain":
-            launch_ms = target_call_ms(ch)
-            plain_chain = ch
-        if name == "project":
-            proj_launch_ms = target_call_ms(ch)
-            proj_infos = ch.all_infos()[1]
+        if name in ("project", "plain", "project_warm", "plain_warm"):
+            launch[name] = target_call_ms(ch)
         print(f"# {name}: {legs[name]['per_chain_s'] * 1e3:.1f} ms/chain, ok={legs[name]['ok']}, "
               f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
               file=sys.stderr, flush=True)
+        del ch
 
     if "project" not in legs or "plain" not in legs:
         # a partial run (profiling): one line per leg, not the benchmark record
@@ -623,15 +800,37 @@ def main():
                               "verified": v["ok"], "mean_iters": round(v["iters_mean"], 2)}))
         return
     N = legs["project"]["N"]
+    ns, bids = [n] * N, [0] * N
     per_step = {k: v["per_chain_s"] for k, v in legs.items()}
     value = N * T / per_step["project"]
-    # roofline of the dominant kernel: the batched solve kernel in the plain leg (GMRES only),
-    # one launch per timestep, timed by HIP events on its stream
-    pl = legs["plain"]
-    passes = 1 if args.reorth == "auto" else 2
-    byts = gmres_bytes(n, pl["polish_m"], pl["iters"], pl["restarts"], passes) / T  # per launch
-    launch_s = sum(launch_ms) / 1e3 / T
-    achieved = byts / launch_s / 1e9
+
+    def leg_roof(name, project, warm=False):
+        r = legs[name]
+        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], project, warm=warm)
+        ls = np.mean(launch[name]) / 1e3
+        ro = roofline(f"solve_kernel ({'projection + polish' if project else 'plain GMRES'}, "
+                      f"{N} systems per launch)", byts, ls,
+                      traffic_bytes(f"c2_{name}", r["polish_m"]) if args.reorth == "auto"
+                      else None)
+        if project:
+            fl = projection_flops(ns, r["infos"])
+            ro["projection_flops_per_launch"] = int(fl)
+            ro["projection_tflops"] = round(fl / ls / 1e12, 3)
+            ro["fp64_matrix_peak_tflops"] = 78.6
+        return ro
+
+    def summary(name):
+        r = legs[name]
+        d = {"value": round(N * T / per_step[name], 2),
+             "ms_per_step": round(per_step[name] * 1e3, 3),
+             "mean_iters": round(r["iters_mean"], 2), "polish_m": r["polish_m"],
+             "mean_guess_residual": round(r["guess_res_mean"], 4),
+             "verified": r["ok"], "verified_solves": r["verified_solves"]}
+        if name in launch:
+            d["target_phase_value"] = round(N * T / (sum(launch[name]) / 1e3), 2)
+            d["target_launch_ms"] = round(float(np.mean(launch[name])), 4)
+        return d
+
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "target systems/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -643,43 +842,29 @@ def main():
                    "polish_m": legs["project"]["polish_m"], "graph": graph,
                    "reorth": args.reorth},
         "verified": all(v["ok"] for v in legs.values()),
-        "plain_gmres": {"value": round(N * T / per_step["plain"], 2),
-                        "ms_per_step": round(per_step["plain"] * 1e3, 3),
-                        "mean_iters": round(pl["iters_mean"], 2), "restart": pl["polish_m"]},
-        "seed_galerkin": None if "project_seed_galerkin" not in legs else {
-            "value": round(N * T / per_step["project_seed_galerkin"], 2),
-            "ms_per_step": round(per_step["project_seed_galerkin"] * 1e3, 3),
-            "mean_iters": round(legs["project_seed_galerkin"]["iters_mean"], 2),
-            "polish_m": legs["project_seed_galerkin"]["polish_m"]},
-        "projection": {"mean_polish_iters": round(legs["project"]["iters_mean"], 2),
-                       "mean_guess_residual": round(legs["project"]["guess_res_mean"], 4),
-                       "seed_iters_per_chain": legs["project"]["seed_iters_total"]},
+        "project": summary("project"),
+        "plain_gmres": summary("plain"),
         "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu, "waves": t.waves,
                          "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4),
                          "seed_waves": None if ts is None else ts.waves}
                      for k, (t, ts) in tunings.items()},
-        "roofline": {"kernel": "solve_kernel (plain GMRES leg, 63 systems per launch)",
-                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_bytes() if args.reorth == "auto"
-                     and pl["polish_m"] == TRAFFIC["polish_m"] else None,
-                     "bytes_per_launch": int(byts), "launch_ms": round(launch_s * 1e3, 4)},
+        # the headline chain's own target launch: projection + polish of the 63 targets
+        "roofline": leg_roof("project", True),
+        "roofline_plain": leg_roof("plain", False),
+        "per_timestep": {"project": per_step_log(legs["project"]["infos"]),
+                         "plain_iters_mean": per_step_log(legs["plain"]["infos"])["iters_mean"]},
     }
-    # the headline chain's own target launch (projection + polish, 63 systems), the same
-    # kernel: HBM roofline of its algorithmic bytes, and its FP64 matrix-core flops
-    pb, pf = projected_bytes_flops(n, legs["project"]["polish_m"], proj_infos)
-    pls = sum(proj_launch_ms) / 1e3 / T
-    pach = pb / T / pls / 1e9
-    out["roofline_projected"] = {
-        "kernel": "solve_kernel (projection + polish, target Galerkin, 63 systems per launch)",
-        "bound": "hbm", "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(pach / HBM_PEAK_GBS, 4),
-        "traffic": traffic_bytes(TRAFFIC_PROJECTED) if args.reorth == "auto"
-        and legs["project"]["polish_m"] == TRAFFIC_PROJECTED["polish_m"] else None,
-        "bytes_per_launch": int(pb / T), "launch_ms": round(pls * 1e3, 4),
-        "mfma_f64_flops_per_launch": int(pf / T),
-        "mfma_f64_tflops": round(pf / T / pls / 1e12, 3), "mfma_f64_peak_tflops": 78.6}
-    del plain_chain
+    out["project"]["seed_iters_per_chain"] = legs["project"]["seed_iters_total"]
+    if "project_seed_galerkin" in legs:
+        out["seed_galerkin"] = summary("project_seed_galerkin")
+    if "project_warm" in legs and "plain_warm" in legs:
+        out["warm_start"] = {"note": "x_base = m^{n-1} for targets and seed start m^{n-1}",
+                             "project": summary("project_warm"),
+                             "plain_gmres": summary("plain_warm"),
+                             "roofline": leg_roof("project_warm", True, True)}
+        out["per_timestep"]["project_warm"] = per_step_log(legs["project_warm"]["infos"])
+        out["per_timestep"]["plain_warm_iters_mean"] = \
+            per_step_log(legs["plain_warm"]["infos"])["iters_mean"]
     cg = copy_gbs()
     out["roofline"]["torch_copy_gbs"] = round(cg, 1)
     if not args.no_uneven:
@@ -687,10 +872,7 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for k, v in out["uneven"].items() if k in ("project", "plain"))
     if not args.no_mixed:
-        out["mixed"] = mixed_leg(args)
-        r128 = out["mixed"].get("plain_fp64", {}).get("roofline")
-        if r128:
-            r128["torch_copy_gbs"] = round(cg, 1)
+        out["mixed"] = mixed_leg(args, orc)
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["mixed"].values() if isinstance(v, dict))
     if not args.no_learned:
@@ -712,8 +894,7 @@ def main():
         out["verified"] = out["verified"] and all(
             v["verified"] for v in out["cycle"]["legs"].values())
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps,
-                                           args.reorth)
+        out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

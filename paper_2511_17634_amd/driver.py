@@ -395,6 +395,51 @@ class Batch:
         return (ms[so:so + gr.C * gr.n].view(gr.C, gr.n),
                 mt[to:to + gr.N * gr.C * gr.n].view(gr.N, gr.C, gr.n))
 
+    def verify_chain(self):
+        """One eager chain in which every target solve is checked as soon as it is enqueued:
+        the FP64 relative residual of each target's solution with the operator and right-hand
+        side rebuilt from that step's m^{n-1} through the library (xkp_build_rhs into a scratch
+        buffer, xkp_residual, whose operator is formed from m~ on the fly).  Returns rel [T, N].
+        One linearisation pass per step."""
+        import torch
+        assert self.K == 1
+        bt = torch.empty_like(self.bt)
+        dv = [self._desc(self.tgt_sys, self.mt, bt, par) for par in (0, 1)]
+        rel = torch.empty((self.T, self.N), dtype=torch.float64, device=self.dev)
+
+        def hook(par, bases):
+            t = self.step_no % self.T
+            self.ctx.build_rhs(dv[par], self.N)
+            self.ctx.residual(dv[par], self.N, rel[t])
+        self.s_main.wait_stream(torch.cuda.current_stream(self.dev))
+        self.reset()
+        for _ in range(self.T):
+            self.step(after_targets=hook)
+        self._join()
+        return rel.cpu().numpy()
+
+    def record_chain(self, picks):
+        """One eager chain that copies the solutions of targets `picks` after every timestep:
+        returns a [T, len(picks), nmax] float64 tensor (row t = m^{t+1}; a target of a smaller
+        grid fills the first n entries).  One linearisation pass per step."""
+        import torch
+        assert self.K == 1
+        rec = torch.zeros((self.T, len(picks), self.nmax), dtype=torch.float64, device=self.dev)
+
+        def hook(par, bases):
+            t = self.step_no % self.T
+            with torch.cuda.stream(self.s_main):
+                for j, i in enumerate(picks):
+                    H, off, _ = self.tgt_sys[i]
+                    rec[t, j, :H * H].copy_(self.mt[1 - par][off:off + H * H])
+        self.s_main.wait_stream(torch.cuda.current_stream(self.dev))
+        self.reset()
+        for _ in range(self.T):
+            self.step(after_targets=hook)
+        self._join()
+        torch.cuda.synchronize(self.dev)
+        return rec
+
     def verify_last(self):
         """FP64 relative residual of every target's last solution (operator and right-hand side
         of the last timestep rebuilt through the library)."""

@@ -1,7 +1,8 @@
 """The benchmark's algorithmic byte and flop models (bench.py), against hand counts: GMRES
-bytes per Arnoldi step and cycle end, with restarts and two Gram-Schmidt passes; the projected
-launch's bytes and FP64 matrix-core products at kept basis dimensions of one and two passes over
-the column tiles; the counter figures apply only to the sources they were taken with."""
+bytes per Arnoldi step and cycle end, with restarts, two Gram-Schmidt passes and FP32 element
+sizes; a target launch's bytes (per-target inputs and outputs, the seed basis once per launch)
+and the projection's flops; the scipy matrix of the CPU baseline is the oracle's operator; the
+counter figures apply only to the sources they were taken with."""
 import os
 import sys
 
@@ -38,22 +39,58 @@ def test_gmres_bytes_restarts_and_passes():
     assert bench.gmres_bytes(n, m, [m], [1]) == bench.gmres_bytes(n, m, [m], [0])
 
 
-def test_projected_bytes_flops_by_hand():
+def test_launch_bytes_and_flops_by_hand():
     n, pm = 4096, 10
-    inf = {"basis_dim": np.array([[30, 40, 0]]), "iters": np.array([[12, 10, 7]]),
-           "restarts": np.array([[1, 0, 0]])}
-    b, f = bench.projected_bytes_flops(n, pm, inf)
-    # k = 30: 2 row tiles, 2 column tiles of [A'V | r] (31 columns), one pass over them;
-    # k = 40: 3 and 3 tiles, two passes (at most two column tiles each); k = 0: no projection
-    proj = 8 * n * (30 + 31 + 1 * 30 + 31 + 30 + 1) + 8 * n * (40 + 41 + 2 * 40 + 41 + 40 + 1)
-    assert b == proj + bench.gmres_bytes(n, pm, inf["iters"], inf["restarts"], 1)
-    # one 16x16x4 product (2048 flops) per 4 rows and tile pair
-    assert f == 2048 * (n // 4) * (2 * 2 + 3 * 3)
+    inf = {"basis_dim": np.array([[30, 30, 30], [25, 25, 25]]),
+           "iters": np.array([[12, 10, 7], [9, 9, 11]]),
+           "restarts": np.array([[1, 0, 0], [0, 0, 1]])}
+    ns, bids = [n] * 3, [0] * 3
+    b = bench.launch_alg_bytes(ns, bids, inf, pm, project=True)
+    # per launch: each target's GMRES bytes, m~ and b read and x0 written (24 n), the seed
+    # basis V_k read once (8 n k); averaged over the two launches
+    want = sum(bench.gmres_bytes(n, pm, [inf["iters"][t, i]], [inf["restarts"][t, i]])
+               for t in range(2) for i in range(3))
+    want += 2 * 3 * 24 * n + 8 * n * 30 + 8 * n * 25
+    assert b == want / 2
+    # plain GMRES: the GMRES bytes only; a warm start also reads x_base (8 n)
+    assert bench.launch_alg_bytes(ns, bids, inf, pm, project=False) == \
+        sum(bench.gmres_bytes(n, pm, inf["iters"][:, i], inf["restarts"][:, i])
+            for i in range(3)) / 2
+    assert bench.launch_alg_bytes(ns, bids, inf, pm, project=True, warm=True) == \
+        want / 2 + 3 * 8 * n
+    # two bases (uneven sizes) are each read once per launch
+    b2 = bench.launch_alg_bytes([n, n, 1024], [0, 0, 1], inf, pm, project=True)
+    assert b2 < b
+    # V_k^T [A'V_k | r]: 2 n k (k + 1) flops per target
+    assert bench.projection_flops(ns, inf) == (3 * 2 * n * 30 * 31 + 3 * 2 * n * 25 * 26) / 2
+
+
+def test_mixed_gmres_bytes_use_element_sizes():
+    n, m = 1000, 8
+    # FP32 basis (4 bytes) and FP32 operator (12 n): the basis part halves, the cycle end keeps
+    # its FP64 residual
+    k = 5
+    want = sum(4 * n * (j + 1) + 4 * n + 12 * n for j in range(k)) + 4 * n * k + 48 * n
+    assert bench.gmres_bytes(n, m, [k], [0], sv=4, sop=12) == want
+
+
+def test_scipy_matrix_is_the_operator(olib):
+    import oracle
+    rng = np.random.default_rng(3)
+    for H in (3, 8, 13):
+        A = oracle.Operator(H, 0.01, 0.5, rng.uniform(0, 1, H * H))
+        u = rng.normal(size=H * H)
+        M = bench.scipy_matrix(A)
+        assert np.abs(M @ u - oracle.apply(A, u)).max() <= 1e-12 * np.abs(oracle.apply(A, u)).max()
 
 
 def test_traffic_only_for_the_sources_it_was_taken_with(monkeypatch):
-    assert bench.traffic_bytes() is not None or bench.csrc_digest() != bench.TRAFFIC["csrc_digest"]
-    monkeypatch.setitem(bench.TRAFFIC, "csrc_digest", "0" * 16)
-    assert bench.traffic_bytes() is None
-    tp = dict(bench.TRAFFIC_PROJECTED, csrc_digest="0" * 16)
-    assert bench.traffic_bytes(tp) is None
+    monkeypatch.setitem(bench.TRAFFIC, "probe", {"csrc_digest": bench.csrc_digest(),
+                                                 "fetch_kib": 1.0, "write_kib": 2.0,
+                                                 "fetch_scale": 2.0, "write_scale": 1.0,
+                                                 "polish_m": 10})
+    assert bench.traffic_bytes("probe", 10) == 1024 * 4
+    assert bench.traffic_bytes("probe", 20) is None
+    assert bench.traffic_bytes("missing", 10) is None
+    monkeypatch.setitem(bench.TRAFFIC["probe"], "csrc_digest", "0" * 16)
+    assert bench.traffic_bytes("probe", 10) is None
