@@ -84,6 +84,11 @@ typedef enum {
  * rounding, with one workgroup reduction per Arnoldi step instead of one per basis column;
  * larger calls use two modified Gram-Schmidt passes.
  */
+/* Discarded cycles whose basis fits the registers of a workgroup (grids of at most 4096
+ * unknowns: up to 6 steps per cycle at 64x64 with 8-wave workgroups, 9 with 4-wave ones; up to 8
+ * / 15 at 32x32) keep it there and orthogonalise by two classical Gram-Schmidt passes, each one
+ * workgroup reduction for all the step's inner products (CGS2, an orthonormal basis to working
+ * precision like two modified passes); longer cycles use the single modified pass above. */
 typedef enum {
     XKP_REORTH_AUTO = 0,   /* two passes while a basis is kept, one pass elsewhere          */
     XKP_REORTH_ALWAYS = 1  /* two passes in every Arnoldi step                              */
@@ -373,7 +378,8 @@ typedef struct {
 /*
  * Launch autotuner for target calls: times xkp_target_project_solve on the given batch (one
  * representative timestep) for each kernel variant covering the batch (workgroups of 8, 16 or 4
- * wave64s), each candidate restart length of the polish (m/4, m/2, 3m/4 and m, at least 8) and each
+ * wave64s), each candidate restart length of the polish (6, 8, 9, then m/4 (at least 8), m/2, 3m/4
+ * and m, at most m; the short ones let the cycle's basis stay in registers) and each
  * workgroup count per compute unit the kernels can hold (1..occupancy), two timed calls each
  * after one untimed call, and keeps the fastest candidate whose every target converged.  The
  * chosen variant and workgroup count are stored in the context and apply to its later seed and

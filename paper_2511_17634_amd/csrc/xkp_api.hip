@@ -1,6 +1,7 @@
 // C ABI of libxkp: context, workspace and argument checks around the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -244,7 +245,7 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
     if (n_targets == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int grid = solve_grid(ctx, n_targets);
-    const int flags = params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0;
+    const int flags = (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0) | xkp::kRegBasis;
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
                              *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
                              nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}));
@@ -264,7 +265,8 @@ xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *
     if (n_targets == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int grid = solve_grid(ctx, n_targets);
-    const int flags = xkp::kLearned | (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0);
+    const int flags = xkp::kLearned | (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0) |
+                      xkp::kRegBasis;
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
                              *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
                              nmax, ctx->queue, xkp::Learned{alpha, alpha_ld, alpha_scale, gate}));
@@ -513,12 +515,12 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int m = params->m;
     const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
-    int cand_m[4] = {m / 4, m / 2, (3 * m) / 4, m};
-    for (int &c : cand_m) {
-        if (c < 8) c = 8;
+    // short restarts whose basis fits the registers (6, 8, 9), then fractions of m (>= 8)
+    int cand_m[7] = {6, 8, 9, m / 4 < 8 ? 8 : m / 4, m / 2, (3 * m) / 4, m};
+    for (int &c : cand_m)
         if (c > m) c = m;
-    }
-    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 4, false, 2,
+    std::sort(cand_m, cand_m + 7);
+    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 7, false, 2,
                      [&](const xkp_params &P) {
                          return xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
                                                          &P, infos);
@@ -627,7 +629,7 @@ xkp_status xkp_target_project_solve_noalloc(int device, void *hip_stream, int32_
     unsigned *queue = (unsigned *)base;
     hipLaunchKernelGGL(clear_queue_kernel, dim3(1), dim3(64), 0, stream, queue);
     if (hipGetLastError() != hipSuccess) return XKP_EDEVICE;
-    const int flags = params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0;
+    const int flags = (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0) | xkp::kRegBasis;
     return from_hip(xkp::v512::launch_solve(stream, (int)grid, rmax,
                                             xkp::v512::lds_vec_len(nmax), targets, n_targets,
                                             *params, flags, n_bases, bases, nullptr, infos,

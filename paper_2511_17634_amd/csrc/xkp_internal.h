@@ -34,7 +34,8 @@ enum GmresFlags {
     kKeepBasis = 2,    // seed build: write the first cycle into bases[i]
     kTarget = 4,       // project onto the seed basis first, then polish from the projection
     kLearned = 8,      // try the learned guess first; project only if it fails the gate
-    kDcgs = 16         // seeds: the kept cycle by DCGS2 (set by the launcher when the LDS fits)
+    kDcgs = 16,        // seeds: the kept cycle by DCGS2 (set by the launcher when the LDS fits)
+    kRegBasis = 32     // discarded cycles with the basis in registers where it fits
 };
 
 // Learned-guess inputs of a solve launch: target i's predicted residual coordinates at

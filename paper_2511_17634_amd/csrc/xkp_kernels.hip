@@ -646,6 +646,283 @@ __device__ __forceinline__ int arnoldi_dcgs2(const Coef &C, const OpConst &o, do
     }
 }
 
+// ----------------------------------------------------------------------------------------
+// GMRES with the Krylov basis in registers (cycles whose basis is discarded: target polish and
+// plain GMRES, systems of up to 8 rows per thread).  Each thread keeps its rows of the cycle's
+// basis vectors, so the Gram-Schmidt sweeps read no memory at all; the two Gram-Schmidt passes
+// are classical (CGS2: all inner products of a pass in one workgroup reduction, two reductions
+// per Arnoldi step instead of one per basis column), and the norm of the twice-orthogonalised
+// vector follows from the second pass's reduction, ||w2||^2 = ||w1||^2 - ||V^T w1||^2 (the
+// second correction is of the order of the unit roundoff, so there is no cancellation).  Two
+// classical passes give an orthonormal basis to working precision, as two modified passes do.
+
+// Columns the register path holds at R rows per thread (2 R registers each), by workgroup
+// size: what fits the per-lane register budget (256 at two waves per SIMD, 512 with the
+// accumulation registers at one) next to the rest of the cycle without spilling to memory.
+// Sixteen-wave workgroups (128 registers per lane) have no register path.
+template <int R> struct RegCols { static constexpr int value = 0; };
+#if XKP_NT == 512
+template <> struct RegCols<2> { static constexpr int value = 9; };
+template <> struct RegCols<8> { static constexpr int value = 7; };
+#elif XKP_NT == 256
+template <> struct RegCols<4> { static constexpr int value = 16; };
+template <> struct RegCols<16> { static constexpr int value = 10; };
+#endif
+constexpr int kWideMax = 26;   // values reduced together by WideRed (>= every RegCols + 2)
+
+// Workgroup sum of up to kWideMax values at once, one barrier: `red` is LDS of
+// 2 * kWideMax * kNW doubles, halves alternating between calls.  Only the first nv values are
+// summed (nv a compile-time constant after unrolling in the callers).
+struct WideRed {
+    double *red;
+    int par;
+    template <int NV>
+    __device__ __forceinline__ void sum(double (&v)[NV], int nv) {
+        double *slot = red + par * (kWideMax * kNW);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            if (q < nv) {
+                const double t = wave_sum(v[q]);
+                if ((threadIdx.x & 63) == 0) slot[q * kNW + (threadIdx.x >> 6)] = t;
+            }
+        }
+        lds_barrier();
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < nv) v[q] = tree_sum<kNW>(slot + q * kNW);
+        par ^= 1;
+    }
+};
+
+// One cycle's Arnoldi steps with the basis in registers.  The steps are instantiated one by one
+// (step<J> calls step<J + 1>), so every basis column is addressed by a compile-time index and
+// the array stays in registers.
+template <int RMAX, bool MIXED, int MC>
+struct RegCycle {
+    typedef double vt;   // mixed precision stores FP32-rounded values (the FP32 basis)
+    vt (&V)[MC][RMAX];
+    double (&w)[RMAX];
+    const Coef &C;
+    const OpConst &o;
+    GmresLds &L;
+    WideRed &wr;
+    int mc;            // steps allowed in this cycle
+    double tol_abs;    // stop when the residual estimate reaches max(tol_abs, gfloor)
+    double gfloor;
+    double gcur;
+    int kk, iters;
+
+    template <int J>
+    __device__ __forceinline__ void step() {
+        if constexpr (J < MC - 1) {
+            if (J >= mc) return;
+            const int tid = threadIdx.x;
+            if constexpr (MIXED)
+                stencil_lds_f32<RMAX>(L.vbuf, C, o, w);
+            else
+                stencil_lds<RMAX>(L.vbuf, C, o, w);
+            ++iters;
+            // pass 1: h1 = V_{J+1}^T w and ||w||^2 in one reduction
+            double d[J + 2];
+#pragma unroll
+            for (int i = 0; i <= J; ++i) {
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < RMAX; k += 2) {
+                    a0 += (double)V[i][k] * w[k];
+                    a1 += (double)V[i][k + 1] * w[k + 1];
+                }
+                d[i] = a0 + a1;
+            }
+            d[J + 1] = dot_rows<RMAX>(w, w);
+            wr.template sum<J + 2>(d, J + 2);
+            const double wn0 = sqrt(d[J + 1]);
+            double h[J + 1];
+#pragma unroll
+            for (int i = 0; i <= J; ++i) {
+                h[i] = d[i];
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) w[k] -= d[i] * (double)V[i][k];
+            }
+            // pass 2: h2 = V_{J+1}^T w1 and ||w1||^2 in one reduction
+#pragma unroll
+            for (int i = 0; i <= J; ++i) {
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int k = 0; k < RMAX; k += 2) {
+                    a0 += (double)V[i][k] * w[k];
+                    a1 += (double)V[i][k + 1] * w[k + 1];
+                }
+                d[i] = a0 + a1;
+            }
+            d[J + 1] = dot_rows<RMAX>(w, w);
+            wr.template sum<J + 2>(d, J + 2);
+            double c2 = 0.0;
+#pragma unroll
+            for (int i = 0; i <= J; ++i) {
+                h[i] += d[i];
+                c2 += d[i] * d[i];
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) w[k] -= d[i] * (double)V[i][k];
+            }
+            const double hn = sqrt(fmax(d[J + 1] - c2, 0.0));
+            const bool brk = !(hn > 1e-14 * wn0);
+            const double rhn = brk ? 0.0 : 1.0 / hn;
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) {
+                w[k] = MIXED ? (double)(float)(w[k] * rhn) : w[k] * rhn;
+                V[J + 1][k] = w[k];
+            }
+            // Givens rotations of column J (every thread holds the same values)
+            double t = h[0];
+#pragma unroll
+            for (int i = 1; i <= J; ++i) {
+                const double c = L.cs[i - 1], sn = L.sn[i - 1];
+                const double rr = c * t + sn * h[i];
+                t = -sn * t + c * h[i];
+                if (tid == 0) L.Rp[tri(J) + i - 1] = rr;
+            }
+            const double den = sqrt(t * t + hn * hn);
+            const double rden = 1.0 / den;
+            const double cj = t * rden, sj = hn * rden;
+            if (tid == 0) {
+                L.Rp[tri(J) + J] = den;
+                L.cs[J] = cj;
+                L.sn[J] = sj;
+                L.gv[J] = cj * gcur;
+            }
+            gcur = -sj * gcur;
+            kk = J + 1;
+            // the next operator application reads the new vector's neighbours
+            store_rows_lds<RMAX>(L.vbuf, w);
+            lds_barrier();
+            if (fabs(gcur) <= fmax(tol_abs, gfloor) || brk) return;
+            step<J + 1>();
+        }
+    }
+
+    // x += V_k y (y in LDS)
+    template <int J>
+    __device__ __forceinline__ void add_to(double (&x)[RMAX]) {
+        if constexpr (J < MC - 1) {
+            if (J >= kk) return;
+            const double yc = L.yv[J];
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) x[k] += yc * (double)V[J][k];
+            add_to<J + 1>(x);
+        }
+    }
+};
+
+template <int RMAX, bool MIXED, int MC>
+__device__ __forceinline__ void gmres_reg(const xkp_system &s, const xkp_params &P, int flags,
+                                          int prestatus, int gsrc, const Coef &C, xkp_info *info,
+                                          GmresLds &L) {
+    typedef double vt;
+    const OpConst o = op_const(s);
+    const int n = o.n, mpol = P.polish_m > 0 ? P.polish_m : P.m;
+    const int tid = threadIdx.x;
+    BlockRed br{L.red, 0};
+    WideRed wr{L.ext, 0};
+    constexpr bool mixed = MIXED;
+
+    build_coeffs<RMAX>(s, o, C, mixed);
+    vt V[MC][RMAX];   // this thread's rows of the cycle's basis vectors
+    double w[RMAX], cur[RMAX];
+
+    load_rows<RMAX>(s.b, n, cur);
+    const double bnorm = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
+    int iters = 0, restarts = 0, status = XKP_OK;
+    double res_est = 0.0, res_true = 0.0, guess = 0.0;
+
+    if (bnorm == 0.0) {
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) w[k] = 0.0;
+        store_rows<RMAX>(s.x, n, w);
+    } else {
+        const double *xs = (flags & kStartFromX) ? s.x : s.x0;
+        if (xs) {
+            load_rows<RMAX>(xs, n, w);
+            store_rows_lds<RMAX>(L.vbuf, w);
+            if (xs != s.x) store_rows<RMAX>(s.x, n, w);
+            lds_barrier();
+            stencil_lds<RMAX>(L.vbuf, C, o, w);
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) cur[k] -= w[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) w[k] = 0.0;
+            store_rows<RMAX>(s.x, n, w);
+        }
+        double beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
+        guess = res_true = res_est = beta / bnorm;
+        if (beta > P.tol * bnorm) {
+            for (;;) {
+                // v_0 = r / beta (rounded to FP32 in mixed precision: the stored basis)
+                const double rbeta = 1.0 / beta;
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) {
+                    w[k] = mixed ? (double)(float)(cur[k] * rbeta) : cur[k] * rbeta;
+                    V[0][k] = w[k];
+                }
+                store_rows_lds<RMAX>(L.vbuf, w);
+                lds_barrier();
+                RegCycle<RMAX, MIXED, MC> cy{V, w, C, o, L, wr, mpol, P.tol * bnorm,
+                                             mixed ? kMixedCycleDrop * beta : 0.0, beta, 0,
+                                             iters};
+                cy.template step<0>();
+                iters = cy.iters;
+                const int kk = cy.kk;
+                res_est = fabs(cy.gcur) / bnorm;
+                // y = R^{-1} g by one wavefront (lane c holds g_c and 1 / R_cc)
+                if (tid < 64) {
+                    double gl = (tid < kk) ? L.gv[tid] : 0.0;
+                    const double rdiag = (tid < kk) ? 1.0 / L.Rp[tri(tid) + tid] : 0.0;
+                    for (int c = kk - 1; c >= 0; --c) {
+                        const double yc = readlane_d(gl, c) * readlane_d(rdiag, c);
+                        if (tid < c) gl -= L.Rp[tri(c) + tid] * yc;
+                        if (tid == 0) L.yv[c] = yc;
+                    }
+                }
+                lds_barrier();
+                // x += V_k y
+                load_rows<RMAX>(s.x, n, w);
+                cy.template add_to<0>(w);
+                store_rows<RMAX>(s.x, n, w);
+                store_rows_lds<RMAX>(L.vbuf, w);
+                lds_barrier();
+                // true residual in FP64
+                stencil_lds<RMAX>(L.vbuf, C, o, w);
+                load_rows<RMAX>(s.b, n, cur);
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) cur[k] -= w[k];
+                beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
+                res_true = beta / bnorm;
+                if (beta <= P.tol * bnorm) break;
+                if (restarts >= P.max_restarts) {
+                    status = XKP_ENOCONV;
+                    break;
+                }
+                ++restarts;
+            }
+        }
+    }
+    if (tid == 0) {
+        int st = status;
+        if (st == XKP_OK && (flags & kTarget) && prestatus == XKP_ESINGULAR) st = XKP_ESINGULAR;
+        info->status = st;
+        info->iters = iters;
+        info->restarts = restarts;
+        if (!(flags & kTarget)) info->basis_dim = 0;
+        info->res_est = res_est;
+        info->res_true = res_true;
+        info->guess_res = guess;
+        info->guess_source = gsrc;
+        info->pad = 0;
+    }
+    __syncthreads();
+}
+
 template <int RMAX, bool MIXED>
 __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params &P, int flags,
                                           int prestatus, int gsrc,
@@ -1500,6 +1777,14 @@ __device__ __noinline__ int project_call(xkp_system s, xkp_info *info, int n_bas
                           xkp_dyn_lds, uni(nlds), uni(nbuf), uni(nregion));
 }
 
+template <int R, bool MIXED, int MC>
+__device__ __noinline__ void gmres_reg_call(xkp_system s, xkp_params P, int flags, int pre,
+                                            int gsrc, Coef C, xkp_info *info, int nlds) {
+    GmresLds L(xkp_dyn_lds, uni(nlds), kNT * R);
+    gmres_reg<R, MIXED, MC>(uni(s), uni(P), uni(flags), uni(pre), uni(gsrc), uni(C), uni(info),
+                            L);
+}
+
 template <int R, bool MIXED>
 __device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, int pre, int gsrc,
                                         xkp_basis_header *hdr, double *Vfirst, double *Hb,
@@ -1638,6 +1923,19 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         hdr = (xkp_basis_header *)keep_base;
         Vfirst = (double *)((char *)keep_base + 256);
         Hb = (double *)((char *)keep_base + basis_off_h(s.H * s.H, P.m));
+    }
+    // discarded cycles that fit the register budget keep their basis in registers
+    constexpr int MC = RegCols<R>::value;
+    if constexpr (MC > 0) {
+        const int mpol = P.polish_m > 0 ? P.polish_m : P.m;
+        if (!keep_base && (flags & kRegBasis) && mpol + 1 <= MC &&
+            P.reorth == XKP_REORTH_AUTO) {
+            if (P.precision == XKP_MIXED)
+                gmres_reg_call<R, true, MC>(s, P, flags, pre, gsrc, C, info, nlds);
+            else
+                gmres_reg_call<R, false, MC>(s, P, flags, pre, gsrc, C, info, nlds);
+            return;
+        }
     }
     // seeds keep the FP64 operator in mixed precision: one system per timestep on the chain's
     // critical path, where the FP32 operator's cycle limit would cost restarts
@@ -1997,7 +2295,7 @@ int lds_vec_len(int nmax) {
 
 static size_t gmres_lds_bytes(int nlds) {
     return sizeof(double) * ((size_t)nlds + kMMax * (kMMax + 1) / 2 + 6 * kMMax + 3 +
-                             2 * kRedSlots * kNW);
+                             2 * kRedSlots * kNW + 2 * kWideMax * kNW);
 }
 static size_t project_lds_bytes(int nlds) {
     return sizeof(double) * ((size_t)nlds + (kMMax + 1) + kMMax + kMMax / 2 + 2 * kRedSlots * kNW);

@@ -269,7 +269,7 @@ def test_autotune_picks_a_converging_candidate(X):
     t0 = np.stack([blob_pair(H, seed=90, jitter=1.0 + 0.5 * i)[1] for i in range(6)])
     ch = Chain(H, T, m, s0, t0)
     t = ch.autotune(steps=2)
-    assert t.polish_m in (10, 20, 30, 40) and t.wg_per_cu >= 1 and t.n_tried >= 4
+    assert t.polish_m in (6, 8, 9, 10, 20, 30, 40) and t.wg_per_cu >= 1 and t.n_tried >= 7
     assert 0 < t.ms_best <= t.ms_default * 1.000001
     assert ch.params.polish_m == t.polish_m
     ch.run()
