@@ -52,7 +52,8 @@ extern "C" {
 
 typedef enum {
     XKP_OK = 0,            /* success / system converged                                   */
-    XKP_EINVAL = 1,        /* invalid argument or descriptor                              */
+    XKP_EINVAL = 1,        /* invalid argument or descriptor; per system also data that
+                              are not finite (NaN or Inf in m~, f, b or x0)               */
     XKP_ENOMEM = 2,        /* device allocation failed                                    */
     XKP_EDEVICE = 3,       /* HIP runtime error                                           */
     XKP_ENOCONV = 4,       /* GMRES hit max_restarts; x holds the last iterate            */

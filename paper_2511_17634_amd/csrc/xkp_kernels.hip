@@ -856,7 +856,9 @@ __device__ __forceinline__ void gmres_reg(const xkp_system &s, const xkp_params 
         }
         double beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
         guess = res_true = res_est = beta / bnorm;
-        if (beta > P.tol * bnorm) {
+        // data that are not finite (NaN or Inf in m~, f, b or x0) cannot be solved
+        if (!isfinite(beta) || !isfinite(bnorm)) status = XKP_EINVAL;
+        if (status == XKP_OK && beta > P.tol * bnorm) {
             for (;;) {
                 // v_0 = r / beta (rounded to FP32 in mixed precision: the stored basis)
                 const double rbeta = 1.0 / beta;
@@ -899,6 +901,10 @@ __device__ __forceinline__ void gmres_reg(const xkp_system &s, const xkp_params 
                 beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
                 res_true = beta / bnorm;
                 if (beta <= P.tol * bnorm) break;
+                if (!isfinite(beta)) {
+                    status = XKP_EINVAL;   // the operator produced a non-finite value
+                    break;
+                }
                 if (restarts >= P.max_restarts) {
                     status = XKP_ENOCONV;
                     break;
@@ -980,7 +986,9 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
         double beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
         guess = res_true = res_est = beta / bnorm;
         bool first = true;
-        if (beta > P.tol * bnorm) {
+        // data that are not finite (NaN or Inf in m~, f, b or x0) cannot be solved
+        if (!isfinite(beta) || !isfinite(bnorm)) status = XKP_EINVAL;
+        if (status == XKP_OK && beta > P.tol * bnorm) {
             for (;;) {
                 double *V = first ? Vfirst : Vws;
                 // v_0 = r / beta (as stored); the LDS copy feeds the stencil
@@ -1126,6 +1134,10 @@ __device__ __forceinline__ void gmres_one(const xkp_system &s, const xkp_params 
                 beta = sqrt(br.sum(dot_rows<RMAX>(cur, cur)));
                 res_true = beta / bnorm;
                 if (beta <= P.tol * bnorm) break;
+                if (!isfinite(beta)) {
+                    status = XKP_EINVAL;   // the operator produced a non-finite value
+                    break;
+                }
                 if (restarts >= P.max_restarts) {
                     status = XKP_ENOCONV;
                     break;
@@ -1902,6 +1914,9 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
             project = false;
             gsrc = 2;
             flags |= kStartFromX;
+            // the guess used the seed basis: report its dimension as the projection does
+            if (threadIdx.x == 0)
+                info->basis_dim = ((const xkp_basis_header *)bases[s.basis_id])->k;
         }
     }
     if (PROJ && project) {
