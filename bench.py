@@ -255,6 +255,11 @@ def mixed_leg(args, orc=None):
                                 sv=4 if mixed else 8, sop=12 if mixed else 24,
                                 sbv=2 if mixed else 0)
         rec = b.record_chain(picks).cpu().numpy() if orc is not None else None
+        sms = None
+        if method == "project":
+            sms = {"alone": round(seed_call_ms(b, True), 4),
+                   "beside_targets": round(seed_call_ms(b, False), 4),
+                   "rows_per_thread": b.seed_tuning.seed_rows if b.seed_tuning else None}
         mx[name] = {"value": round(b.N * cfg3.T / r["per_chain_s"], 2),
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                     "target_phase_value": round(b.N * cfg3.T / (sum(lm) / 1e3), 2),
@@ -265,6 +270,7 @@ def mixed_leg(args, orc=None):
                     "seed_waves": None if tu is None or b.seed_tuning is None
                     else b.seed_tuning.waves,
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
+                    "seed_call_ms": sms,
                     "roofline": roofline(f"solve_kernel ({name}, {b.N} systems per launch)",
                                          byts, np.mean(lm) / 1e3,
                                          traffic_bytes(f"c3_{name}", r["polish_m"]))}
@@ -572,6 +578,26 @@ def target_call_ms(b):
     return [a.elapsed_time(e) for a, e in ev]
 
 
+def seed_call_ms(b, alone=True):
+    """Mean duration of the seed call (HIP events on the seed stream): over one eager chain in
+    which every timestep's target call waits for its seed call to end (alone), or over the
+    ordinary pipelined chain (seed n+1 beside targets n)."""
+    import torch
+    if not b.with_seeds:
+        return None
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(b.T)]
+    b.reset()
+    for t in range(b.T):
+        if alone and b.pipeline:
+            b.s_seed.wait_stream(b.s_main)
+        b.step(seed_events=ev[t])
+        if alone and b.pipeline:
+            b.s_main.wait_stream(b.s_seed)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(e) for a, e in ev]))
+
+
 def chain_shape(b):
     """(unknowns, basis id) of every target of a driver Batch."""
     return [H * H for H, _, _ in b.tgt_sys], [bid for _, _, bid in b.tgt_sys]
@@ -788,6 +814,15 @@ def main():
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name in ("project", "plain", "project_warm", "plain_warm"):
             launch[name] = target_call_ms(ch)
+        if method == "project":
+            legs[name]["seed_ms"] = {"alone": round(seed_call_ms(ch, True), 4),
+                                     "beside_targets": round(seed_call_ms(ch, False), 4)}
+            if name == "project":
+                # the same seed call on one workgroup, for scale
+                rows = ch.ctx_seed_rows()
+                ch.ctx_seed.set_seed_width(0)
+                legs[name]["seed_ms"]["one_workgroup_alone"] = round(seed_call_ms(ch, True), 4)
+                ch.ctx_seed.set_seed_width(rows)
         print(f"# {name}: {legs[name]['per_chain_s'] * 1e3:.1f} ms/chain, ok={legs[name]['ok']}, "
               f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
               file=sys.stderr, flush=True)
@@ -829,6 +864,8 @@ def main():
         if name in launch:
             d["target_phase_value"] = round(N * T / (sum(launch[name]) / 1e3), 2)
             d["target_launch_ms"] = round(float(np.mean(launch[name])), 4)
+        if "seed_ms" in r:
+            d["seed_call_ms"] = r["seed_ms"]
         return d
 
     out = {
@@ -846,7 +883,8 @@ def main():
         "plain_gmres": summary("plain"),
         "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu, "waves": t.waves,
                          "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4),
-                         "seed_waves": None if ts is None else ts.waves}
+                         "seed_waves": None if ts is None else ts.waves,
+                         "seed_rows_per_thread": None if ts is None else ts.seed_rows}
                      for k, (t, ts) in tunings.items()},
         # the headline chain's own target launch: projection + polish of the 63 targets
         "roofline": leg_roof("project", True),

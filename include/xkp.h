@@ -182,6 +182,23 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
  * reduction trees change).  XKP_EUNSUPPORTED if no kernel variant of that size covers max_n. */
 xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
 
+/*
+ * Seed solves spread over several workgroups (Section 3, Phase 1: the seed of a timestep gates
+ * every target of that timestep, so its single solve is the chain's critical path).  With
+ * rows_per_thread R in {1, 2, 4}, later xkp_seed_build calls of this context (of at most 64
+ * seeds, default Gram-Schmidt setting) solve each seed with ceil(n / (512 R)) workgroups of 512
+ * threads, each owning 512 R consecutive rows, placed on one XCD: the operator's neighbour rows
+ * of adjacent blocks are exchanged through device memory, and each Arnoldi step takes two
+ * classical Gram-Schmidt passes whose inner products are summed over the blocks in a fixed order
+ * (an orthonormal basis to working precision, as the two modified passes of the one-workgroup
+ * solve give); results are those of the one-workgroup solve to rounding.  The workgroups of a
+ * seed must be resident together: each wait for the others gives up after two seconds with
+ * XKP_EDEVICE for that seed (no hang).  Requires grids of at most 128 x 128 and max_m <= 64
+ * (XKP_EUNSUPPORTED otherwise); allocates the exchange buffers (a setup call, like
+ * xkp_ctx_create).  R = 0 returns to one workgroup per seed.
+ */
+xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread);
+
 /* Size in bytes of one seed basis buffer for n unknowns and restart length m. */
 size_t xkp_basis_bytes(int32_t n, int32_t m);
 
@@ -374,6 +391,8 @@ typedef struct {
     float ms_default;     /* time with polish_m = m, 8-wave workgroups, the most per CU     */
     int32_t n_tried;      /* candidates timed                                               */
     int32_t waves;        /* fastest workgroup size in wave64s (now set in the context)     */
+    int32_t seed_rows;    /* xkp_autotune_seeds: rows per thread of the chosen spread-out seed
+                             solve (xkp_ctx_set_seed_width), 0 for one workgroup per seed     */
 } xkp_tuning;
 
 /*
@@ -396,8 +415,10 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
 /*
  * Launch autotuner for seed calls: times xkp_seed_build on the given seeds (one representative
  * timestep) for each kernel variant covering them and each workgroup count per compute unit,
- * five timed calls each after one untimed call, and keeps the fastest candidate whose every seed
- * converged; the variant and workgroup count are stored in the context (meant for a context
+ * then each seed spread over several workgroups (xkp_ctx_set_seed_width with 1, 2 and 4 rows
+ * per thread, where that gives a seed at least two workgroups), five timed calls each after one
+ * untimed call, and keeps the fastest candidate whose every seed converged; the choice is stored
+ * in the context (meant for a context
  * that serves seed calls only: a seed is one workgroup on the chain's critical path, whose best
  * workgroup size can differ from the targets').  out->polish_m is params->m.
  * Side effects: the bases, seeds[i].x and infos hold the last candidate's results.  Synchronises

@@ -20,6 +20,13 @@ struct xkp_ctx {
     int cus;            // compute units of the device
     int per_cu;         // workgroups per compute unit used for the grid (autotuned)
     int variant;        // kernel variant (workgroup size) of the solve launches (autotuned)
+    // seeds spread over several workgroups (xkp_ctx_set_seed_width): rows per thread (0: one
+    // workgroup per seed), workgroups per seed at max_n, exchange areas and later-cycle rows
+    int wide_R, wide_gmax, wide_cap;
+    unsigned char *xch;
+    size_t xch_stride;
+    double *mws;
+    size_t mws_stride;
 };
 
 namespace {
@@ -195,6 +202,8 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     hipError_t f = hipFree(ctx->ws);
     hipError_t q = hipFree(ctx->queue);
+    if (ctx->xch) hipFree(ctx->xch);
+    if (ctx->mws) hipFree(ctx->mws);
     delete ctx;
     return (e == hipSuccess && f == hipSuccess && q == hipSuccess) ? XKP_OK : XKP_EDEVICE;
 }
@@ -212,6 +221,43 @@ xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu) {
     return XKP_EINVAL;
 }
 
+xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread) {
+    if (!ctx || (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 &&
+                 rows_per_thread != 4))
+        return XKP_EINVAL;
+    if (rows_per_thread == 0) {
+        ctx->wide_R = 0;
+        return XKP_OK;
+    }
+    int h = 1;
+    while (h * h < ctx->max_n) ++h;
+    if (h > 128 || ctx->max_m > 64) return XKP_EUNSUPPORTED;
+    const int nb = 512 * rows_per_thread;
+    const int gmax = (ctx->max_n + nb - 1) / nb;
+    const int cap = ctx->max_batch < 64 ? ctx->max_batch : 64;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return XKP_EDEVICE;
+    if (ctx->xch) hipFree(ctx->xch);
+    if (ctx->mws) hipFree(ctx->mws);
+    ctx->xch = nullptr;
+    ctx->mws = nullptr;
+    ctx->wide_R = 0;
+    const size_t xs = xkp::wide::xch_bytes(gmax);
+    const size_t ms = (size_t)(ctx->max_m + 1) * nb;
+    if (hipMalloc((void **)&ctx->xch, xs * cap) != hipSuccess) return XKP_ENOMEM;
+    if (hipMalloc((void **)&ctx->mws, sizeof(double) * ms * gmax * cap) != hipSuccess) {
+        hipFree(ctx->xch);
+        ctx->xch = nullptr;
+        return XKP_ENOMEM;
+    }
+    ctx->xch_stride = xs;
+    ctx->mws_stride = ms;
+    ctx->wide_gmax = gmax;
+    ctx->wide_cap = cap;
+    ctx->wide_R = rows_per_thread;
+    return XKP_OK;
+}
+
 size_t xkp_basis_bytes(int32_t n, int32_t m) {
     if (n < 1 || m < 1) return 0;
     return xkp::basis_bytes(n, m);
@@ -226,6 +272,13 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     if (n_seeds > 0 && (!bases || !infos)) return XKP_EINVAL;
     if (n_seeds == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    if (ctx->wide_R > 0 && n_seeds <= ctx->wide_cap && params->reorth == XKP_REORTH_AUTO) {
+        // each seed over ceil(n / (512 R)) workgroups; a wait gives up after two seconds
+        return from_hip(xkp::wide::launch_wide_seed(ctx->stream, ctx->wide_R, seeds, n_seeds,
+                                                    *params, bases, infos, ctx->xch,
+                                                    ctx->xch_stride, ctx->mws, ctx->mws_stride,
+                                                    ctx->wide_gmax, nmax, 200000000LL));
+    }
     const int grid = solve_grid(ctx, n_seeds);
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
                              *params, xkp::kKeepBasis, 0, nullptr, bases, infos, ctx->ws, ctx->L,
@@ -541,11 +594,65 @@ xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *s
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int nmax = params->batch_max_n > 0 ? params->batch_max_n : ctx->max_n;
     const int cand_m[1] = {params->m};
-    return tune_loop(ctx, nmax, n_seeds, infos, params, cand_m, 1, true, 5,
-                     [&](const xkp_params &P) {
-                         return xkp_seed_build(ctx, n_seeds, seeds, bases, &P, infos);
-                     },
-                     out);
+    const int saved_R = ctx->wide_R;
+    ctx->wide_R = 0;
+    auto call = [&](const xkp_params &P) {
+        return xkp_seed_build(ctx, n_seeds, seeds, bases, &P, infos);
+    };
+    xkp_status st = tune_loop(ctx, nmax, n_seeds, infos, params, cand_m, 1, true, 5, call, out);
+    out->seed_rows = 0;
+    if (st != XKP_OK) {
+        ctx->wide_R = saved_R;
+        return st;
+    }
+    // then each seed over several workgroups, 512 R rows each (R = 1, 2, 4), when it allows
+    // at least two of them; kept if faster with every seed converged
+    int h = 1;
+    while (h * h < nmax) ++h;
+    if (n_seeds > 64 || h > 128 || params->reorth != XKP_REORTH_AUTO) return XKP_OK;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return XKP_EDEVICE;
+    }
+    std::vector<xkp_info> host(n_seeds);
+    int best_R = 0;
+    for (int R : {1, 2, 4}) {
+        if ((nmax + 512 * R - 1) / (512 * R) < 2) continue;
+        if (xkp_ctx_set_seed_width(ctx, R) != XKP_OK) continue;
+        float ms = 0.f;
+        bool ok = call(*params) == XKP_OK && hipEventRecord(e0, ctx->stream) == hipSuccess;
+        for (int rep = 0; ok && rep < 5; ++rep) ok = call(*params) == XKP_OK;
+        ok = ok && hipEventRecord(e1, ctx->stream) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+             hipMemcpy(host.data(), infos, sizeof(xkp_info) * n_seeds,
+                       hipMemcpyDeviceToHost) == hipSuccess;
+        if (!ok) {
+            st = XKP_EDEVICE;
+            break;
+        }
+        ms /= 5.f;
+        ++out->n_tried;
+        bool conv = true;
+        for (const xkp_info &i : host) conv = conv && i.status == XKP_OK;
+        if (conv && ms < out->ms_best) {
+            out->ms_best = ms;
+            best_R = R;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != XKP_OK) {
+        xkp_ctx_set_seed_width(ctx, 0);
+        return st;
+    }
+    st = xkp_ctx_set_seed_width(ctx, best_R);
+    if (st != XKP_OK) return st;
+    out->seed_rows = best_R;
+    // the last candidate's results are in the outputs: recompute them with the choice
+    return call(*params);
 }
 
 size_t xkp_cnn_param_count(int32_t k) {

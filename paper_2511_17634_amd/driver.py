@@ -227,10 +227,10 @@ class Batch:
         return (self.info_s_all[t * self.S * w:(t + 1) * self.S * w],
                 self.info_t_all[t * self.N * w:(t + 1) * self.N * w])
 
-    def step(self, events=None, after_targets=None):
+    def step(self, events=None, after_targets=None, seed_events=None):
         """Enqueue one timestep.  `events`, if given, is a pair of HIP events recorded on the
-        main stream around the target call; `after_targets(par, bases)` is called after the
-        target call is enqueued."""
+        main stream around the target call (`seed_events`: on the seed stream around the seed
+        call); `after_targets(par, bases)` is called after the target call is enqueued."""
         par = self.step_no & 1
         c = self.ctx
         inf_s, inf_t = self._info_slices(self.step_no % self.T)
@@ -240,7 +240,11 @@ class Batch:
             if self.pipeline and self.step_no >= 2:
                 self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
             cs.build_rhs(self.seed_desc[par], self.S)
+            if seed_events is not None:
+                seed_events[0].record(cs.stream)
             cs.seed_build(self.seed_desc[par], self.S, bases, self.params, inf_s)
+            if seed_events is not None:
+                seed_events[1].record(cs.stream)
             bases = self._accumulate(par, bases)
             if self.pipeline:
                 self.ev_seed[par].record(self.s_seed)
@@ -351,6 +355,11 @@ class Batch:
         self.reset()
         torch.cuda.synchronize(self.dev)
         return t
+
+    def ctx_seed_rows(self):
+        """Rows per thread of the seed context's spread-out seed solve (0: one workgroup)."""
+        t = getattr(self, "seed_tuning", None)
+        return 0 if t is None else int(t.seed_rows)
 
     def _join(self):
         """Order the current stream after everything enqueued on the chain's streams."""

@@ -42,7 +42,8 @@ class Params(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("polish_m", ct.c_int32), ("wg_per_cu", ct.c_int32), ("ms_best", ct.c_float),
-                ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("waves", ct.c_int32)]
+                ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("waves", ct.c_int32),
+                ("seed_rows", ct.c_int32)]
 
 
 class XkpError(RuntimeError):
@@ -69,6 +70,7 @@ def load():
                                        ct.c_int32]
         lib.xkp_ctx_destroy.argtypes = [P]
         lib.xkp_ctx_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
+        lib.xkp_ctx_set_seed_width.argtypes = [P, ct.c_int32]
         lib.xkp_basis_bytes.argtypes = [ct.c_int32, ct.c_int32]
         lib.xkp_basis_bytes.restype = ct.c_size_t
         lib.xkp_seed_build.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P]
@@ -109,7 +111,7 @@ def load():
                   "xkp_score_flow", "xkp_cluster_seeds",
                   "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch",
-                  "xkp_target_project_solve_noalloc"):
+                  "xkp_target_project_solve_noalloc", "xkp_ctx_set_seed_width"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -215,6 +217,12 @@ class Context:
     def set_launch(self, waves, wg_per_cu=1):
         """Workgroup size (8 or 16 wave64s) and workgroups per compute unit of later solves."""
         _check(load().xkp_ctx_set_launch(self._h, waves, wg_per_cu), "xkp_ctx_set_launch")
+
+    def set_seed_width(self, rows_per_thread):
+        """Later seed calls spread each seed over workgroups of 512 * rows_per_thread rows
+        (1, 2 or 4), or one workgroup per seed (0)."""
+        _check(load().xkp_ctx_set_seed_width(self._h, rows_per_thread),
+               "xkp_ctx_set_seed_width")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,149 @@
+"""GPU parity of seed solves spread over several workgroups (xkp_ctx_set_seed_width) against the
+FP64 oracle and against the one-workgroup seed solve, through the C ABI: converged solution
+within the Varah bound, iteration counts, the kept basis (leading columns, Hessenberg matrix,
+orthonormality, Arnoldi relation), restarts, a warm start, several seeds of different sizes in
+one call, the BF16 copy, and a projected chain on the spread-out seeds."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import blob_pair, cpu, dev, t64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def X():
+    from paper_2511_17634_amd import xkp
+    xkp.load()
+    return xkp
+
+
+def _seeds(X, Hs, T, m, R, x0s=None, precision=None, tol=1e-8, polish_m=0):
+    """Seeds of sides Hs in one call with rows_per_thread R (0: one workgroup each)."""
+    import torch
+    nmax = max(H * H for H in Hs)
+    ctx = X.Context(nmax, m, len(Hs))
+    ctx.set_seed_width(R)
+    specs, out = [], []
+    for k, H in enumerate(Hs):
+        ms, _ = blob_pair(H, seed=100 + H)
+        b = torch.zeros(H * H, dtype=torch.float64, device=dev())
+        x = torch.zeros(H * H, dtype=torch.float64, device=dev())
+        x0 = None if x0s is None else t64(x0s[k])
+        specs.append(X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=b, x=x, x0=x0))
+        out.append((H, ms, b, x))
+    d = X.pack_systems(specs, dev())
+    ctx.build_rhs(d, len(Hs))
+    bases = X.Bases(len(Hs), [H * H for H in Hs], m)
+    info = ctx.new_infos(len(Hs))
+    P = X.Context.params(m, tol=tol, polish_m=polish_m,
+                         precision=X.FP64 if precision is None else precision)
+    ctx.seed_build(d, len(Hs), bases.ptrs, P, info)
+    torch.cuda.synchronize()
+    return bases, X.infos_to_numpy(info), [(H, ms, cpu(b), cpu(x)) for H, ms, b, x in out]
+
+
+def _check_seed(X, H, T, m, ms, b, x, inf, bases, i, tol=1e-8, polish_m=0):
+    A = oracle.Operator(H, 1.0 / T, 0.5, ms)
+    assert inf["status"] == X.OK, inf["status"]
+    assert oracle.residual(A, b, x) <= tol and abs(oracle.residual(A, b, x) - inf["res_true"]) <= 1e-12
+    xs, _ = oracle.banded_solve(A, b)
+    rinf = np.abs(b - oracle.apply(A, x)).max()
+    assert np.abs(x - xs).max() <= A.dt * rinf * (1 + 1e-6) + 1e-13 * np.abs(xs).max()
+    ro = oracle.gmres(A, b, m=m, tol=tol, keep_basis=True)
+    if polish_m == 0:
+        assert abs(int(inf["iters"]) - ro.iters) <= max(2, 0.05 * ro.iters), (inf["iters"], ro.iters)
+    hdr = bases.header(i)
+    k = hdr["k"]
+    assert k == inf["basis_dim"] and abs(k - ro.basis_dim) <= 1
+    V = cpu(bases.V(i))[:, :k + 1]
+    Hb = cpu(bases.Hbar(i))[:k + 1, :k]
+    c = min(6, k + 1, ro.basis_dim + 1)
+    assert np.abs(V[:, :c] - ro.V[:, :c]).max() <= 1e-10
+    assert np.abs(V[:, :k].T @ V[:, :k] - np.eye(k)).max() <= 1e-12
+    AV = np.stack([oracle.apply(A, V[:, j]) for j in range(k)], axis=1)
+    Anorm = sum(np.abs(cf) for cf in oracle.coeffs(A)).max()   # max row sum of |A|
+    assert np.abs(AV - V @ Hb).max() <= 1e-12 * Anorm
+    kk = min(k, ro.basis_dim)
+    assert np.abs(Hb[:kk + 1, :min(kk, 6)] - ro.Hbar[:kk + 1, :min(kk, 6)]).max() <= \
+        1e-9 * np.abs(ro.Hbar).max()
+
+
+@pytest.mark.parametrize("H,m,R", [(64, 40, 1), (64, 40, 2), (128, 60, 1), (128, 60, 4),
+                                   (100, 50, 1), (28, 30, 1), (32, 16, 1)])
+def test_wide_seed_matches_oracle(X, H, m, R):
+    T = 100 if H != 28 else 50
+    bases, inf, out = _seeds(X, [H], T, m, R)
+    H_, ms, b, x = out[0]
+    _check_seed(X, H, T, m, ms, b, x, inf[0], bases, 0)
+
+
+def test_wide_seed_equals_one_workgroup_seed(X):
+    """The same seeds (three sizes in one call) spread out and on one workgroup each: same
+    steps, kept bases and solutions to rounding."""
+    Hs, T, m = [32, 64, 100], 100, 30
+    b1, i1, o1 = _seeds(X, Hs, T, m, 0)
+    b2, i2, o2 = _seeds(X, Hs, T, m, 1)
+    assert np.array_equal(i1["status"], i2["status"]) and np.all(i2["status"] == X.OK)
+    assert np.abs(i1["iters"].astype(int) - i2["iters"].astype(int)).max() <= 1
+    for k in range(3):
+        kk = min(b1.header(k)["k"], b2.header(k)["k"])
+        assert abs(b1.header(k)["k"] - b2.header(k)["k"]) <= 1
+        V1, V2 = cpu(b1.V(k))[:, :kk], cpu(b2.V(k))[:, :kk]
+        assert np.abs(V1[:, :8] - V2[:, :8]).max() <= 1e-10, k
+        x1, x2 = o1[k][3], o2[k][3]
+        assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x1).max(), k
+
+
+def test_wide_seed_restarts_and_warm_start(X):
+    """A first cycle that cannot converge (m = 8): later cycles (polish restart 6) on the
+    workgroups' own basis rows reach the tolerance; and a warm start x0 = m^{n-1}."""
+    H, T, m = 64, 100, 8
+    bases, inf, out = _seeds(X, [H], T, m, 1, polish_m=6)
+    H_, ms, b, x = out[0]
+    assert inf[0]["restarts"] >= 2 and inf[0]["basis_dim"] == m
+    _check_seed(X, H, T, m, ms, b, x, inf[0], bases, 0, polish_m=6)
+    ms0, _ = blob_pair(H, seed=100 + H)
+    bases, inf, out = _seeds(X, [H], T, 40, 1, x0s=[ms0])
+    H_, ms, b, x = out[0]
+    A = oracle.Operator(H, 1.0 / T, 0.5, ms)
+    assert inf[0]["status"] == X.OK and oracle.residual(A, b, x) <= 1e-8
+    ro = oracle.gmres(A, b, x0=ms0, m=40, keep_basis=True)
+    assert abs(int(inf[0]["iters"]) - ro.iters) <= max(2, 0.05 * ro.iters)
+    V = cpu(bases.V(0))
+    assert np.abs(V[:, :6] - ro.V[:, :6]).max() <= 1e-10
+
+
+def test_wide_seed_bf16_copy(X):
+    import torch
+    H, T, m = 64, 100, 40
+    bases, inf, out = _seeds(X, [H], T, m, 1, precision=X.MIXED)
+    assert inf[0]["status"] == X.OK and bases.header(0)["bf16"] == 1
+    k = bases.header(0)["k"]
+    Vp = bases.V_padded(0)[:, :k + 1]
+    want = Vp.to(torch.float32).to(torch.bfloat16).view(torch.int16)
+    assert torch.equal(bases.Vb_bits(0)[:, :k + 1], want)
+
+
+def test_projected_chain_on_wide_seeds(X):
+    """A 64x64 chain (1 seed + 6 targets, 8 timesteps) with the seed spread over workgroups:
+    every solve converges and targets and seed follow the oracle chain."""
+    import torch
+    from oracle.chain import run_chain
+    from paper_2511_17634_amd.driver import Chain
+    H, T, m, steps = 64, 100, 40, 8
+    s0, _ = blob_pair(H, seed=55)
+    t0 = np.stack([blob_pair(H, seed=55, jitter=0.5 + 0.4 * i)[1] for i in range(6)])
+    ch = Chain(H, T, m, s0, t0)
+    ch.ctx_seed.set_seed_width(1)
+    ch.reset()
+    for _ in range(steps):
+        ch.step()
+    torch.cuda.synchronize()
+    s_inf, t_inf = ch.infos()
+    assert np.all(s_inf["status"] == X.OK) and np.all(t_inf["status"] == X.OK)
+    ms_o, mt_o, st = run_chain(s0, t0, H, T, m, steps=steps)
+    bound = steps * 1e-8 * max(np.linalg.norm(s0), np.linalg.norm(t0, axis=1).max())
+    assert np.abs(cpu(ch.target_state) - mt_o).max() <= bound
+    assert np.abs(cpu(ch.seed_state) - ms_o).max() <= bound
