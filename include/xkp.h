@@ -185,17 +185,18 @@ xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
 /*
  * Seed solves spread over several workgroups (Section 3, Phase 1: the seed of a timestep gates
  * every target of that timestep, so its single solve is the chain's critical path).  With
- * rows_per_thread R in {1, 2, 4}, later xkp_seed_build calls of this context (of at most 64
- * seeds, default Gram-Schmidt setting) solve each seed with ceil(n / (512 R)) workgroups of 512
- * threads, each owning 512 R consecutive rows, placed on one XCD: the operator's neighbour rows
- * of adjacent blocks are exchanged through device memory, and each Arnoldi step takes two
- * classical Gram-Schmidt passes whose inner products are summed over the blocks in a fixed order
- * (an orthonormal basis to working precision, as the two modified passes of the one-workgroup
- * solve give); results are those of the one-workgroup solve to rounding.  The workgroups of a
- * seed must be resident together: each wait for the others gives up after two seconds with
- * XKP_EDEVICE for that seed (no hang).  Requires grids of at most 128 x 128 and max_m <= 64
- * (XKP_EUNSUPPORTED otherwise); allocates the exchange buffers (a setup call, like
- * xkp_ctx_create).  R = 0 returns to one workgroup per seed.
+ * rows_per_thread = 1, later xkp_seed_build calls of this context (of at most 64 seeds, default
+ * Gram-Schmidt setting) solve each seed with ceil(n / 256) workgroups of 256 threads, each owning
+ * 256 consecutive rows and keeping its rows of the cycle's basis in LDS; a seed's workgroups share
+ * one XCD when there are at most 32 of them.  The operator's neighbour rows of adjacent blocks
+ * are exchanged through device memory, and each Arnoldi step takes two classical Gram-Schmidt
+ * passes whose inner products are summed over the blocks in a fixed order (an orthonormal basis
+ * to working precision, as the two modified passes of the one-workgroup solve give); results are
+ * those of the one-workgroup solve to rounding.  The workgroups of a seed must be resident
+ * together: each wait for the others gives up after two seconds with XKP_EDEVICE for that seed
+ * (no hang).  Requires grids of at most 128 x 128 and max_m <= 64 (XKP_EUNSUPPORTED otherwise);
+ * allocates the exchange buffers (a setup call, like xkp_ctx_create).  0 returns to one
+ * workgroup per seed.
  */
 xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread);
 
@@ -391,8 +392,8 @@ typedef struct {
     float ms_default;     /* time with polish_m = m, 8-wave workgroups, the most per CU     */
     int32_t n_tried;      /* candidates timed                                               */
     int32_t waves;        /* fastest workgroup size in wave64s (now set in the context)     */
-    int32_t seed_rows;    /* xkp_autotune_seeds: rows per thread of the chosen spread-out seed
-                             solve (xkp_ctx_set_seed_width), 0 for one workgroup per seed     */
+    int32_t seed_rows;    /* xkp_autotune_seeds: 1 if spreading each seed over several
+                             workgroups was chosen (xkp_ctx_set_seed_width), else 0           */
 } xkp_tuning;
 
 /*
@@ -415,8 +416,8 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
 /*
  * Launch autotuner for seed calls: times xkp_seed_build on the given seeds (one representative
  * timestep) for each kernel variant covering them and each workgroup count per compute unit,
- * then each seed spread over several workgroups (xkp_ctx_set_seed_width with 1, 2 and 4 rows
- * per thread, where that gives a seed at least two workgroups), five timed calls each after one
+ * then each seed spread over several workgroups (xkp_ctx_set_seed_width 1, where that gives a
+ * seed at least two workgroups), five timed calls each after one
  * untimed call, and keeps the fastest candidate whose every seed converged; the choice is stored
  * in the context (meant for a context
  * that serves seed calls only: a seed is one workgroup on the chain's critical path, whose best

@@ -20,13 +20,11 @@ struct xkp_ctx {
     int cus;            // compute units of the device
     int per_cu;         // workgroups per compute unit used for the grid (autotuned)
     int variant;        // kernel variant (workgroup size) of the solve launches (autotuned)
-    // seeds spread over several workgroups (xkp_ctx_set_seed_width): rows per thread (0: one
-    // workgroup per seed), workgroups per seed at max_n, exchange areas and later-cycle rows
+    // seeds spread over several workgroups (xkp_ctx_set_seed_width): on (1) or off (0),
+    // workgroups per seed at max_n, seeds per call, exchange areas
     int wide_R, wide_gmax, wide_cap;
     unsigned char *xch;
     size_t xch_stride;
-    double *mws;
-    size_t mws_stride;
 };
 
 namespace {
@@ -203,7 +201,6 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t f = hipFree(ctx->ws);
     hipError_t q = hipFree(ctx->queue);
     if (ctx->xch) hipFree(ctx->xch);
-    if (ctx->mws) hipFree(ctx->mws);
     delete ctx;
     return (e == hipSuccess && f == hipSuccess && q == hipSuccess) ? XKP_OK : XKP_EDEVICE;
 }
@@ -222,9 +219,7 @@ xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu) {
 }
 
 xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread) {
-    if (!ctx || (rows_per_thread != 0 && rows_per_thread != 1 && rows_per_thread != 2 &&
-                 rows_per_thread != 4))
-        return XKP_EINVAL;
+    if (!ctx || (rows_per_thread != 0 && rows_per_thread != 1)) return XKP_EINVAL;
     if (rows_per_thread == 0) {
         ctx->wide_R = 0;
         return XKP_OK;
@@ -232,29 +227,24 @@ xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread) {
     int h = 1;
     while (h * h < ctx->max_n) ++h;
     if (h > 128 || ctx->max_m > 64) return XKP_EUNSUPPORTED;
-    const int nb = 512 * rows_per_thread;
+    const int nb = xkp::wide::rows_per_block();
     const int gmax = (ctx->max_n + nb - 1) / nb;
     const int cap = ctx->max_batch < 64 ? ctx->max_batch : 64;
+    if (ctx->xch && ctx->wide_gmax == gmax && ctx->wide_cap == cap) {
+        ctx->wide_R = 1;
+        return XKP_OK;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return XKP_EDEVICE;
     if (ctx->xch) hipFree(ctx->xch);
-    if (ctx->mws) hipFree(ctx->mws);
     ctx->xch = nullptr;
-    ctx->mws = nullptr;
     ctx->wide_R = 0;
     const size_t xs = xkp::wide::xch_bytes(gmax);
-    const size_t ms = (size_t)(ctx->max_m + 1) * nb;
     if (hipMalloc((void **)&ctx->xch, xs * cap) != hipSuccess) return XKP_ENOMEM;
-    if (hipMalloc((void **)&ctx->mws, sizeof(double) * ms * gmax * cap) != hipSuccess) {
-        hipFree(ctx->xch);
-        ctx->xch = nullptr;
-        return XKP_ENOMEM;
-    }
     ctx->xch_stride = xs;
-    ctx->mws_stride = ms;
     ctx->wide_gmax = gmax;
     ctx->wide_cap = cap;
-    ctx->wide_R = rows_per_thread;
+    ctx->wide_R = 1;
     return XKP_OK;
 }
 
@@ -273,10 +263,9 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     if (n_seeds == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     if (ctx->wide_R > 0 && n_seeds <= ctx->wide_cap && params->reorth == XKP_REORTH_AUTO) {
-        // each seed over ceil(n / (512 R)) workgroups; a wait gives up after two seconds
-        return from_hip(xkp::wide::launch_wide_seed(ctx->stream, ctx->wide_R, seeds, n_seeds,
-                                                    *params, bases, infos, ctx->xch,
-                                                    ctx->xch_stride, ctx->mws, ctx->mws_stride,
+        // each seed over ceil(n / 256) workgroups; a wait gives up after two seconds
+        return from_hip(xkp::wide::launch_wide_seed(ctx->stream, seeds, n_seeds, *params,
+                                                    bases, infos, ctx->xch, ctx->xch_stride,
                                                     ctx->wide_gmax, nmax, 200000000LL));
     }
     const int grid = solve_grid(ctx, n_seeds);
@@ -605,8 +594,8 @@ xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *s
         ctx->wide_R = saved_R;
         return st;
     }
-    // then each seed over several workgroups, 512 R rows each (R = 1, 2, 4), when it allows
-    // at least two of them; kept if faster with every seed converged
+    // then each seed over several workgroups (256-row blocks) when that gives it at least
+    // two; kept if faster with every seed converged
     int h = 1;
     while (h * h < nmax) ++h;
     if (n_seeds > 64 || h > 128 || params->reorth != XKP_REORTH_AUTO) return XKP_OK;
@@ -618,8 +607,8 @@ xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *s
     }
     std::vector<xkp_info> host(n_seeds);
     int best_R = 0;
-    for (int R : {1, 2, 4}) {
-        if ((nmax + 512 * R - 1) / (512 * R) < 2) continue;
+    for (int R : {1}) {
+        if ((nmax + 255) / 256 < 2) continue;
         if (xkp_ctx_set_seed_width(ctx, R) != XKP_OK) continue;
         float ms = 0.f;
         bool ok = call(*params) == XKP_OK && hipEventRecord(e0, ctx->stream) == hipSuccess;

@@ -78,16 +78,14 @@ XKP_DECLARE_VARIANT(v512)
 XKP_DECLARE_VARIANT(v1024)
 XKP_DECLARE_VARIANT(v256)
 
-// Seeds spread over several workgroups (xkp_wide.hip): R rows per thread, 512 R rows per
-// workgroup, up to gmax workgroups per seed; xch: per-seed exchange areas of xch_stride bytes
-// (xch_bytes(gmax)); mws: per-workgroup basis rows of later cycles, mws_stride doubles each.
+// Seeds spread over several workgroups (xkp_wide.hip): blocks of rows_per_block() rows, up to
+// gmax workgroups per seed; xch: per-seed exchange areas of xch_stride bytes (xch_bytes(gmax)).
 namespace wide {
 size_t xch_bytes(int gmax);
-size_t lds_bytes(int R);
-hipError_t launch_wide_seed(hipStream_t st, int R, const xkp_system *sys, int nsys,
-                            xkp_params P, void *const *keep_bases, xkp_info *infos,
-                            unsigned char *xch, size_t xch_stride, double *mws,
-                            size_t mws_stride, int gmax, int nmax, long long limit);
+int rows_per_block();
+hipError_t launch_wide_seed(hipStream_t st, const xkp_system *sys, int nsys, xkp_params P,
+                            void *const *keep_bases, xkp_info *infos, unsigned char *xch,
+                            size_t xch_stride, int gmax, int nmax, long long limit);
 }  // namespace wide
 
 // Score and probability-flow embedding (xkp_epilogue.hip).

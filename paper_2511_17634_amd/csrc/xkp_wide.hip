@@ -2,15 +2,16 @@
 //
 // A seed is one system per timestep on the projected chain's critical path (Section 3, Phase 1:
 // every target of the timestep waits for its basis), so one workgroup per seed leaves the chip
-// idle while it runs.  Here each seed is split into G contiguous row blocks of NB = 512 R rows,
-// one workgroup per block (thread t owns rows t, t + 512, ... of its block), all G on one XCD
-// (workgroup ids congruent mod 8) so that their exchanges stay in one L2.  Per Arnoldi step:
+// idle while it runs.  Here each seed is split into G = ceil(n / 256) contiguous row blocks,
+// one workgroup of 256 threads per block, thread t owning row p = 256 g + t; the block keeps its
+// rows of every basis vector of the current cycle in LDS, so the Gram-Schmidt passes read no
+// device memory.  Per Arnoldi step:
 //   operator   w = A v_j on the owned rows; the neighbours H rows away come from the adjacent
-//              blocks' boundary rows (exchanged), the rest from the block's own LDS copy
-//   Gram-Schmidt  two classical passes (CGS2): pass k forms the owned rows' share of V^T w
-//              (and of ||w||^2), the G shares are exchanged and summed in block order (the same
-//              order in every workgroup, so every workgroup holds bitwise the same sums and takes
-//              the same decisions), w -= V h; ||w2||^2 = ||w1||^2 - ||h2||^2
+//              blocks' boundary rows (exchanged), the rest from the block's own LDS vector
+//   Gram-Schmidt  two classical passes (CGS2): pass k forms the block's share of V^T w (and of
+//              ||w||^2), the G shares are exchanged and summed in block order (the same order in
+//              every workgroup, so every workgroup holds bitwise the same sums and takes the
+//              same decisions), w -= V h; ||w2||^2 = ||w1||^2 - ||h2||^2
 //   then       v_{j+1} = w2 / ||w2|| on the owned rows, its boundary rows exchanged for the next
 //              operator application; Givens rotations and the Hessenberg column computed
 //              identically by every workgroup
@@ -23,92 +24,114 @@
 // until G arrivals of this round are counted; readers use device-coherent loads.  Exchange
 // buffers alternate between rounds.  Every wait is bounded in time: a workgroup whose partners
 // do not arrive (they must all be resident at once) gives up, and the seed gets XKP_EDEVICE.
-#define XKP_NT 512
+// A seed's workgroups share one XCD (ids congruent mod 8) when G <= 32, so that their exchanges
+// stay in one L2; larger seeds spread over the XCDs.
+#define XKP_NT 256
 #define XKP_VARIANT wdev
 #include "xkp_device.h"
 #include "xkp_internal.h"
+
+#include <mutex>
+#include <vector>
 
 namespace xkp {
 namespace wide {
 
 using namespace xkp::wdev;
 
-constexpr int NT = 512, NW = NT / 64;
+constexpr int NT = 256, NW = NT / 64;
 constexpr int HM = 128;                    // largest grid side (halo rows on each side)
 constexpr int kMM = 64;                    // largest restart length
 constexpr int kWV = kMM + 4;               // values of one exchange (j + 2 <= kMM + 1)
 
-// Per-seed exchange area (bytes): the arrival counter, then two rounds of per-workgroup value
-// slots, then two rounds of per-workgroup boundary rows (low H rows, high H rows).
-__host__ __device__ inline size_t xch_part_off() { return 256; }
-__host__ __device__ inline size_t xch_bnd_off(int gmax) {
-    return xch_part_off() + sizeof(double) * 2 * (size_t)gmax * kWV;
+// Per-seed exchange area: two rounds of per-workgroup value slots, then two rounds of
+// per-workgroup boundary rows (low H rows, high H rows).  Every published double is a 16-byte
+// unit {low word, tag, high word, tag} written with one store: a reader that sees both tags
+// equal to the round it waits for has the value (no separate flag, no counter), and a launch
+// starts by setting every tag to 0xFFFFFFFF, a round no solve reaches.
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kAux = 16;   // cache policy sc1: device-coherent store / load
+__host__ __device__ inline size_t xch_units(int gmax) {
+    return 2 * (size_t)gmax * kWV + 2 * (size_t)gmax * 2 * HM;
 }
-size_t xch_bytes(int gmax) {
-    return (xch_bnd_off(gmax) + sizeof(double) * 2 * (size_t)gmax * 2 * HM + 255) & ~(size_t)255;
-}
-
-__device__ __forceinline__ void pub(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double get(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+size_t xch_bytes(int gmax) { return (16 * xch_units(gmax) + 255) & ~(size_t)255; }
+int rows_per_block() { return NT; }
 
 struct Wide {
-    unsigned *cnt;
-    double *part, *bnd;
-    int gmax, G, g, H, nb, n;
+    __amdgpu_buffer_rsrc_t rs;   // the seed's exchange area
+    int gmax, G, g;
     unsigned round;
     long long limit;
     int *abort_lds;
-    double *red, *tot, *vbuf;   // LDS
+    double *red, *tot;   // LDS
 
-    // Round of exchange: publishes nothing itself (callers stored with pub()), orders every
-    // thread's stores, counts this workgroup's arrival and waits for the others.
-    __device__ bool sync() {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned target = (round + 1u) * (unsigned)G;
-            const long long t0 = __builtin_amdgcn_s_memrealtime();
-            while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
-                    *abort_lds = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+    __device__ __forceinline__ unsigned part_unit(unsigned rnd, int gg, int v) const {
+        return (unsigned)(((size_t)(rnd & 1) * gmax + gg) * kWV + v);
+    }
+    __device__ __forceinline__ unsigned bnd_unit(unsigned rnd, int gg, int side, int t) const {
+        return (unsigned)(2 * (size_t)gmax * kWV + (((size_t)(rnd & 1) * gmax + gg) * 2 + side) * HM + t);
+    }
+    __device__ __forceinline__ void put(unsigned unit, double v) const {
+        const unsigned lo = __double2loint(v), hi = __double2hiint(v);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4_t{lo, round, hi, round}, rs, unit * 16u, 0,
+                                               kAux);
+    }
+    __device__ __forceinline__ u32x4_t load(unsigned unit) const {
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, unit * 16u, 0, kAux);
+    }
+    static __device__ __forceinline__ bool ready(u32x4_t u, unsigned rnd) {
+        return u[1] == rnd && u[3] == rnd;
+    }
+    static __device__ __forceinline__ double value(u32x4_t u) {
+        return __hiloint2double((int)u[2], (int)u[0]);
+    }
+    // the unit's value once it carries round rnd; false (and the workgroup told) on time-out.
+    // The pause between polls doubles up to about 2 us, so that workgroups waiting long (for
+    // partners not yet resident) do not flood the memory system with polls.
+    __device__ __forceinline__ bool wait(unsigned unit, unsigned rnd, u32x4_t &u) const {
+        if (ready(u, rnd)) return true;
+        const long long t0 = __builtin_amdgcn_s_memrealtime();
+        int pause = 1;
+        for (;;) {
+            if (*(volatile int *)abort_lds) return false;   // another wait already gave up
+            u = load(unit);
+            if (ready(u, rnd)) return true;
+            if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                *(volatile int *)abort_lds = 1;
+                return false;
             }
+            for (int i = 0; i < pause; ++i) __builtin_amdgcn_s_sleep(1);
+            if (pause < 64) pause *= 2;
         }
+    }
+    // ends a round: every thread has its data; false if a wait timed out anywhere
+    __device__ __forceinline__ bool end_round() {
         __syncthreads();
         ++round;
         return *abort_lds == 0;
     }
-    __device__ double *my_part() { return part + ((size_t)(round & 1) * gmax + g) * kWV; }
-    __device__ const double *part_of(int gg) const {
-        return part + ((size_t)(round & 1) * gmax + gg) * kWV;
-    }
-    __device__ double *bnd_of(unsigned rnd, int gg, int side) const {
-        return bnd + (((size_t)(rnd & 1) * gmax + gg) * 2 + side) * HM;
-    }
-
     // The workgroup's share of nv values, already summed per wave in red[v * NW + wave], is
-    // published; after the exchange tot[v] holds the sums over the G blocks in block order.
-    __device__ bool reduce(int nv) {
+    // published; then tot[v] = the sums over the G blocks in block order (the G shares loaded
+    // sixteen at a time).  Callers may publish other units of this round before calling.
+    __device__ __forceinline__ bool reduce(int nv) {
         __syncthreads();
-        double *mp = my_part();
-        for (int v = threadIdx.x; v < nv; v += NT) pub(mp + v, tree_sum<NW>(red + v * NW));
         const unsigned rnd = round;
-        if (!sync()) return false;
+        for (int v = threadIdx.x; v < nv; v += NT) put(part_unit(rnd, g, v), tree_sum<NW>(red + v * NW));
         for (int v = threadIdx.x; v < nv; v += NT) {
             double t = 0.0;
-            for (int gg = 0; gg < G; ++gg)
-                t += get(part + ((size_t)(rnd & 1) * gmax + gg) * kWV + v);
+            for (int g0 = 0; g0 < G; g0 += 16) {
+                u32x4_t sh[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    sh[e] = g0 + e < G ? load(part_unit(rnd, g0 + e, v)) : u32x4_t{0, 0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (g0 + e < G && wait(part_unit(rnd, g0 + e, v), rnd, sh[e]))
+                        t += value(sh[e]);
+            }
             tot[v] = t;
         }
-        __syncthreads();
-        return true;
+        return end_round();
     }
 };
 
@@ -128,21 +151,37 @@ __device__ __forceinline__ void wave_put4(double a, double b, double c, double d
     }
 }
 
-template <int R>
+// LDS layout (doubles), mmax = the largest cycle length of the call:
+//   Vl    (mmax + 1) x NT: the block's rows of the cycle's basis vectors, column-major
+//   vbuf  NT + 2 HM: the operator's input, owned rows at HM + t, halos around them
+//   red   kWV x NW, tot kWV, Rp mmax (mmax + 1) / 2, cs, sn, yv mmax, gv mmax + 1, flags
+__host__ __device__ inline size_t lds_doubles(int mmax) {
+    return (size_t)(mmax + 1) * NT + NT + 2 * HM + kWV * NW + kWV +
+           (size_t)mmax * (mmax + 1) / 2 + 4 * (size_t)mmax + 1 + 2;
+}
+
 __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restrict__ sys, int nsys,
                                                        xkp_params P, void *const *keep_bases,
                                                        xkp_info *infos, unsigned char *xch,
-                                                       size_t xch_stride, double *mws,
-                                                       size_t mws_stride, int gmax, int nmax,
-                                                       long long limit) {
-    constexpr int NB = NT * R;
+                                                       size_t xch_stride, int gmax, int packed,
+                                                       int nmax, long long limit) {
     const int tid = threadIdx.x;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int si = xcd + 8 * (slot / gmax), g = slot % gmax;
+    // seed si, block g: packed, a seed's blocks share an XCD (ids congruent mod 8)
+    int si, g;
+    if (packed) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        si = xcd + 8 * (slot / gmax);
+        g = slot % gmax;
+    } else {
+        si = blockIdx.x / gmax;
+        g = blockIdx.x % gmax;
+    }
     if (si >= nsys) return;
     const xkp_system s = sys[si];
     xkp_info *info = infos + si;
     const int H = s.H;
+    const int m = P.m, mpol = P.polish_m > 0 ? P.polish_m : P.m;
+    const int mmax = m > mpol ? m : mpol;
     const bool ok = H > 0 && H <= HM && (long)H * H <= nmax && s.mt && s.b && s.x &&
                     s.dt > 0.0 && keep_bases[si] != nullptr && P.m >= 1 && P.m <= kMM &&
                     P.polish_m >= 0 && P.polish_m <= kMM;
@@ -150,86 +189,91 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
         if (g == 0 && tid == 0) info->status = XKP_EINVAL;
         return;
     }
-    const int n = H * H, G = (n + NB - 1) / NB;
+    const int n = H * H, G = (n + NT - 1) / NT;
     if (g >= G) return;
 
     extern __shared__ __attribute__((aligned(16))) double lds[];
-    double *vbuf = lds;                               // [HM | NB owned | HM]
-    double *red = vbuf + NB + 2 * HM;                 // kWV x NW
-    double *tot = red + kWV * NW;                     // kWV
-    double *Rp = tot + kWV;                           // kMM (kMM + 1) / 2
-    double *cs = Rp + kMM * (kMM + 1) / 2, *sn = cs + kMM, *gv = sn + kMM, *yv = gv + kMM + 1;
-    int *flags = (int *)(yv + kMM);                   // [0] abort
+    double *Vl = lds;
+    double *vbuf = Vl + (size_t)(mmax + 1) * NT;
+    double *red = vbuf + NT + 2 * HM;
+    double *tot = red + kWV * NW;
+    double *Rp = tot + kWV;
+    double *cs = Rp + (size_t)mmax * (mmax + 1) / 2, *sn = cs + mmax, *yv = sn + mmax;
+    double *gv = yv + mmax;
+    int *flags = (int *)(gv + mmax + 1);
 
     if (tid == 0) flags[0] = 0;
-    for (int t = tid; t < NB + 2 * HM; t += NT) vbuf[t] = 0.0;
+    for (int t = tid; t < NT + 2 * HM; t += NT) vbuf[t] = 0.0;
     __syncthreads();
     unsigned char *xs = xch + (size_t)si * xch_stride;
-    Wide X{(unsigned *)xs, (double *)(xs + xch_part_off()), (double *)(xs + xch_bnd_off(gmax)),
-           gmax, G, g, H, NB, n, 0u, limit, flags, red, tot, vbuf};
+    Wide X{__builtin_amdgcn_make_buffer_rsrc(xs, (short)0, (int)xch_stride, 0x00020000), gmax,
+           G, g, 0u, limit, flags, red, tot};
 
-    // rows owned: local r_q = tid + NT q, global p_q = g NB + r_q; the last block's rows at or
-    // past n are zero and are never read from a basis column (the kept basis ends at row n)
-    const int base = g * NB;
-    bool own[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) own[q] = base + tid + NT * q < n;
+    // this thread's row p = g NT + tid; rows at or past n (last block) are zero throughout
+    const int base = g * NT, p = base + tid;
+    const bool own = p < n;
     const OpConst o = op_const(s);
-    double cE[R], cW[R], cN[R], cS[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int p = base + tid + NT * q;
-        double e = 0.0, w = 0.0, nn = 0.0, ss = 0.0;
-        if (p < n) {
-            const int i = p / H, j = p - (p / H) * H;
-            const double mE = (i + 1 < H) ? s.mt[p + H] : 0.0;
-            const double mW = (i > 0) ? s.mt[p - H] : 0.0;
-            const double mN = (j + 1 < H) ? s.mt[p + 1] : 0.0;
-            const double mS = (j > 0) ? s.mt[p - 1] : 0.0;
-            const double fxp = s.fx ? s.fx[p] : 0.0;
-            const double fyp = s.fy ? s.fy[p] : 0.0;
-            const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
-            const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
-            e = (i + 1 < H) ? -o.a + ex : 0.0;
-            w = (i > 0) ? -o.a - ex : 0.0;
-            nn = (j + 1 < H) ? -o.a + ey : 0.0;
-            ss = (j > 0) ? -o.a - ey : 0.0;
-        }
-        cE[q] = e;
-        cW[q] = w;
-        cN[q] = nn;
-        cS[q] = ss;
+    double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
+    if (own) {
+        const int i = p / H, j = p - (p / H) * H;
+        const double mE = (i + 1 < H) ? s.mt[p + H] : 0.0;
+        const double mW = (i > 0) ? s.mt[p - H] : 0.0;
+        const double mN = (j + 1 < H) ? s.mt[p + 1] : 0.0;
+        const double mS = (j > 0) ? s.mt[p - 1] : 0.0;
+        const double fxp = s.fx ? s.fx[p] : 0.0;
+        const double fyp = s.fy ? s.fy[p] : 0.0;
+        const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
+        const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
+        cE = (i + 1 < H) ? -o.a + ex : 0.0;
+        cW = (i > 0) ? -o.a - ex : 0.0;
+        cN = (j + 1 < H) ? -o.a + ey : 0.0;
+        cS = (j > 0) ? -o.a - ey : 0.0;
     }
-    // y = A u for the owned rows, u in vbuf (owned rows at HM + r, halos around them)
-    auto apply = [&](double (&y)[R]) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const double *u = vbuf + HM + tid + NT * q;
-            y[q] = o.cd * u[0] + cE[q] * u[H] + cW[q] * u[-H] + cN[q] * u[1] + cS[q] * u[-1];
-        }
+    // y = A u for this row, u in vbuf
+    auto apply = [&]() {
+        const double *u = vbuf + HM + tid;
+        return o.cd * u[0] + cE * u[H] + cW * u[-H] + cN * u[1] + cS * u[-1];
     };
-    auto put_own = [&](const double (&v)[R]) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) vbuf[HM + tid + NT * q] = v[q];
+    // this row's value, if it is a boundary row, to the neighbours (this round)
+    auto publish_bnd = [&](double v) {
+        if (tid < H) X.put(X.bnd_unit(X.round, g, 0, tid), v);
+        if (tid >= NT - H) X.put(X.bnd_unit(X.round, g, 1, tid - (NT - H)), v);
     };
-    // boundary rows of the owned block (low H rows, high H rows) published for the neighbours
-    auto pub_bnd = [&](const double (&v)[R]) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int r = tid + NT * q;
-            if (r < H) pub(X.bnd_of(X.round, g, 0) + r, v[q]);
-            if (r >= NB - H) pub(X.bnd_of(X.round, g, 1) + (r - (NB - H)), v[q]);
-        }
-    };
-    // after the exchange of round rnd: the halos from the neighbours' boundary rows
-    auto get_halo = [&](unsigned rnd) {
+    // the halos from the neighbours' boundary rows of this round (before end_round)
+    auto get_halo = [&]() {
+        const unsigned rnd = X.round;
         for (int t = tid; t < H; t += NT) {
-            vbuf[HM - H + t] = g > 0 ? get(X.bnd_of(rnd, g - 1, 1) + t) : 0.0;
-            vbuf[HM + NB + t] = g + 1 < G ? get(X.bnd_of(rnd, g + 1, 0) + t) : 0.0;
+            double lo = 0.0, hi = 0.0;
+            u32x4_t u0 = g > 0 ? X.load(X.bnd_unit(rnd, g - 1, 1, t)) : u32x4_t{0, 0, 0, 0};
+            u32x4_t u1 = g + 1 < G ? X.load(X.bnd_unit(rnd, g + 1, 0, t)) : u32x4_t{0, 0, 0, 0};
+            if (g > 0 && X.wait(X.bnd_unit(rnd, g - 1, 1, t), rnd, u0)) lo = Wide::value(u0);
+            if (g + 1 < G && X.wait(X.bnd_unit(rnd, g + 1, 0, t), rnd, u1)) hi = Wide::value(u1);
+            vbuf[HM - H + t] = lo;
+            vbuf[HM + NT + t] = hi;
         }
+    };
+    // this row into the LDS vector and the neighbours' halos, theirs into ours: one round
+    auto exchange_row = [&](double v) -> bool {
+        vbuf[HM + tid] = v;
+        publish_bnd(v);
+        get_halo();
+        return X.end_round();
+    };
+    // one classical pass over columns 0..j: the block's shares of V^T w and ||w||^2, summed
+    // over the blocks into tot[0..j+1]
+    auto pass = [&](int j, double w) -> bool {
+        for (int c0 = 0; c0 <= j + 1; c0 += 4) {
+            double d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = c0 + e;
+                d[e] = c <= j ? Vl[c * NT + tid] * w : (c == j + 1 ? w * w : 0.0);
+            }
+            wave_put4(d[0], d[1], d[2], d[3], red, c0, j + 2);
+        }
+        return X.reduce(j + 2);
     };
 
-    const int m = P.m, mpol = P.polish_m > 0 ? P.polish_m : P.m;
     xkp_basis_header *hdr = (xkp_basis_header *)keep_bases[si];
     const int ldv = (n + 8) & ~7;
     double *Vk = (double *)((char *)hdr + 256);
@@ -237,54 +281,43 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     unsigned short *Vb = P.precision == XKP_MIXED
                              ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
                              : nullptr;
-    double *Vw = mws + (size_t)(si * gmax + g) * mws_stride;   // later cycles: own rows, NB each
+    auto to_bf16 = [](double v) {
+        const unsigned u = __builtin_bit_cast(unsigned, (float)v);
+        return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    };
     if (g == 0)
         for (int t = tid; t < (m + 1) * m; t += NT) Hb[t] = 0.0;
 
-    double b[R], x[R], w[R], r[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int p = base + tid + NT * q;
-        b[q] = p < n ? s.b[p] : 0.0;
-        x[q] = (p < n && s.x0) ? s.x0[p] : 0.0;
-    }
+    const double b = own ? s.b[p] : 0.0;
+    double x = (own && s.x0) ? s.x0[p] : 0.0;
     // x halo for the first residual: straight from the input x0 (or zero)
     for (int t = tid; t < H; t += NT) {
-        const int pl = base - H + t, ph = base + NB + t;
+        const int pl = base - H + t, ph = base + NT + t;
         vbuf[HM - H + t] = (s.x0 && pl >= 0 && pl < n) ? s.x0[pl] : 0.0;
-        vbuf[HM + NB + t] = (s.x0 && ph < n) ? s.x0[ph] : 0.0;
+        vbuf[HM + NT + t] = (s.x0 && ph < n) ? s.x0[ph] : 0.0;
     }
-    put_own(x);
+    vbuf[HM + tid] = x;
     __syncthreads();
 
     int iters = 0, restarts = 0, kfirst = 0, status = XKP_OK;
-    double res_est = 0.0, res_true = 0.0, beta_first = 0.0, bnorm = 0.0, beta = 0.0;
+    double res_est = 0.0, res_true = 0.0, beta_first = 0.0, bnorm = 0.0, beta = 0.0, r = 0.0;
     bool alive = true, first = true;
-    // r = b - A x, its norm (and ||b|| on the first call) and its boundary rows: one exchange
+    // r = b - A x (x in the LDS vector with its halos), ||r|| (and ||b|| on the first call),
+    // r's boundary rows exchanged into the halos: one exchange
     auto residual = [&](bool with_b) -> bool {
-        apply(w);
-        double rr = 0.0, bb = 0.0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            r[q] = b[q] - w[q];
-            rr += r[q] * r[q];
-            bb += b[q] * b[q];
-        }
-        wave_put4(rr, bb, 0.0, 0.0, red, 0, 2);
-        pub_bnd(r);
-        const unsigned rnd = X.round;
+        r = own ? b - apply() : 0.0;
+        wave_put4(r * r, b * b, 0.0, 0.0, red, 0, 2);
+        // r's boundary rows in the same round as the norms
+        __syncthreads();   // every thread has read the LDS vector (x) before the halos change
+        publish_bnd(r);
+        get_halo();
         if (!X.reduce(2)) return false;
-        get_halo(rnd);
         beta = sqrt(tot[0]);
         if (with_b) bnorm = sqrt(tot[1]);
         return true;
     };
     alive = residual(true);
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int p = base + tid + NT * q;
-        if (p < n) s.x[p] = x[q];
-    }
+    if (own) s.x[p] = x;
     // data that are not finite (NaN or Inf in m~, f, b or x0) cannot be solved
     if (alive && (!isfinite(beta) || !isfinite(bnorm))) status = XKP_EINVAL;
     if (alive && status == XKP_OK && bnorm > 0.0) {
@@ -292,122 +325,61 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
         while (alive && beta > P.tol * bnorm) {
             const bool keep = first;
             const int mc = keep ? m : mpol;
-            double *V = keep ? Vk : Vw;
-            const size_t ld = keep ? (size_t)ldv : (size_t)NB;
-            const int coff = keep ? base : 0;   // row offset of the owned block in a column
-            auto col = [&](int c) { return V + (size_t)c * ld + coff; };
-            // v_0 = r / beta (owned rows and halos)
+            // v_0 = r / beta (this row and the halos)
             const double rb0 = 1.0 / beta;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                w[q] = r[q] * rb0;
-                const int p = base + tid + NT * q;
-                if (p < n || !keep) col(0)[tid + NT * q] = (p < n) ? w[q] : 0.0;
-            }
-            if (keep) {
-                if (g + 1 == G)
-                    for (int p = n + tid; p < ldv; p += NT) Vk[p] = 0.0;
-                beta_first = beta;
-            }
-            put_own(w);
+            double w = own ? r * rb0 : 0.0;
+            vbuf[HM + tid] = w;
             for (int t = tid; t < H; t += NT) {
                 vbuf[HM - H + t] *= rb0;
-                vbuf[HM + NB + t] *= rb0;
+                vbuf[HM + NT + t] *= rb0;
             }
-            if (keep && Vb) {
-#pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int p = base + tid + NT * q;
-                    if (p < n) {
-                        const unsigned u = __builtin_bit_cast(unsigned, (float)w[q]);
-                        Vb[p] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-                    }
+            Vl[tid] = w;
+            if (keep) {
+                if (own) {
+                    Vk[p] = w;
+                    if (Vb) Vb[p] = to_bf16(w);
                 }
+                if (g + 1 == G)
+                    for (int q = n + tid; q < ldv; q += NT) Vk[q] = 0.0;
+                beta_first = beta;
             }
             __syncthreads();
             double gcur = beta;
             int kk = 0;
             for (int j = 0; j < mc; ++j) {
-                apply(w);
+                w = apply();
                 ++iters;
-                // pass 1: shares of V_{j+1}^T w and ||w||^2
-                for (int c0 = 0; c0 <= j + 1; c0 += 4) {
-                    double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int c = c0 + e;
-                        if (c <= j) {
-                            const double *vc = col(c);
-#pragma unroll
-                            for (int q = 0; q < R; ++q) d[e] += (own[q] ? vc[tid + NT * q] : 0.0) * w[q];
-                        } else if (c == j + 1) {
-#pragma unroll
-                            for (int q = 0; q < R; ++q) d[e] += w[q] * w[q];
-                        }
-                    }
-                    wave_put4(d[0], d[1], d[2], d[3], red, c0, j + 2);
-                }
-                if (!(alive = X.reduce(j + 2))) break;
+                if (!(alive = pass(j, w))) break;
                 const double wn0 = sqrt(tot[j + 1]);
-                for (int c = 0; c <= j; ++c) {
-                    const double hc = tot[c];
-                    const double *vc = col(c);
-#pragma unroll
-                    for (int q = 0; q < R; ++q) w[q] -= hc * (own[q] ? vc[tid + NT * q] : 0.0);
-                }
-                // keep pass 1's coefficients: tot is overwritten by pass 2
+                for (int c = 0; c <= j; ++c) w -= tot[c] * Vl[c * NT + tid];
+                // pass 1's coefficients wait in yv while pass 2 reuses tot
                 for (int c = tid; c <= j; c += NT) yv[c] = tot[c];
-                // pass 2: shares of V_{j+1}^T w1 and ||w1||^2
-                for (int c0 = 0; c0 <= j + 1; c0 += 4) {
-                    double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int c = c0 + e;
-                        if (c <= j) {
-                            const double *vc = col(c);
-#pragma unroll
-                            for (int q = 0; q < R; ++q) d[e] += (own[q] ? vc[tid + NT * q] : 0.0) * w[q];
-                        } else if (c == j + 1) {
-#pragma unroll
-                            for (int q = 0; q < R; ++q) d[e] += w[q] * w[q];
-                        }
-                    }
-                    wave_put4(d[0], d[1], d[2], d[3], red, c0, j + 2);
-                }
-                if (!(alive = X.reduce(j + 2))) break;
+                if (!(alive = pass(j, w))) break;
                 double c2 = 0.0;
                 for (int c = 0; c <= j; ++c) {
                     const double hc = tot[c];
                     c2 += hc * hc;
-                    const double *vc = col(c);
-#pragma unroll
-                    for (int q = 0; q < R; ++q) w[q] -= hc * (own[q] ? vc[tid + NT * q] : 0.0);
+                    w -= hc * Vl[c * NT + tid];
                 }
                 const double hn = sqrt(fmax(tot[j + 1] - c2, 0.0));
                 const bool brk = !(hn > 1e-14 * wn0);
                 const double rhn = brk ? 0.0 : 1.0 / hn;
-#pragma unroll
-                for (int q = 0; q < R; ++q) w[q] = w[q] * rhn;
-                // v_{j+1}: owned rows into the basis, boundary rows to the neighbours
-                double *vn = col(j + 1);
-#pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int p = base + tid + NT * q;
-                    if (p < n || !keep) vn[tid + NT * q] = (p < n) ? w[q] : 0.0;
-                    if (keep && Vb && p < n) {
-                        const unsigned u = __builtin_bit_cast(unsigned, (float)w[q]);
-                        Vb[(size_t)(j + 1) * ldv + p] =
-                            (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+                w = own ? w * rhn : 0.0;
+                Vl[(j + 1) * NT + tid] = w;
+                if (keep) {
+                    if (own) {
+                        Vk[(size_t)(j + 1) * ldv + p] = w;
+                        if (Vb) Vb[(size_t)(j + 1) * ldv + p] = to_bf16(w);
                     }
+                    if (g + 1 == G)
+                        for (int q = n + tid; q < ldv; q += NT)
+                            Vk[(size_t)(j + 1) * ldv + q] = 0.0;
+                    // unrotated Hessenberg column j (its other entries are zero), by block 0
+                    if (g == 0)
+                        for (int rr = tid; rr <= j + 1; rr += NT)
+                            Hb[(size_t)j * (m + 1) + rr] = rr <= j ? yv[rr] + tot[rr] : hn;
                 }
-                if (keep && g + 1 == G)
-                    for (int p = n + tid; p < ldv; p += NT) Vk[(size_t)(j + 1) * ldv + p] = 0.0;
-                // Hessenberg column j (both passes) and its Givens rotations, the same in every
-                // workgroup; the kept cycle's unrotated column is written by block 0
-                if (keep && g == 0)
-                    for (int rr = tid; rr <= m; rr += NT)
-                        Hb[(size_t)j * (m + 1) + rr] =
-                            rr <= j ? yv[rr] + tot[rr] : (rr == j + 1 ? hn : 0.0);
+                // Givens rotations of column j (every thread holds the same values)
                 double t = yv[0] + tot[0];
                 for (int i = 1; i <= j; ++i) {
                     const double hi = yv[i] + tot[i];
@@ -419,9 +391,8 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                 const double den = sqrt(t * t + hn * hn);
                 const double rden = 1.0 / den;
                 const double cj = t * rden, sj = hn * rden;
-                pub_bnd(w);
-                const unsigned rnd = X.round;
-                __syncthreads();   // every thread has read cs, sn, yv, tot
+                // every thread has read yv, cs and sn before they change
+                __syncthreads();
                 if (tid == 0) {
                     Rp[(j * (j + 1)) / 2 + j] = den;
                     cs[j] = cj;
@@ -430,10 +401,8 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                 }
                 gcur = -sj * gcur;
                 kk = j + 1;
-                put_own(w);
-                if (!(alive = X.sync())) break;
-                get_halo(rnd);
-                __syncthreads();
+                // v_{j+1}'s boundary rows to the neighbours, theirs into the halos
+                if (!(alive = exchange_row(w))) break;
                 if (fabs(gcur) <= P.tol * bnorm || brk) break;
             }
             if (!alive) break;
@@ -449,28 +418,15 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                 }
             }
             __syncthreads();
-            for (int c = 0; c < kk; ++c) {
-                const double yc = yv[c];
-                const double *vc = col(c);
-#pragma unroll
-                for (int q = 0; q < R; ++q) x[q] += yc * (own[q] ? vc[tid + NT * q] : 0.0);
-            }
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int p = base + tid + NT * q;
-                if (p < n) s.x[p] = x[q];
-            }
+            for (int c = 0; c < kk; ++c) x += yv[c] * Vl[c * NT + tid];
+            if (own) s.x[p] = x;
             if (first) {
                 kfirst = kk;
                 first = false;
             }
             // the new x's boundary rows, then the true residual in FP64
-            put_own(x);
-            pub_bnd(x);
-            const unsigned rnd = X.round;
-            if (!(alive = X.sync())) break;
-            get_halo(rnd);
-            __syncthreads();
+            __syncthreads();   // every thread has read yv
+            if (!(alive = exchange_row(x))) break;
             if (!(alive = residual(false))) break;
             res_true = beta / bnorm;
             if (beta <= P.tol * bnorm) break;
@@ -485,12 +441,7 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
             ++restarts;
         }
     } else if (alive && status == XKP_OK) {
-        // b = 0: x = 0
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int p = base + tid + NT * q;
-            if (p < n) s.x[p] = 0.0;
-        }
+        if (own) s.x[p] = 0.0;   // b = 0: x = 0
     }
     if (!alive) status = XKP_EDEVICE;
     if (g == 0 && tid == 0) {
@@ -514,42 +465,55 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     }
 }
 
-__global__ void clear_counters_kernel(unsigned char *xch, size_t stride, int nsys) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nsys) *(unsigned *)(xch + (size_t)i * stride) = 0u;
+// Sets every unit of the launch's exchange areas to tag 0xFFFFFFFF (no round matches it).
+__global__ void clear_exchange_kernel(unsigned char *xch, size_t bytes) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(xch, (short)0, (int)bytes, 0x00020000);
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < bytes / 16;
+         i += gridDim.x * blockDim.x)
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4_t{0u, 0xFFFFFFFFu, 0u, 0xFFFFFFFFu}, rs,
+                                               i * 16u, 0, kAux);
 }
 
-size_t lds_bytes(int R) {
-    return sizeof(double) * ((size_t)NT * R + 2 * HM + kWV * NW + kWV + kMM * (kMM + 1) / 2 +
-                             4 * kMM + 1) + 16;
+size_t lds_bytes(int mmax) { return sizeof(double) * lds_doubles(mmax) + 16; }
+
+// Raises the kernel's dynamic-LDS limit once per device (to the largest size asked for), so
+// that a launch inside a graph capture makes no attribute call.
+static hipError_t set_lds(size_t bytes) {
+    static std::mutex mu;
+    static std::vector<std::pair<int, size_t>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto &d : done)
+        if (d.first == dev) {
+            if (d.second >= bytes) return hipSuccess;
+            e = hipFuncSetAttribute((const void *)wide_seed_kernel,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e == hipSuccess) d.second = bytes;
+            return e;
+        }
+    e = hipFuncSetAttribute((const void *)wide_seed_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done.push_back({dev, bytes});
+    return e;
 }
 
-hipError_t launch_wide_seed(hipStream_t st, int R, const xkp_system *sys, int nsys,
-                            xkp_params P, void *const *keep_bases, xkp_info *infos,
-                            unsigned char *xch, size_t xch_stride, double *mws,
-                            size_t mws_stride, int gmax, int nmax, long long limit) {
-    hipLaunchKernelGGL(clear_counters_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, xch,
-                       xch_stride, nsys);
-    const dim3 grid(8 * gmax * ((nsys + 7) / 8));
-    const size_t lds = lds_bytes(R);
-    switch (R) {
-    case 1:
-        hipLaunchKernelGGL(wide_seed_kernel<1>, grid, dim3(NT), lds, st, sys, nsys, P,
-                           keep_bases, infos, xch, xch_stride, mws, mws_stride, gmax, nmax,
-                           limit);
-        break;
-    case 2:
-        hipLaunchKernelGGL(wide_seed_kernel<2>, grid, dim3(NT), lds, st, sys, nsys, P,
-                           keep_bases, infos, xch, xch_stride, mws, mws_stride, gmax, nmax,
-                           limit);
-        break;
-    case 4:
-        hipLaunchKernelGGL(wide_seed_kernel<4>, grid, dim3(NT), lds, st, sys, nsys, P,
-                           keep_bases, infos, xch, xch_stride, mws, mws_stride, gmax, nmax,
-                           limit);
-        break;
-    default: return hipErrorInvalidValue;
-    }
+hipError_t launch_wide_seed(hipStream_t st, const xkp_system *sys, int nsys, xkp_params P,
+                            void *const *keep_bases, xkp_info *infos, unsigned char *xch,
+                            size_t xch_stride, int gmax, int nmax, long long limit) {
+    const int mpol = P.polish_m > 0 ? P.polish_m : P.m;
+    const size_t lds = lds_bytes(P.m > mpol ? P.m : mpol);
+    hipError_t e = set_lds(lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(clear_exchange_kernel, dim3(256), dim3(256), 0, st, xch,
+                       xch_stride * nsys);
+    // up to 32 workgroups of a seed fit one XCD (one per compute unit)
+    const int packed = gmax <= 32 ? 1 : 0;
+    const dim3 grid(packed ? 8 * gmax * ((nsys + 7) / 8) : gmax * nsys);
+    hipLaunchKernelGGL(wide_seed_kernel, grid, dim3(NT), lds, st, sys, nsys, P, keep_bases,
+                       infos, xch, xch_stride, gmax, packed, nmax, limit);
     return hipGetLastError();
 }
 

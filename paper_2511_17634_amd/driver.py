@@ -239,6 +239,10 @@ class Batch:
             cs = self.ctx_seed
             if self.pipeline and self.step_no >= 2:
                 self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
+            if self.pipeline and self.step_no >= 1 and self.ctx_seed_rows() > 0:
+                # a seed spread over several workgroups needs them resident together: it runs
+                # after the previous target call rather than beside it
+                self.s_seed.wait_event(self.ev_tgt[1 - par])
             cs.build_rhs(self.seed_desc[par], self.S)
             if seed_events is not None:
                 seed_events[0].record(cs.stream)
@@ -357,9 +361,8 @@ class Batch:
         return t
 
     def ctx_seed_rows(self):
-        """Rows per thread of the seed context's spread-out seed solve (0: one workgroup)."""
-        t = getattr(self, "seed_tuning", None)
-        return 0 if t is None else int(t.seed_rows)
+        """1 if the seed context spreads each seed over several workgroups, else 0."""
+        return int(getattr(self.ctx_seed, "seed_width", 0))
 
     def _join(self):
         """Order the current stream after everything enqueued on the chain's streams."""

@@ -213,16 +213,18 @@ class Context:
                                   max_n, max_m, max_batch), "xkp_ctx_create")
         self._h = h
         self.max_n, self.max_m, self.max_batch = max_n, max_m, max_batch
+        self.seed_width = 0        # 1 once seed calls are spread over several workgroups
 
     def set_launch(self, waves, wg_per_cu=1):
         """Workgroup size (8 or 16 wave64s) and workgroups per compute unit of later solves."""
         _check(load().xkp_ctx_set_launch(self._h, waves, wg_per_cu), "xkp_ctx_set_launch")
 
     def set_seed_width(self, rows_per_thread):
-        """Later seed calls spread each seed over workgroups of 512 * rows_per_thread rows
-        (1, 2 or 4), or one workgroup per seed (0)."""
+        """Later seed calls spread each seed over workgroups of 256 rows (1), or one workgroup
+        per seed (0)."""
         _check(load().xkp_ctx_set_seed_width(self._h, rows_per_thread),
                "xkp_ctx_set_seed_width")
+        self.seed_width = int(rows_per_thread)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -301,6 +303,7 @@ class Context:
         _check(load().xkp_autotune_seeds(self._h, n_sys, _ptr(systems), _ptr(bases_ptrs),
                                          ct.byref(params), _ptr(infos), ct.byref(t)),
                "xkp_autotune_seeds")
+        self.seed_width = int(t.seed_rows)
         return t
 
     def learned_solve(self, systems, n_sys, n_bases, bases_ptrs, params, alpha, alpha_ld,
