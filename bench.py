@@ -45,12 +45,12 @@ TRAFFIC = {}
 
 
 def csrc_digest():
-    """Digest of the sources the solve kernel is built from, to tell whether stored counter
-    figures still apply."""
+    """Digest of the sources the solve and projection kernels are built from, to tell whether
+    stored counter figures still apply."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2511_17634_amd", "csrc")
-    for f in ("xkp_device.h", "xkp_internal.h", "xkp_kernels.hip"):
+    for f in ("xkp_device.h", "xkp_internal.h", "xkp_kernels.hip", "xkp_project.hip"):
         h.update(f.encode())
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
@@ -117,6 +117,63 @@ def launch_alg_bytes(ns, bids, inf, polish_m, project, warm=False, sv=8, sop=24,
                 used[bids[i]] = (ns[i], int(kd[t, i]))
             total += sum((8 + sbv) * n * k for n, k in used.values())
     return total / T
+
+
+def polish_alg_bytes(ns, inf, polish_m, sv=8, sop=24, passes=1):
+    """Algorithmic HBM bytes of one solve launch that polishes projected guesses made by the
+    projection launches, averaged over a chain: per target its GMRES bytes and the guess x0
+    and b read (16 n)."""
+    iters, rest = inf["iters"], inf["restarts"]
+    T, N = iters.shape
+    total = 0
+    for i in range(N):
+        total += gmres_bytes(ns[i], polish_m, iters[:, i], rest[:, i], passes, sv, sop)
+        total += T * 16 * ns[i]
+    return total / T
+
+
+def projection_roofline(label, ns, inf, proj_s, mixed=False):
+    """The projection launches (Gram shares on the matrix cores, the small solves, x0) against
+    the matrix-core peak of their contraction's type: FP64, or BF16 in mixed precision."""
+    fl = projection_flops(ns, inf)
+    peak = 2500.0 if mixed else 78.6
+    ach = fl / proj_s / 1e12
+    return {"kernel": label, "bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+            "flops_per_launch": int(fl), "launch_ms": round(proj_s * 1e3, 4)}
+
+
+def target_rooflines(b, label, r, project, lm, warm=False, mixed=False, traffic_key=None):
+    """Roofline objects of a chain's target call.  With the projection inside the solve launch
+    (or plain GMRES): the one solve launch against HBM, launch_alg_bytes over the call's measured
+    duration lm (ms per timestep).  With the projection in launches of its own (the context's
+    autotuned choice): the solve launch (the polish) against HBM and the projection launches
+    against the matrix-core peak, each over its own duration from the library's phase events.
+    Returns (solve-launch roofline, projection roofline or None, phase figures)."""
+    ns, bids = chain_shape(b)
+    sv, sop, sbv = (4, 12, 2) if mixed else (8, 24, 0)
+    traffic = traffic_bytes(traffic_key, r["polish_m"]) if traffic_key else None
+    if project and getattr(b.ctx, "split", -1) >= 0:
+        pj, so = target_phase_ms(b)
+        byts = polish_alg_bytes(ns, r["infos"], r["polish_m"], sv, sop)
+        ro = roofline(f"solve_kernel (polish from the projected guess, {label})", byts,
+                      np.mean(so) / 1e3, traffic)
+        rp = projection_roofline(f"gram_kernel + x0_kernel (target projection, {label})", ns,
+                                 r["infos"], np.mean(pj) / 1e3, mixed)
+        return ro, rp, {"projection": "own launches", "split_tiles": int(b.ctx.split),
+                        "projection_launch_ms": round(float(np.mean(pj)), 4),
+                        "solve_launch_ms": round(float(np.mean(so)), 4)}
+    byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], project, warm=warm, sv=sv,
+                            sop=sop, sbv=sbv)
+    ls = np.mean(lm) / 1e3
+    ro = roofline(f"solve_kernel ({'projection + polish' if project else 'plain GMRES'}, "
+                  f"{label})", byts, ls, traffic)
+    if project:
+        fl = projection_flops(ns, r["infos"])
+        ro["projection_flops_per_launch"] = int(fl)
+        ro["projection_tflops"] = round(fl / ls / 1e12, 3)
+        return ro, None, {"projection": "inside the solve launch"}
+    return ro, None, {}
 
 
 def projection_flops(ns, inf):
@@ -203,8 +260,9 @@ def uneven_leg(args):
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.uneven_steps, 1, graph)
         lm = target_call_ms(b)
-        ns, bids = chain_shape(b)
-        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], method == "project")
+        ro, rp, ph = target_rooflines(b, f"{b.N} systems of three sizes per launch", r,
+                                      method == "project", lm,
+                                      traffic_key=f"uneven_{name}")
         un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                     "target_phase_value": round(b.N * cfg4.T / (sum(lm) / 1e3), 2),
@@ -215,9 +273,9 @@ def uneven_leg(args):
                     "waves": None if tu is None else tu.waves,
                     "seed_waves": None if tu is None or b.seed_tuning is None
                     else b.seed_tuning.waves,
-                    "roofline": roofline(f"solve_kernel ({name}, {b.N} systems of three sizes "
-                                         f"per launch)", byts, np.mean(lm) / 1e3,
-                                         traffic_bytes(f"uneven_{name}", r["polish_m"]))}
+                    "roofline": ro, **ph}
+        if rp is not None:
+            un[name]["roofline_projection"] = rp
         print(f"# uneven {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
               f"launch {np.mean(lm):.3f} ms, frac {un[name]['roofline']['frac']}",
               file=sys.stderr, flush=True)
@@ -249,11 +307,9 @@ def mixed_leg(args, orc=None):
         tu = None if args.no_tune else b.autotune()
         r = time_chain(b, args, args.mixed_steps, 1, graph)
         lm = target_call_ms(b)
-        ns, bids = chain_shape(b)
         mixed = prec == xkp.MIXED
-        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], method == "project",
-                                sv=4 if mixed else 8, sop=12 if mixed else 24,
-                                sbv=2 if mixed else 0)
+        ro, rp, ph = target_rooflines(b, f"{b.N} systems per launch", r, method == "project",
+                                      lm, mixed=mixed, traffic_key=f"c3_{name}")
         rec = b.record_chain(picks).cpu().numpy() if orc is not None else None
         sms = None
         if method == "project":
@@ -271,12 +327,9 @@ def mixed_leg(args, orc=None):
                     else b.seed_tuning.waves,
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
                     "seed_call_ms": sms,
-                    "roofline": roofline(f"solve_kernel ({name}, {b.N} systems per launch)",
-                                         byts, np.mean(lm) / 1e3,
-                                         traffic_bytes(f"c3_{name}", r["polish_m"]))}
-        if method == "project":
-            fl = projection_flops(ns, r["infos"])
-            mx[name]["roofline"]["projection_flops_per_launch"] = int(fl)
+                    "roofline": ro, **ph}
+        if rp is not None:
+            mx[name]["roofline_projection"] = rp
         if rec is not None:
             mx[name]["_rec"] = rec
         print(f"# 128x128 {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, ok={r['ok']}, "
@@ -578,6 +631,24 @@ def target_call_ms(b):
     return [a.elapsed_time(e) for a, e in ev]
 
 
+def target_phase_ms(b):
+    """Per-timestep durations (ms) of the target call's projection launches and of its solve
+    launch, from the phase events the library records on the call's stream
+    (xkp_ctx_set_timing), over one eager chain."""
+    import torch
+    b.ctx.set_timing(True)
+    b.reset()
+    pj, sv = [], []
+    for _ in range(b.T):
+        b.step()
+        a, c = b.ctx.last_timing()
+        pj.append(a)
+        sv.append(c)
+    b.ctx.set_timing(False)
+    torch.cuda.synchronize()
+    return pj, sv
+
+
 def seed_call_ms(b, alone=True):
     """Mean duration of the seed call (HIP events on the seed stream): over one eager chain in
     which every timestep's target call waits for its seed call to end (alone), or over the
@@ -799,7 +870,7 @@ def main():
         print(f"# copy probe: 3 copies of {args.copy_probe} MiB", file=sys.stderr, flush=True)
         del src, dst
     wanted = args.legs.split(",")
-    legs, tunings, launch = {}, {}, {}
+    legs, tunings, launch, roofs = {}, {}, {}, {}
     for name, method, mode, warm in (("project", "project", "target_galerkin", False),
                                      ("project_seed_galerkin", "project", "seed_galerkin", False),
                                      ("plain", "plain", "none", False),
@@ -814,6 +885,9 @@ def main():
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name in ("project", "plain", "project_warm", "plain_warm"):
             launch[name] = target_call_ms(ch)
+            roofs[name] = target_rooflines(
+                ch, f"{ch.N} systems per launch", legs[name], method == "project", launch[name],
+                warm=warm, traffic_key=f"c2_{name}" if args.reorth == "auto" else None)
         if method == "project":
             legs[name]["seed_ms"] = {"alone": round(seed_call_ms(ch, True), 4),
                                      "beside_targets": round(seed_call_ms(ch, False), 4)}
@@ -840,19 +914,11 @@ def main():
     value = N * T / per_step["project"]
 
     def leg_roof(name, project, warm=False):
-        r = legs[name]
-        byts = launch_alg_bytes(ns, bids, r["infos"], r["polish_m"], project, warm=warm)
-        ls = np.mean(launch[name]) / 1e3
-        ro = roofline(f"solve_kernel ({'projection + polish' if project else 'plain GMRES'}, "
-                      f"{N} systems per launch)", byts, ls,
-                      traffic_bytes(f"c2_{name}", r["polish_m"]) if args.reorth == "auto"
-                      else None)
-        if project:
-            fl = projection_flops(ns, r["infos"])
-            ro["projection_flops_per_launch"] = int(fl)
-            ro["projection_tflops"] = round(fl / ls / 1e12, 3)
-            ro["fp64_matrix_peak_tflops"] = 78.6
-        return ro
+        ro, rp, ph = roofs[name]
+        out_ro = dict(ro)
+        if rp is not None:
+            out_ro["projection_launches"] = rp
+        return out_ro
 
     def summary(name):
         r = legs[name]
@@ -863,7 +929,8 @@ def main():
              "verified": r["ok"], "verified_solves": r["verified_solves"]}
         if name in launch:
             d["target_phase_value"] = round(N * T / (sum(launch[name]) / 1e3), 2)
-            d["target_launch_ms"] = round(float(np.mean(launch[name])), 4)
+            d["target_call_ms"] = round(float(np.mean(launch[name])), 4)
+            d.update(roofs[name][2])
         if "seed_ms" in r:
             d["seed_call_ms"] = r["seed_ms"]
         return d
@@ -882,6 +949,7 @@ def main():
         "project": summary("project"),
         "plain_gmres": summary("plain"),
         "autotune": {k: {"polish_m": t.polish_m, "wg_per_cu": t.wg_per_cu, "waves": t.waves,
+                         "split": t.split,
                          "ms_best": round(t.ms_best, 4), "ms_default": round(t.ms_default, 4),
                          "seed_waves": None if ts is None else ts.waves,
                          "seed_rows_per_thread": None if ts is None else ts.seed_rows}

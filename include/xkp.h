@@ -193,12 +193,58 @@ xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
  * passes whose inner products are summed over the blocks in a fixed order (an orthonormal basis
  * to working precision, as the two modified passes of the one-workgroup solve give); results are
  * those of the one-workgroup solve to rounding.  The workgroups of a seed must be resident
- * together: each wait for the others gives up after two seconds with XKP_EDEVICE for that seed
- * (no hang).  Requires grids of at most 128 x 128 and max_m <= 64 (XKP_EUNSUPPORTED otherwise);
- * allocates the exchange buffers (a setup call, like xkp_ctx_create).  0 returns to one
- * workgroup per seed.
+ * together: each wait for the others gives up after a time limit (two seconds unless
+ * xkp_ctx_set_seed_wait says otherwise) with XKP_EDEVICE for that seed (no hang; the other seeds
+ * of the call and later calls are not affected).  Requires grids of at most 128 x 128 and
+ * max_m <= 64 (XKP_EUNSUPPORTED otherwise); allocates the exchange buffers (a setup call, like
+ * xkp_ctx_create).  0 returns to one workgroup per seed.
  */
 xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread);
+
+/*
+ * The time after which a wait of a spread-out seed (xkp_ctx_set_seed_width) gives up, in
+ * microseconds (0 .. 60e6; default 2e6).  0 gives up at the first wait whose data has not yet
+ * arrived: the seed then reports XKP_EDEVICE, its basis header and info carrying that status.
+ * XKP_EINVAL outside the range.
+ */
+xkp_status xkp_ctx_set_seed_wait(xkp_ctx *ctx, int64_t microseconds);
+
+/*
+ * Target projection in launches of its own (Section 3, Phase 2).  With max_tiles >= 0, later
+ * xkp_target_project_solve calls of this context (projection modes other than XKP_PROJ_NONE)
+ * first project every target over the whole chip, then polish in the solve launch:
+ *   1. each target's rows are split into at most T row tiles of a multiple of 256 rows
+ *      (T = max_tiles, or when 0 about as many tiles in all as the chip runs Gram workgroups
+ *      at once, two per compute unit; never more than one tile per 256 rows nor more tiles than
+ *      the context's partial slots, 2048 at most); one workgroup per tile forms its rows of
+ *      A' V_k and its share of V_k^T [A' V_k | r_base] (FP64 matrix cores, or BF16 ones for the
+ *      mixed-precision Gram matrix, z in FP64), and the target's last tile adds the shares in
+ *      tile order and solves the small system (LU with partial pivoting, or Givens rotations for
+ *      XKP_PROJ_SEED_LSQ)
+ *   2. x0 = x_base + V_k alpha by tiles
+ *   3. the solve launch polishes from x0.
+ * Batches of more than the context's max_batch targets project inside the solve launch.
+ * Statuses, basis_dim, guess_res and the iterate are those of the in-launch projection up to
+ * rounding (the order of the row sums differs).  Calls stay free of allocation and host
+ * synchronisation (graph-capturable).  The first call with max_tiles >= 0 allocates the partial
+ * slots (at most 2048 of (max_m + 1)^2 doubles) and per-target buffers (a setup call);
+ * max_tiles = -1 returns to the projection inside the solve launch (the default).  XKP_EINVAL
+ * for max_tiles < -1.
+ */
+xkp_status xkp_ctx_set_projection_split(xkp_ctx *ctx, int32_t max_tiles);
+
+/*
+ * Phase timing of target calls.  With on = 1, each later xkp_target_project_solve of this
+ * context records three HIP events on its stream: before the projection launches, before the
+ * solve launch, after it (the first two coincide when the projection runs inside the solve
+ * launch).  The first call with on = 1 creates the events (a setup call).  Recording events
+ * stays graph-capturable but adds event nodes: keep timing off in captured chains.
+ * xkp_ctx_last_timing waits for the last recorded call and returns its projection launches'
+ * and solve launch's durations in milliseconds; XKP_EINVAL if timing is off or no call has
+ * been recorded since it was switched on.
+ */
+xkp_status xkp_ctx_set_timing(xkp_ctx *ctx, int32_t on);
+xkp_status xkp_ctx_last_timing(xkp_ctx *ctx, float *ms_projection, float *ms_solve);
 
 /* Size in bytes of one seed basis buffer for n unknowns and restart length m. */
 size_t xkp_basis_bytes(int32_t n, int32_t m);
@@ -394,6 +440,9 @@ typedef struct {
     int32_t waves;        /* fastest workgroup size in wave64s (now set in the context)     */
     int32_t seed_rows;    /* xkp_autotune_seeds: 1 if spreading each seed over several
                              workgroups was chosen (xkp_ctx_set_seed_width), else 0           */
+    int32_t split;        /* xkp_autotune: the tile cap of the projection in launches of its
+                             own if that was chosen (xkp_ctx_set_projection_split, now set in
+                             the context), -1 for the projection inside the solve launch    */
 } xkp_tuning;
 
 /*
@@ -402,9 +451,12 @@ typedef struct {
  * wave64s), each candidate restart length of the polish (6, 8, 9, then m/4 (at least 8), m/2, 3m/4
  * and m, at most m; the short ones let the cycle's basis stay in registers) and each
  * workgroup count per compute unit the kernels can hold (1..occupancy), two timed calls each
- * after one untimed call, and keeps the fastest candidate whose every target converged.  The
- * chosen variant and workgroup count are stored in the context and apply to its later seed and
- * target calls; the chosen restart length is returned for the caller's params.
+ * after one untimed call, and keeps the fastest candidate whose every target converged.  For
+ * projected batches of at most max_batch targets every candidate is timed twice: with the
+ * projection inside the solve launch and in launches of its own (xkp_ctx_set_projection_split,
+ * with the context's tile cap if one was set, else 0).  The chosen variant, workgroup count
+ * and projection placement are stored in the context and apply to its later seed and target
+ * calls; the chosen restart length is returned for the caller's params.
  * Side effects: targets[i].x and infos hold the last candidate's results.  Unlike the other
  * calls this one synchronises the stream (it reads timings and statuses back), so it must not
  * be captured in a graph.  Returns XKP_ENOCONV if no candidate converged everywhere.

@@ -26,6 +26,7 @@ UNITS = [("xkp_kernels.hip", "xkp_kernels_512.o", ["-DXKP_NT=512", "-DXKP_VARIAN
                                                    "-DXKP_DEPTH16=2"]),
          ("xkp_common.hip", "xkp_common.o", []),
          ("xkp_wide.hip", "xkp_wide.o", []),
+         ("xkp_project.hip", "xkp_project.o", []),
          ("xkp_cnn.hip", "xkp_cnn.o", []),
          ("xkp_epilogue.hip", "xkp_epilogue.o", []),
          ("xkp_cluster.hip", "xkp_cluster.o", []),

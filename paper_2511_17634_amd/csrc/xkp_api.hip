@@ -25,6 +25,18 @@ struct xkp_ctx {
     int wide_R, wide_gmax, wide_cap;
     unsigned char *xch;
     size_t xch_stride;
+    long long wide_limit;   // give-up time of a spread-out seed's waits, 100 MHz ticks
+    // targets projected in launches of their own (xkp_ctx_set_projection_split): on, tiles per
+    // target at most (0: as many as the slots allow), partial slots, per-target counters,
+    // coefficients and statuses
+    int split, split_tiles, pj_slots, pj_stride;
+    double *pj_part, *pj_alpha;
+    unsigned *pj_ctr;
+    int *pj_stat;
+    // phase timing of target calls (xkp_ctx_set_timing): before the projection launches, before
+    // the solve launch, after it; recorded once a call has run
+    int timing, timed;
+    hipEvent_t tev[3];
 };
 
 namespace {
@@ -174,6 +186,7 @@ xkp_status xkp_ctx_create(xkp_ctx **out, int device, void *hip_stream, int32_t m
     c->cus = cus;
     c->per_cu = choose(max_n)->solve_per_cu(max_n);
     c->variant = 0;
+    c->wide_limit = 200000000LL;   // two seconds
     c->L = xkp::ws_layout(max_n, max_m, npad_for(max_n));
     if (hipMalloc((void **)&c->ws, sizeof(double) * c->L.stride * (size_t)c->slots) != hipSuccess) {
         delete c;
@@ -201,6 +214,12 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t f = hipFree(ctx->ws);
     hipError_t q = hipFree(ctx->queue);
     if (ctx->xch) hipFree(ctx->xch);
+    if (ctx->pj_part) hipFree(ctx->pj_part);
+    if (ctx->pj_alpha) hipFree(ctx->pj_alpha);
+    if (ctx->pj_ctr) hipFree(ctx->pj_ctr);
+    if (ctx->pj_stat) hipFree(ctx->pj_stat);
+    if (ctx->tev[0])
+        for (hipEvent_t ev : ctx->tev) hipEventDestroy(ev);
     delete ctx;
     return (e == hipSuccess && f == hipSuccess && q == hipSuccess) ? XKP_OK : XKP_EDEVICE;
 }
@@ -248,6 +267,87 @@ xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread) {
     return XKP_OK;
 }
 
+xkp_status xkp_ctx_set_timing(xkp_ctx *ctx, int32_t on) {
+    if (!ctx || (on != 0 && on != 1)) return XKP_EINVAL;
+    if (on && !ctx->tev[0]) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+        for (int i = 0; i < 3; ++i) {
+            if (hipEventCreate(&ctx->tev[i]) != hipSuccess) {
+                for (int q = 0; q < i; ++q) hipEventDestroy(ctx->tev[q]);
+                ctx->tev[0] = nullptr;
+                return XKP_EDEVICE;
+            }
+        }
+    }
+    ctx->timing = on;
+    ctx->timed = 0;
+    return XKP_OK;
+}
+
+xkp_status xkp_ctx_last_timing(xkp_ctx *ctx, float *ms_projection, float *ms_solve) {
+    if (!ctx || !ms_projection || !ms_solve || !ctx->timing || !ctx->timed) return XKP_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    if (hipEventSynchronize(ctx->tev[2]) != hipSuccess ||
+        hipEventElapsedTime(ms_projection, ctx->tev[0], ctx->tev[1]) != hipSuccess ||
+        hipEventElapsedTime(ms_solve, ctx->tev[1], ctx->tev[2]) != hipSuccess)
+        return XKP_EDEVICE;
+    return XKP_OK;
+}
+
+xkp_status xkp_ctx_set_seed_wait(xkp_ctx *ctx, int64_t microseconds) {
+    if (!ctx || microseconds < 0 || microseconds > 60000000LL) return XKP_EINVAL;
+    ctx->wide_limit = 100LL * microseconds;
+    return XKP_OK;
+}
+
+xkp_status xkp_ctx_set_projection_split(xkp_ctx *ctx, int32_t max_tiles) {
+    if (!ctx || max_tiles < -1) return XKP_EINVAL;
+    if (max_tiles < 0) {
+        ctx->split = 0;
+        return XKP_OK;
+    }
+    ctx->split_tiles = max_tiles;
+    if (ctx->pj_part) {
+        ctx->split = 1;
+        return XKP_OK;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    // one slot per 256-row tile of a full batch of the largest systems, 2048 at most: a batch
+    // with more tiles than slots splits its targets into fewer tiles, down to one per target
+    const int tiles = (ctx->max_n + 255) / 256;
+    long slots = (long)ctx->max_batch * tiles;
+    if (slots > 2048) slots = 2048;
+    const int stride = xkp::proj::slot_doubles(ctx->max_m);
+    double *part = nullptr, *alpha = nullptr;
+    unsigned *ctr = nullptr;
+    int *stat = nullptr;
+    if (hipMalloc((void **)&part, sizeof(double) * stride * (size_t)slots) != hipSuccess ||
+        hipMalloc((void **)&alpha, sizeof(double) * 64 * (size_t)ctx->max_batch) != hipSuccess ||
+        hipMalloc((void **)&ctr, sizeof(unsigned) * (size_t)ctx->max_batch) != hipSuccess ||
+        hipMalloc((void **)&stat, sizeof(int) * (size_t)ctx->max_batch) != hipSuccess) {
+        if (part) hipFree(part);
+        if (alpha) hipFree(alpha);
+        if (ctr) hipFree(ctr);
+        return XKP_ENOMEM;
+    }
+    if (hipMemset(ctr, 0, sizeof(unsigned) * (size_t)ctx->max_batch) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        hipFree(part);
+        hipFree(alpha);
+        hipFree(ctr);
+        hipFree(stat);
+        return XKP_EDEVICE;
+    }
+    ctx->pj_part = part;
+    ctx->pj_alpha = alpha;
+    ctx->pj_ctr = ctr;
+    ctx->pj_stat = stat;
+    ctx->pj_slots = (int)slots;
+    ctx->pj_stride = stride;
+    ctx->split = 1;
+    return XKP_OK;
+}
+
 size_t xkp_basis_bytes(int32_t n, int32_t m) {
     if (n < 1 || m < 1) return 0;
     return xkp::basis_bytes(n, m);
@@ -263,15 +363,15 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     if (n_seeds == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     if (ctx->wide_R > 0 && n_seeds <= ctx->wide_cap && params->reorth == XKP_REORTH_AUTO) {
-        // each seed over ceil(n / 256) workgroups; a wait gives up after two seconds
+        // each seed over ceil(n / 256) workgroups; a wait gives up after ctx->wide_limit
         return from_hip(xkp::wide::launch_wide_seed(ctx->stream, seeds, n_seeds, *params,
                                                     bases, infos, ctx->xch, ctx->xch_stride,
-                                                    ctx->wide_gmax, nmax, 200000000LL));
+                                                    ctx->wide_gmax, nmax, ctx->wide_limit));
     }
     const int grid = solve_grid(ctx, n_seeds);
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
                              *params, xkp::kKeepBasis, 0, nullptr, bases, infos, ctx->ws, ctx->L,
-                             nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}));
+                             nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}, nullptr));
 }
 
 xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
@@ -287,10 +387,28 @@ xkp_status xkp_target_project_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_s
     if (n_targets == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     const int grid = solve_grid(ctx, n_targets);
-    const int flags = (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0) | xkp::kRegBasis;
-    return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
-                             *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
-                             nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}));
+    int flags = (params->mode != XKP_PROJ_NONE ? xkp::kTarget : 0) | xkp::kRegBasis;
+    if (ctx->timing && hipEventRecord(ctx->tev[0], ctx->stream) != hipSuccess) return XKP_EDEVICE;
+    if (ctx->split && params->mode != XKP_PROJ_NONE && n_targets <= ctx->max_batch) {
+        // the projection over row tiles across the chip, then the polish from x0 (the
+        // per-target buffers hold max_batch targets: a larger batch projects in the solve
+        // launch)
+        const hipError_t e = xkp::proj::launch_project(
+            ctx->stream, targets, n_targets, n_bases, bases, *params, nmax, ctx->pj_part,
+            ctx->pj_slots, ctx->pj_stride, ctx->pj_ctr, ctx->pj_alpha, ctx->pj_stat, infos,
+            ctx->split_tiles, ctx->cus);
+        if (e != hipSuccess) return XKP_EDEVICE;
+        flags |= xkp::kPreProjected;
+    }
+    if (ctx->timing && hipEventRecord(ctx->tev[1], ctx->stream) != hipSuccess) return XKP_EDEVICE;
+    st = from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
+                           *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
+                           nmax, ctx->queue, xkp::Learned{nullptr, 0, 0.0, 0.0}, ctx->pj_stat));
+    if (st == XKP_OK && ctx->timing) {
+        if (hipEventRecord(ctx->tev[2], ctx->stream) != hipSuccess) return XKP_EDEVICE;
+        ctx->timed = 1;
+    }
+    return st;
 }
 
 xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targets,
@@ -311,7 +429,8 @@ xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *
                       xkp::kRegBasis;
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
                              *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
-                             nmax, ctx->queue, xkp::Learned{alpha, alpha_ld, alpha_scale, gate}));
+                             nmax, ctx->queue, xkp::Learned{alpha, alpha_ld, alpha_scale, gate},
+                             nullptr));
 }
 
 xkp_status xkp_basis_coeffs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems,
@@ -562,12 +681,48 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     for (int &c : cand_m)
         if (c > m) c = m;
     std::sort(cand_m, cand_m + 7);
-    return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 7, false, 2,
-                     [&](const xkp_params &P) {
-                         return xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases,
-                                                         &P, infos);
-                     },
-                     out);
+    auto run = [&](xkp_tuning *t) {
+        return tune_loop(ctx, nmax, n_targets, infos, params, cand_m, 7, false, 2,
+                         [&](const xkp_params &P) {
+                             return xkp_target_project_solve(ctx, n_targets, targets, n_bases,
+                                                             bases, &P, infos);
+                         },
+                         t);
+    };
+    // every candidate with the projection inside the solve launch, then (projected batches the
+    // per-target buffers hold) with the projection in launches of its own; the faster stays
+    const int saved_split = ctx->split;
+    ctx->split = 0;
+    xkp_tuning t_in = *out;
+    xkp_status st = run(&t_in);
+    if (st != XKP_OK) {
+        ctx->split = saved_split;
+        return st;
+    }
+    *out = t_in;
+    out->split = -1;
+    if (params->mode == XKP_PROJ_NONE || n_targets > ctx->max_batch) return XKP_OK;
+    const int in_w = ctx->per_cu, in_v = ctx->variant;
+    const int tiles = ctx->pj_part ? ctx->split_tiles : 0;
+    st = xkp_ctx_set_projection_split(ctx, tiles);
+    if (st != XKP_OK) {
+        ctx->split = 0;
+        return st == XKP_ENOMEM ? XKP_OK : st;   // no room for the split buffers: stay in-launch
+    }
+    xkp_tuning t_sp = t_in;
+    st = run(&t_sp);
+    if (st == XKP_OK && t_sp.ms_best < t_in.ms_best) {
+        t_sp.ms_default = t_in.ms_default;
+        t_sp.n_tried += t_in.n_tried;
+        t_sp.split = tiles;
+        *out = t_sp;
+        return XKP_OK;   // the split run left its variant and workgroup count in the context
+    }
+    out->n_tried += st == XKP_OK ? t_sp.n_tried : 0;
+    ctx->split = 0;
+    ctx->per_cu = in_w;
+    ctx->variant = in_v;
+    return st == XKP_OK || st == XKP_ENOCONV ? XKP_OK : st;
 }
 
 xkp_status xkp_autotune_seeds(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds,
@@ -730,7 +885,7 @@ xkp_status xkp_target_project_solve_noalloc(int device, void *hip_stream, int32_
                                             xkp::v512::lds_vec_len(nmax), targets, n_targets,
                                             *params, flags, n_bases, bases, nullptr, infos,
                                             (double *)(base + kScratchHead), L, nmax, queue,
-                                            xkp::Learned{nullptr, 0, 0.0, 0.0}));
+                                            xkp::Learned{nullptr, 0, 0.0, 0.0}, nullptr));
 }
 
 const char *xkp_status_string(xkp_status s) {

@@ -138,6 +138,152 @@ __device__ __forceinline__ OpConst op_const(const xkp_system &s) {
     return o;
 }
 
+// A descriptor a launch can solve: a grid of at most nmax unknowns with its arrays and dt > 0.
+__device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
+    return s.H > 0 && (long)s.H * s.H <= nmax && s.mt != nullptr && s.b != nullptr &&
+           s.x != nullptr && s.dt > 0.0;
+}
+
+// The four neighbour coefficients of row p < n (Section 2.3: the lagged-density drift terms
+// and the drift field f, zero where the neighbour lies outside the grid).
+__device__ __forceinline__ void row_coeffs(const xkp_system &s, const OpConst &o, int p,
+                                           double &cE, double &cW, double &cN, double &cS) {
+    const int H = o.H;
+    const double *__restrict__ mt = s.mt;
+    const int i = p / H, j = p - (p / H) * H;
+    const double mE = (i + 1 < H) ? mt[p + H] : 0.0;
+    const double mW = (i > 0) ? mt[p - H] : 0.0;
+    const double mN = (j + 1 < H) ? mt[p + 1] : 0.0;
+    const double mS = (j > 0) ? mt[p - 1] : 0.0;
+    const double fxp = s.fx ? s.fx[p] : 0.0;
+    const double fyp = s.fy ? s.fy[p] : 0.0;
+    const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
+    const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
+    cE = (i + 1 < H) ? -o.a + ex : 0.0;
+    cW = (i > 0) ? -o.a - ex : 0.0;
+    cN = (j + 1 < H) ? -o.a + ey : 0.0;
+    cS = (j > 0) ? -o.a - ey : 0.0;
+}
+
+// BF16 bits of a double: rounded to FP32, then to the nearest BF16 (ties to even); finite
+// values only.
+__device__ __forceinline__ unsigned short to_bf16(double d) {
+    const unsigned u = __builtin_bit_cast(unsigned, (float)d);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// ----------------------------------------------------------------------------------------
+// Small dense solves of the projection (Section 3, Phase 2), one wavefront.
+
+// Least squares min ||z - Hbar alpha|| for the (kk+1) x kk upper Hessenberg matrix in LDS (row
+// major) by Givens rotations, wavefront 0, lane q owning column q.  z is in LDS (kk+1 values).
+__device__ inline bool lsq_hessenberg_wave(double *A, int lda, int kk, double *z, double *out) {
+    const int q = threadIdx.x;
+    double cmax = 0.0;
+    if (q < kk)
+        for (int r = 0; r <= kk; ++r) cmax = fmax(cmax, fabs(A[r * lda + q]));
+    const double amax = wave_max(cmax);
+    if (!(amax > 0.0)) return true;
+    for (int c = 0; c < kk; ++c) {
+        const double a0 = A[c * lda + c], a1 = A[(c + 1) * lda + c];
+        const double den = sqrt(a0 * a0 + a1 * a1);
+        if (!(den > 1e-13 * amax)) return true;
+        const double cs = a0 / den, sn = a1 / den;
+        wave_lds_sync();
+        if (q >= c && q < kk) {
+            const double u = A[c * lda + q], v = A[(c + 1) * lda + q];
+            A[c * lda + q] = cs * u + sn * v;
+            A[(c + 1) * lda + q] = -sn * u + cs * v;
+        }
+        if (q == 0) {
+            const double u = z[c], v = z[c + 1];
+            z[c] = cs * u + sn * v;
+            z[c + 1] = -sn * u + cs * v;
+        }
+        wave_lds_sync();
+    }
+    // back substitution on the triangle, lane r holding z_r
+    double zl = (q < kk) ? z[q] : 0.0;
+    for (int c = kk - 1; c >= 0; --c) {
+        const double xc = readlane_d(zl, c) / A[c * lda + c];
+        if (q < c) zl -= A[q * lda + c] * xc;
+        if (q == 0) out[c] = xc;
+    }
+    wave_lds_sync();
+    return false;
+}
+
+// LU with partial pivoting of the kk x kk row-major LDS matrix A (leading dimension lda,
+// kk <= KM) by one wavefront, lane r holding row r in registers.  Per column the pivot is the
+// largest remaining |A[r][c]| (lowest lane on ties); rows are not moved: the pivot lane writes
+// its row's remaining entries to rowbuf (LDS, KM doubles, 16-byte aligned), every lane reads
+// them back as broadcasts and updates its row in place.  zr is lane r's right-hand side entry;
+// the solution goes to out[0..kk) in LDS.  A pivot <= 1e-13 max|A| reports singular (true).
+// The column loops are unrolled to KM, so every register index is a constant.
+template <int KM>
+__device__ __forceinline__ bool lu_regs(const double *A, int lda, int kk, double zr, double *out,
+                                        double *rowbuf) {
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    const int r = threadIdx.x & 63;
+    kk = __builtin_amdgcn_readfirstlane(kk);
+    double a[KM];
+    double rowmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        a[q] = (r < kk && q < kk) ? A[r * lda + q] : 0.0;
+        rowmax = fmax(rowmax, fabs(a[q]));
+    }
+    const double amax = wave_max(rowmax);
+    if (!(amax > 0.0)) return true;
+    bool active = r < kk;
+    int pc = KM;          // the column this lane's row is the pivot of
+    double rp = 0.0;      // the reciprocal of that pivot
+    int pl_of = 0;        // lane c: the pivot lane of column c
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+        if (c < kk) {
+            const double v = active ? fabs(a[c]) : -1.0;
+            const double vmax = wave_max(v);
+            if (!(vmax > 1e-13 * amax)) return true;
+            const int pl = __ffsll((unsigned long long)__ballot(active && v == vmax)) - 1;
+            if (r == c) pl_of = pl;
+            if (r == pl) {
+#pragma unroll
+                for (int q = c & ~1; q < KM; q += 2) *(d2_t *)(rowbuf + q) = d2_t{a[q], a[q + 1]};
+            }
+            wave_lds_sync();
+            const double piv = rowbuf[c];
+            if (r == pl) {
+                active = false;
+                pc = c;
+                rp = 1.0 / piv;
+            }
+            const double l = active ? a[c] / piv : 0.0;
+#pragma unroll
+            for (int q = (c + 1) & ~1; q < KM; q += 2) {
+                const d2_t u = *(const d2_t *)(rowbuf + q);
+                if (q > c) a[q] -= l * u[0];
+                a[q + 1] -= l * u[1];
+            }
+            zr -= l * readlane_d(zr, pl);
+            wave_lds_sync();   // read before the next pivot row is written
+        }
+    }
+    // back substitution on the pivot rows, last column first
+#pragma unroll
+    for (int c = KM - 1; c >= 0; --c) {
+        if (c < kk) {
+            const int pl = __builtin_amdgcn_readlane(pl_of, c);
+            const double xc = readlane_d(zr, pl) * readlane_d(rp, pl);
+            if (pc < c) zr -= a[c] * xc;
+            if (r == 0) out[c] = xc;
+        }
+    }
+    wave_lds_sync();
+    return false;
+}
+
+
 
 }  // namespace XKP_VARIANT
 }  // namespace xkp

@@ -35,7 +35,9 @@ enum GmresFlags {
     kTarget = 4,       // project onto the seed basis first, then polish from the projection
     kLearned = 8,      // try the learned guess first; project only if it fails the gate
     kDcgs = 16,        // seeds: the kept cycle by DCGS2 (set by the launcher when the LDS fits)
-    kRegBasis = 32     // discarded cycles with the basis in registers where it fits
+    kRegBasis = 32,    // discarded cycles with the basis in registers where it fits
+    kPreProjected = 64 // targets projected by the projection launches (xkp_project.hip): x holds
+                       // x0, pre[i] the projection's status
 };
 
 // Learned-guess inputs of a solve launch: target i's predicted residual coordinates at
@@ -60,7 +62,7 @@ struct Learned {
                             int nsys, xkp_params P, int flags, int n_bases,                      \
                             const void *const *bases, void *const *keep_bases,                   \
                             xkp_info *infos, double *ws, WsLayout L, int nmax,                   \
-                            unsigned *queue, Learned lg);                                        \
+                            unsigned *queue, Learned lg, const int *pre);                        \
     hipError_t launch_coeffs(hipStream_t st, int grid, int rmax, const xkp_system *sys,         \
                              int nsys, int n_bases, const void *const *bases, int m_out,         \
                              int kind, double *alpha, int nmax);                                 \
@@ -87,6 +89,20 @@ hipError_t launch_wide_seed(hipStream_t st, const xkp_system *sys, int nsys, xkp
                             void *const *keep_bases, xkp_info *infos, unsigned char *xch,
                             size_t xch_stride, int gmax, int nmax, long long limit);
 }  // namespace wide
+
+// Target projection in launches of its own (xkp_project.hip): every target split into at most
+// tiles_cap row tiles (0: about one round of items on the cus compute units), then x0 written
+// to the targets' x; per target, the status (XKP_OK, XKP_ESINGULAR, XKP_EINVAL, -1 for a
+// rejected descriptor) goes to stat for the polish launch (kPreProjected).  part: slots partial
+// slots of slot_doubles(mmax) doubles; ctr: one zeroed counter per target; alpha: 64 per target.
+namespace proj {
+int slot_doubles(int mmax);
+int tiles_per_target(int nsys, int nmax, int slots, int tiles_cap, int cus);
+hipError_t launch_project(hipStream_t st, const xkp_system *sys, int nsys, int n_bases,
+                          const void *const *bases, xkp_params P, int nmax, double *part,
+                          int slots, int sstride, unsigned *ctr, double *alpha, int *stat,
+                          xkp_info *infos, int tiles_cap, int cus);
+}  // namespace proj
 
 // Score and probability-flow embedding (xkp_epilogue.hip).
 namespace epi {

@@ -105,12 +105,6 @@ __device__ __forceinline__ void bst16(rsrc_t r, unsigned byte_off, unsigned shor
     __builtin_amdgcn_raw_buffer_store_b16(v, r, byte_off, soff, 0);
 }
 
-// BF16 bits of a double: rounded to FP32, then to the nearest BF16 (ties to even); finite
-// values only.
-__device__ __forceinline__ unsigned short to_bf16(double d) {
-    const unsigned u = __builtin_bit_cast(unsigned, (float)d);
-    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
 // Row k of this thread: p = 2t + (k & 1) + (k >> 1) * 2 kNT, addressed as the lane offset of the
 // pair (one register) + a scalar offset.  Every per-row array a thread holds is indexed by k.
 __device__ __forceinline__ int row_of(int k) {
@@ -273,27 +267,11 @@ struct Coef {
 
 template <int RMAX>
 __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &C, bool mixed) {
-    const int H = o.H;
-    const double *__restrict__ mt = s.mt;
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
         const int p = row_of(k);
         double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
-        if (p < o.n) {
-            const int i = p / H, j = p - (p / H) * H;
-            const double mE = (i + 1 < H) ? ld(mt, p + H) : 0.0;
-            const double mW = (i > 0) ? ld(mt, p - H) : 0.0;
-            const double mN = (j + 1 < H) ? ld(mt, p + 1) : 0.0;
-            const double mS = (j > 0) ? ld(mt, p - 1) : 0.0;
-            const double fxp = s.fx ? ld(s.fx, p) : 0.0;
-            const double fyp = s.fy ? ld(s.fy, p) : 0.0;
-            const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
-            const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
-            cE = (i + 1 < H) ? -o.a + ex : 0.0;
-            cW = (i > 0) ? -o.a - ex : 0.0;
-            cN = (j + 1 < H) ? -o.a + ey : 0.0;
-            cS = (j > 0) ? -o.a - ey : 0.0;
-        }
+        if (p < o.n) row_coeffs(s, o, p, cE, cW, cN, cS);
         const unsigned off = (unsigned)p * 8u;
         bst(mkbuf(C.E, kNT * RMAX), off, cE);
         bst(mkbuf(C.W, kNT * RMAX), off, cW);
@@ -415,10 +393,6 @@ __device__ __forceinline__ void store_rows_lds(double *v, const double (&r)[RMAX
     for (int k = 0; k < RMAX; k += 2) *(double2_t *)(vc + k * kNT) = double2_t{r[k], r[k + 1]};
 }
 
-__device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
-    return s.H > 0 && (long)s.H * s.H <= nmax && s.mt != nullptr && s.b != nullptr &&
-           s.x != nullptr && s.dt > 0.0;
-}
 
 // ----------------------------------------------------------------------------------------
 // LDS layout of the GMRES kernel: vbuf[nlds] | Rp[kMMax*(kMMax+1)/2] | cs | sn | gv | h1 | yv | red
@@ -1239,44 +1213,6 @@ __device__ bool lu_solve_wave(double *A, int lda, int kk, double zr, double *out
     return false;
 }
 
-// Least squares min ||z - Hbar alpha|| for the (kk+1) x kk upper Hessenberg matrix in LDS (row
-// major) by Givens rotations, wavefront 0, lane q owning column q.  z is in LDS (kk+1 values).
-__device__ bool lsq_hessenberg_wave(double *A, int lda, int kk, double *z, double *out) {
-    const int q = threadIdx.x;
-    double cmax = 0.0;
-    if (q < kk)
-        for (int r = 0; r <= kk; ++r) cmax = fmax(cmax, fabs(A[r * lda + q]));
-    const double amax = wave_max(cmax);
-    if (!(amax > 0.0)) return true;
-    for (int c = 0; c < kk; ++c) {
-        const double a0 = A[c * lda + c], a1 = A[(c + 1) * lda + c];
-        const double den = sqrt(a0 * a0 + a1 * a1);
-        if (!(den > 1e-13 * amax)) return true;
-        const double cs = a0 / den, sn = a1 / den;
-        wave_lds_sync();
-        if (q >= c && q < kk) {
-            const double u = A[c * lda + q], v = A[(c + 1) * lda + q];
-            A[c * lda + q] = cs * u + sn * v;
-            A[(c + 1) * lda + q] = -sn * u + cs * v;
-        }
-        if (q == 0) {
-            const double u = z[c], v = z[c + 1];
-            z[c] = cs * u + sn * v;
-            z[c + 1] = -sn * u + cs * v;
-        }
-        wave_lds_sync();
-    }
-    // back substitution on the triangle, lane r holding z_r
-    double zl = (q < kk) ? z[q] : 0.0;
-    for (int c = kk - 1; c >= 0; --c) {
-        const double xc = readlane_d(zl, c) / A[c * lda + c];
-        if (q < c) zl -= A[q * lda + c] * xc;
-        if (q == 0) out[c] = xc;
-    }
-    wave_lds_sync();
-    return false;
-}
-
 // Partial [V_k^T W] over the 8-row groups g = wave, wave + kNW, ... for KTR row tiles and NTC
 // column tiles starting at column tile tc0, FP64 matrix cores (v_mfma_f64_16x16x4: A 16x4 from
 // lane i + 16 kk, B 4x16 from lane j + 16 kk).  Lane l loads rows 8g + 2(l/16) and the next one
@@ -1900,11 +1836,17 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           const void *const *bases, void *keep_base,
                                           const Coef &C, double *slot, const WsLayout &Lw,
                                           double *lds, int nlds, int nbuf, int nregion,
-                                          const Learned &lg, const float *al) {
+                                          const Learned &lg, const float *al, int pre0) {
     int pre = XKP_OK;
     int gsrc = (flags & kTarget) ? 1 : 0;
     bool project = PROJ;
-    if (flags & kLearned) {
+    if (flags & kPreProjected) {
+        // projected by the projection launches: x holds x0; no basis (XKP_EINVAL) was reported
+        // there
+        if (pre0 != XKP_OK && pre0 != XKP_ESINGULAR) return;
+        pre = pre0;
+        flags |= kStartFromX;
+    } else if (flags & kLearned) {
         // the network's guess, kept when its FP64 residual passes the gate
         for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;
         lds_barrier();
@@ -1967,7 +1909,7 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
                                                     void *const *keep_bases, xkp_info *infos,
                                                     double *ws, WsLayout Lw, int nmax, int nlds,
                                                     int nbuf, int nregion, unsigned *queue,
-                                                    Learned lg) {
+                                                    Learned lg, const int *pre) {
     double *lds = xkp_dyn_lds;
     __shared__ int next[2];
     double *slot = ws + (size_t)blockIdx.x * Lw.stride;
@@ -1990,9 +1932,10 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
         void *kb = (flags & kKeepBasis) ? keep_bases[si] : nullptr;
         const int n = s.H * s.H;
         const float *al = (flags & kLearned) ? lg.alpha + (size_t)si * lg.ld : nullptr;
+        const int pre0 = (flags & kPreProjected) ? pre[si] : XKP_OK;
 #define XKP_SOLVE(R_)                                                                            \
     solve_one<R_, PROJ>(s, info, P, flags, n_bases, bases, kb, C, slot, Lw, lds, nlds, nbuf, nregion, \
-                        lg, al)
+                        lg, al, pre0)
         if constexpr (RMAX > kRClass0) {
             if (n <= kNT * kRClass0) {
                 XKP_SOLVE(kRClass0);
@@ -2372,8 +2315,9 @@ static SolvePlan solve_plan(int nlds, bool proj) {
 hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_system *sys,
                         int nsys, xkp_params P, int flags, int n_bases, const void *const *bases,
                         void *const *keep_bases, xkp_info *infos, double *ws, WsLayout L,
-                        int nmax, unsigned *queue, Learned lg) {
-    const bool proj = (flags & kTarget) != 0;
+                        int nmax, unsigned *queue, Learned lg, const int *pre) {
+    // targets projected by the projection launches need no projection code or LDS here
+    const bool proj = (flags & kTarget) != 0 && (flags & kPreProjected) == 0;
     SolvePlan sp = solve_plan(nlds, proj || (flags & kLearned) != 0);
     // seeds of up to 4096 unknowns: the kept cycle by DCGS2, its LDS after the GMRES layout
     if ((flags & kKeepBasis) && !proj && rmax * kNT <= 4096) {
@@ -2387,7 +2331,7 @@ hipError_t launch_solve(hipStream_t st, int grid, int rmax, int nlds, const xkp_
         if (e != hipSuccess) return e;                                                         \
         hipLaunchKernelGGL((solve_kernel<R, PJ>), dim3(grid), dim3(kNT), sp.lds, st, sys, nsys, \
                            P, flags, n_bases, bases, keep_bases, infos, ws, L, nmax, nlds,     \
-                           sp.nbuf, sp.nregion, queue, lg);                                    \
+                           sp.nbuf, sp.nregion, queue, lg, pre);                               \
     }
     XKP_DISPATCH(rmax, {
         if (proj) XKP_LAUNCH_SOLVE(true) else XKP_LAUNCH_SOLVE(false)

@@ -281,10 +281,6 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     unsigned short *Vb = P.precision == XKP_MIXED
                              ? (unsigned short *)((char *)hdr + basis_off_vb(n, m))
                              : nullptr;
-    auto to_bf16 = [](double v) {
-        const unsigned u = __builtin_bit_cast(unsigned, (float)v);
-        return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-    };
     if (g == 0)
         for (int t = tid; t < (m + 1) * m; t += NT) Hb[t] = 0.0;
 

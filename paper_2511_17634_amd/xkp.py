@@ -43,7 +43,7 @@ class Params(ct.Structure):
 class Tuning(ct.Structure):
     _fields_ = [("polish_m", ct.c_int32), ("wg_per_cu", ct.c_int32), ("ms_best", ct.c_float),
                 ("ms_default", ct.c_float), ("n_tried", ct.c_int32), ("waves", ct.c_int32),
-                ("seed_rows", ct.c_int32)]
+                ("seed_rows", ct.c_int32), ("split", ct.c_int32)]
 
 
 class XkpError(RuntimeError):
@@ -71,6 +71,10 @@ def load():
         lib.xkp_ctx_destroy.argtypes = [P]
         lib.xkp_ctx_set_launch.argtypes = [P, ct.c_int32, ct.c_int32]
         lib.xkp_ctx_set_seed_width.argtypes = [P, ct.c_int32]
+        lib.xkp_ctx_set_seed_wait.argtypes = [P, ct.c_int64]
+        lib.xkp_ctx_set_projection_split.argtypes = [P, ct.c_int32]
+        lib.xkp_ctx_set_timing.argtypes = [P, ct.c_int32]
+        lib.xkp_ctx_last_timing.argtypes = [P, ct.POINTER(ct.c_float), ct.POINTER(ct.c_float)]
         lib.xkp_basis_bytes.argtypes = [ct.c_int32, ct.c_int32]
         lib.xkp_basis_bytes.restype = ct.c_size_t
         lib.xkp_seed_build.argtypes = [P, ct.c_int32, P, P, ct.POINTER(Params), P]
@@ -111,7 +115,9 @@ def load():
                   "xkp_score_flow", "xkp_cluster_seeds",
                   "xkp_cnn_forward", "xkp_cnn_backward", "xkp_cnn_adam",
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch",
-                  "xkp_target_project_solve_noalloc", "xkp_ctx_set_seed_width"):
+                  "xkp_target_project_solve_noalloc", "xkp_ctx_set_seed_width",
+                  "xkp_ctx_set_seed_wait", "xkp_ctx_set_projection_split",
+                  "xkp_ctx_set_timing", "xkp_ctx_last_timing"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -214,6 +220,7 @@ class Context:
         self._h = h
         self.max_n, self.max_m, self.max_batch = max_n, max_m, max_batch
         self.seed_width = 0        # 1 once seed calls are spread over several workgroups
+        self.split = -1            # >= 0 once targets are projected in launches of their own
 
     def set_launch(self, waves, wg_per_cu=1):
         """Workgroup size (8 or 16 wave64s) and workgroups per compute unit of later solves."""
@@ -225,6 +232,28 @@ class Context:
         _check(load().xkp_ctx_set_seed_width(self._h, rows_per_thread),
                "xkp_ctx_set_seed_width")
         self.seed_width = int(rows_per_thread)
+
+    def set_seed_wait(self, microseconds):
+        """Give-up time of a spread-out seed's waits (default two seconds)."""
+        _check(load().xkp_ctx_set_seed_wait(self._h, int(microseconds)), "xkp_ctx_set_seed_wait")
+
+    def set_projection_split(self, max_tiles=0):
+        """Later target calls project in launches of their own over at most max_tiles row tiles
+        per target (0: as many as fit); -1 projects inside the solve launch again."""
+        _check(load().xkp_ctx_set_projection_split(self._h, int(max_tiles)),
+               "xkp_ctx_set_projection_split")
+        self.split = int(max_tiles)
+
+    def set_timing(self, on=True):
+        """Record phase events around later target calls (see last_timing)."""
+        _check(load().xkp_ctx_set_timing(self._h, int(bool(on))), "xkp_ctx_set_timing")
+
+    def last_timing(self):
+        """(projection ms, solve ms) of the last target call recorded with timing on."""
+        a, b = ct.c_float(), ct.c_float()
+        _check(load().xkp_ctx_last_timing(self._h, ct.byref(a), ct.byref(b)),
+               "xkp_ctx_last_timing")
+        return float(a.value), float(b.value)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -268,6 +297,7 @@ class Context:
         t = Tuning()
         _check(load().xkp_autotune(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
                                    ct.byref(params), _ptr(infos), ct.byref(t)), "xkp_autotune")
+        self.split = int(t.split)
         return t
 
     def basis_accumulate(self, n, n_src, src_ptrs, out_ptrs, per_source, cap, out_k=None):

@@ -80,6 +80,8 @@ def test_host_side_errors_without_gpu(lib):
     t = xkp.Tuning()
     assert lib.xkp_autotune(None, 1, None, 0, None, ct.byref(P), None, ct.byref(t)) == xkp.EINVAL
     assert lib.xkp_ctx_set_launch(None, 8, 1) == xkp.EINVAL
+    assert lib.xkp_ctx_set_projection_split(None, 0) == xkp.EINVAL
+    assert lib.xkp_ctx_set_seed_wait(None, 1000) == xkp.EINVAL
     assert lib.xkp_learned_solve(None, 1, None, 1, None, ct.byref(P), None, 41, 1.0, 1e-6,
                                  None) == xkp.EINVAL
     assert lib.xkp_basis_coeffs(None, 1, None, 1, None, 40, 0, None) == xkp.EINVAL

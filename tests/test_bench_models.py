@@ -1,7 +1,8 @@
 """The benchmark's algorithmic byte and flop models (bench.py), against hand counts: GMRES
 bytes per Arnoldi step and cycle end, with restarts, two Gram-Schmidt passes and FP32 element
 sizes; a target launch's bytes (per-target inputs and outputs, the seed basis once per launch)
-and the projection's flops; the scipy matrix of the CPU baseline is the oracle's operator; the
+and the projection's flops; the polish launch after the projection launches and their
+matrix-core roofline; the scipy matrix of the CPU baseline is the oracle's operator; the
 counter figures apply only to the sources they were taken with."""
 import os
 import sys
@@ -94,3 +95,20 @@ def test_traffic_only_for_the_sources_it_was_taken_with(monkeypatch):
     assert bench.traffic_bytes("missing", 10) is None
     monkeypatch.setitem(bench.TRAFFIC["probe"], "csrc_digest", "0" * 16)
     assert bench.traffic_bytes("probe", 10) is None
+
+
+def test_polish_bytes_and_projection_roofline_by_hand():
+    """The polish launch after the projection launches: GMRES bytes plus x0 and b read (16 n)
+    per target; the projection launches against the FP64 (or BF16) matrix-core peak."""
+    n, pm = 4096, 10
+    inf = {"basis_dim": np.array([[30, 30, 30], [25, 25, 25]]),
+           "iters": np.array([[12, 10, 7], [9, 9, 11]]),
+           "restarts": np.array([[1, 0, 0], [0, 0, 1]])}
+    want = sum(bench.gmres_bytes(n, pm, [inf["iters"][t, i]], [inf["restarts"][t, i]])
+               for t in range(2) for i in range(3)) + 2 * 3 * 16 * n
+    assert bench.polish_alg_bytes([n] * 3, inf, pm) == want / 2
+    fl = bench.projection_flops([n] * 3, inf)
+    rp = bench.projection_roofline("p", [n] * 3, inf, 2e-5)
+    assert rp["bound"] == "mfma" and rp["peak"] == 78.6 and rp["unit"] == "TFLOP/s"
+    assert rp["achieved"] == round(fl / 2e-5 / 1e12, 3) and rp["flops_per_launch"] == int(fl)
+    assert bench.projection_roofline("p", [n] * 3, inf, 2e-5, mixed=True)["peak"] == 2500.0

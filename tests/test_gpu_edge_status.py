@@ -36,12 +36,16 @@ def _seed_basis(X, H, T, m, precision):
     return ctx, bases, t0
 
 
+@pytest.mark.parametrize("split", [-1, 0])
 @pytest.mark.parametrize("precision,polish_m", [("fp64", 0), ("fp64", 6), ("mixed", 0)])
-def test_duplicated_basis_column_is_singular(X, precision, polish_m):
+def test_duplicated_basis_column_is_singular(X, precision, polish_m, split):
+    """split >= 0: the projection runs in launches of its own."""
     import torch
     H, T, m = 48, 100, 20
     prec = X.MIXED if precision == "mixed" else X.FP64
     ctx, bases, t0 = _seed_basis(X, H, T, m, prec)
+    if split >= 0:
+        ctx.set_projection_split(split)
     k = bases.header(0)["k"]
     assert k >= 2
     # column 1 := column 0 (the FP64 columns and the BF16 copy): V^T A' V has two equal rows
@@ -79,15 +83,20 @@ def test_duplicated_basis_column_is_singular(X, precision, polish_m):
     assert st == oracle.ESINGULAR and np.array_equal(x0, t0)
 
 
-@pytest.mark.parametrize("where", ["mt_seed", "mt_target", "mt_plain", "b_plain", "x0_target"])
-def test_non_finite_data_is_rejected(X, where):
+@pytest.mark.parametrize("where,split", [("mt_seed", -1), ("mt_target", -1), ("mt_plain", -1),
+                                         ("b_plain", -1), ("x0_target", -1), ("mt_target", 0),
+                                         ("x0_target", 0)])
+def test_non_finite_data_is_rejected(X, where, split):
     """One NaN (or Inf in x0) in a system's data: the system's status is XKP_EINVAL (no
-    iterations spent on it), while a finite system solved in the same launch converges."""
+    iterations spent on it), while a finite system solved in the same launch converges (split
+    >= 0: targets projected in launches of their own)."""
     import torch
     H, T, m = 32, 100, 16
     n = H * H
     dt = 1.0 / T
     ctx, bases, t0 = _seed_basis(X, H, T, m, X.FP64)
+    if split >= 0:
+        ctx.set_projection_split(split)
     bad = t64(t0).clone()
     good = t64(t0)
     mts = torch.stack([bad, good])

@@ -132,8 +132,9 @@ def mixed_target_setup(X, H, T, m, jitter, n_t=3, seed_precision=None):
     return ctx, bases, d, specs, mts
 
 
+@pytest.mark.parametrize("split", [-1, 0])
 @pytest.mark.parametrize("H,m", [(64, 40), (128, 60)])
-def test_mixed_projection_guess_matches_bf16_emulation(X, H, m):
+def test_mixed_projection_guess_matches_bf16_emulation(X, H, m, split):
     """x0 of the mixed target-Galerkin projection vs the same projection emulated on the CPU:
     A'V_k with the FP32 operator, both factors rounded to BF16, their products summed exactly
     (FP64), V_k^T r_base and the solve in FP64.  What remains between the two is the FP32
@@ -145,6 +146,8 @@ def test_mixed_projection_guess_matches_bf16_emulation(X, H, m):
     import torch
     T = 100
     ctx, bases, d, specs, mts = mixed_target_setup(X, H, T, m, jitter=1.0)
+    if split >= 0:   # the projection in launches of its own
+        ctx.set_projection_split(split)
     info = ctx.new_infos(len(specs))
     ctx.target_project_solve(d, len(specs), 1, bases.ptrs,
                              X.Context.params(m, tol=1e300, precision=X.MIXED), info)

@@ -201,10 +201,14 @@ def test_chain_grid28_full_matches_oracle(X):
     assert np.abs(np.array(its) - it_o).max() <= 2
 
 
-def test_zero_rhs_and_exact_start(X):
+@pytest.mark.parametrize("split", [-1, 0])
+def test_zero_rhs_and_exact_start(X, split):
+    """split >= 0: the target is projected in launches of its own."""
     import torch
     H, m = 16, 10
     ctx, bases, x, b, info = seed_on_gpu(X, H, 100, m, np.zeros(H * H))
+    if split >= 0:
+        ctx.set_projection_split(split)
     assert info["status"] == X.OK and info["iters"] == 0 and np.all(x == 0)
     assert bases.header(0)["k"] == 0
     # a target projected on an empty basis keeps x_base and still converges

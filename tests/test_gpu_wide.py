@@ -147,3 +147,35 @@ def test_projected_chain_on_wide_seeds(X):
     bound = steps * 1e-8 * max(np.linalg.norm(s0), np.linalg.norm(t0, axis=1).max())
     assert np.abs(cpu(ch.target_state) - mt_o).max() <= bound
     assert np.abs(cpu(ch.seed_state) - ms_o).max() <= bound
+
+
+def test_wide_seed_wait_gives_up_and_recovers(X):
+    """A zero wait limit (xkp_ctx_set_seed_wait) makes every spread-out workgroup give up at the
+    first exchange whose data has not arrived: the launch ends, the seed reports XKP_EDEVICE in
+    its info and basis header, and the same context then solves the seed normally once the
+    limit is back (the exchange area is re-tagged at every launch)."""
+    import torch
+    H, T, m = 128, 100, 40
+    n = H * H
+    ctx = X.Context(n, m, 1)
+    ctx.set_seed_width(1)
+    ms, _ = blob_pair(H, seed=100 + H)
+    b = torch.zeros(n, dtype=torch.float64, device=dev())
+    x = torch.zeros(n, dtype=torch.float64, device=dev())
+    d = X.pack_systems([X.SystemSpec(H, 1.0 / T, 0.5, t64(ms), b=b, x=x)], dev())
+    ctx.build_rhs(d, 1)
+    bases = X.Bases(1, n, m)
+    P = X.Context.params(m)
+    ctx.set_seed_wait(0)
+    info = ctx.new_infos(1)
+    ctx.seed_build(d, 1, bases.ptrs, P, info)
+    torch.cuda.synchronize()
+    inf = X.infos_to_numpy(info)[0]
+    assert inf["status"] == X.EDEVICE and bases.header(0)["status"] == X.EDEVICE
+    ctx.set_seed_wait(2000000)
+    info = ctx.new_infos(1)
+    ctx.seed_build(d, 1, bases.ptrs, P, info)
+    torch.cuda.synchronize()
+    _check_seed(X, H, T, m, ms, cpu(b), cpu(x), X.infos_to_numpy(info)[0], bases, 0)
+    with pytest.raises(X.XkpError):
+        ctx.set_seed_wait(-1)
