@@ -357,7 +357,12 @@ def mixed_leg(args, orc=None):
 def learned_leg(args):
     """64x64 learned-guess workload: training data from the method's own chain (seed + 4096
     targets x 100 timesteps), training on the GPU, then 1024 held-out targets solved by plain
-    GMRES, projection + polish and the learned guess behind residual gates 1e-6, 1e-2, 1e300."""
+    GMRES, projection + polish, the learned guess behind residual gates 1e-6, 1e-4, 1e-2 and
+    none, and the learned correction of the projection (a second network trained on the
+    projected guess's coordinate error, kept where it lowers the guess's residual).  Each leg
+    is compared with the projection (polish iterations, guess residual, throughput), and a
+    sample of held-out targets gets the smallest residual the seed subspace allows (the floor
+    no guess built from it can pass)."""
     import torch
     from paper_2511_17634_amd import learned, xkp
     from paper_2511_17634_amd.driver import Batch, Group
@@ -372,25 +377,30 @@ def learned_leg(args):
     e0 = np.stack([initial_state(t[0]) for t in ev])
     torch.cuda.synchronize()
     t_gen = time.perf_counter()
-    zeta, gen_ok = learned.generate(s0, t0, T, m)
+    zeta, zeta_p, gen_ok = learned.generate(s0, t0, T, m, with_projection=True)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     ctx = xkp.Context(4096, m, 1)
-    net = xkp.Net(ctx, m + 1, 512, learned.init_params(m + 1, np.random.default_rng(0)))
     imgs = torch.tensor(t0, dtype=torch.float64, device="cuda")
-    t_tr = time.perf_counter()
-    hist = learned.train(net, imgs, zeta, args.learned_epochs, 512, 2e-3)
-    torch.cuda.synchronize()
-    t_tr = time.perf_counter() - t_tr
-    legs, polish_m = {}, 0
+    nets, hists, t_tr = {}, {}, {}
+    for name, target in (("full", zeta), ("correction", zeta - zeta_p)):
+        nets[name] = xkp.Net(ctx, m + 1, 512, learned.init_params(m + 1, np.random.default_rng(0)))
+        t1 = time.perf_counter()
+        hists[name] = learned.train(nets[name], imgs, target, args.learned_epochs, 512, 2e-3)
+        torch.cuda.synchronize()
+        t_tr[name] = round(time.perf_counter() - t1, 2)
+    legs, infos, polish_m = {}, {}, 0
     for name, kw in (("project", dict(method="project")), ("plain", dict(method="plain")),
                      ("learned_gate_1e-6", dict(method="learned", gate=1e-6)),
                      ("learned_gate_1e-4", dict(method="learned", gate=1e-4)),
                      ("learned_gate_1e-2", dict(method="learned", gate=1e-2)),
-                     ("learned_gate_inf", dict(method="learned", gate=1e300))):
+                     ("learned_gate_inf", dict(method="learned", gate=1e300)),
+                     ("learned_correction", dict(method="learned", gate=1e300, correction=True))):
         if kw["method"] == "learned":
+            net = nets["correction" if kw.get("correction") else "full"]
             kw = dict(method="learned", polish_m=polish_m,
-                      learned=dict(params=net.params, scale=1.0, gate=kw["gate"]))
+                      learned=dict(params=net.params, scale=1.0, gate=kw["gate"],
+                                   correction=bool(kw.get("correction"))))
         b = Batch([Group(64, s0[None], e0[:, None])], T, m, reorth=args.reorth, **kw)
         if kw["method"] == "project" and not args.no_tune:
             polish_m = b.autotune().polish_m
@@ -398,21 +408,50 @@ def learned_leg(args):
             b.autotune()
         r = time_chain(b, args, 1, 1, not args.eager)
         _, ti = b.all_infos()
+        infos[name] = ti.copy()
         legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
                       "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                       "mean_iters": round(r["iters_mean"], 2),
                       "median_guess_residual": float(f"{np.median(ti['guess_res']):.4g}"),
-                      "accepted": round(float((ti["guess_source"] == 2).mean()), 4),
+                      "mean_guess_residual": float(f"{np.mean(ti['guess_res']):.4g}"),
+                      "accepted": round(float((ti["guess_source"] >= 2).mean()), 4),
                       "polish_m": r["polish_m"], "verified": r["ok"] and gen_ok}
+        if name == "project":
+            # the floor of the seed subspace on a sample: 16 held-out targets at 4 timesteps
+            picks, steps = list(range(0, b.N, b.N // 16))[:16], (0, 9, 49, 99)
+            floor = learned.span_floor(b, picks, steps)
         print(f"# learned workload {name}: {r['per_chain_s'] * 1e3:.1f} ms/chain, "
               f"mean iters {r['iters_mean']:.1f}, accepted {legs[name]['accepted']:.3f}",
               file=sys.stderr, flush=True)
         del b
+    # every leg against the projection, target by target and timestep by timestep
+    tp = infos["project"]
+    for name, v in legs.items():
+        if name == "project":
+            continue
+        ti = infos[name]
+        v["vs_projection"] = {
+            "iters_delta": round(float(ti["iters"].mean() - tp["iters"].mean()), 3),
+            "value_ratio": round(v["value"] / legs["project"]["value"], 4),
+            "guess_better_frac": round(float((ti["guess_res"] < tp["guess_res"]).mean()), 4)}
+    keys = sorted(floor)
+    fl = np.array([floor[q] for q in keys])
+    at = lambda inf: np.array([inf["guess_res"][t, i] for t, i in keys])
+    sample = {"targets": len({i for _, i in keys}), "timesteps": sorted({t + 1 for t, _ in keys}),
+              "median_floor": float(f"{np.median(fl):.4g}"),
+              "min_floor": float(f"{fl.min():.4g}"),
+              "median_projection": float(f"{np.median(at(tp)):.4g}"),
+              "median_learned": float(f"{np.median(at(infos['learned_gate_inf'])):.4g}"),
+              "median_correction": float(f"{np.median(at(infos['learned_correction'])):.4g}"),
+              "note": "min over a of ||b - A V a|| / ||b|| on the seed basis V of that timestep "
+                      "(A, b the target's): no guess x_base + V a can have a lower residual, so "
+                      "a gate below the floor accepts nothing"}
     return {"workload": cfg.name, "train_targets": len(t0), "eval_targets": len(e0),
             "timesteps": T, "m": m, "unit": "target systems/s",
-            "generate_s": round(t_gen, 2), "train_s": round(t_tr, 2),
-            "epochs": args.learned_epochs, "loss_per_epoch": [float(f"{v:.4g}") for v in hist],
-            "legs": legs}
+            "generate_s": round(t_gen, 2), "train_s": t_tr,
+            "epochs": args.learned_epochs,
+            "loss_per_epoch": {k: [float(f"{v:.4g}") for v in h] for k, h in hists.items()},
+            "subspace_floor": sample, "legs": legs}
 
 
 def copy_gbs():

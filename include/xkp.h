@@ -133,7 +133,8 @@ typedef struct {
     double res_est;       /* last Givens residual estimate, relative                        */
     double res_true;      /* final ||b - A x||_2 / ||b||_2 computed in FP64                  */
     double guess_res;     /* target: relative residual of the starting guess x0            */
-    int32_t guess_source; /* target: 0 x_base, 1 projection onto the seed basis, 2 learned  */
+    int32_t guess_source; /* target: 0 x_base, 1 projection onto the seed basis, 2 learned,
+                             3 projection corrected by the learned prediction                */
     int32_t pad;
 } xkp_info;
 
@@ -303,6 +304,23 @@ xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *
                              int32_t n_bases, const void *const *bases, const xkp_params *params,
                              const float *alpha, int32_t alpha_ld, double alpha_scale,
                              double gate, xkp_info *infos);
+
+/*
+ * Learned correction of the projection: each target is first projected as in xkp_target_project_solve (params->mode, which must not be
+ * XKP_PROJ_NONE: XKP_EINVAL), giving x0_P = x_base + V_k a_P; the prediction alpha + i*alpha_ld
+ * (k+1 FP32 values) is then read as a correction of the projected guess's residual
+ * coordinates: x0_C = x0_P + V_k d with d = argmin || beta * alpha_scale * alpha - Hbar_k d ||
+ * (Givens least squares; train it on basis coordinates of x* minus those of x0_P, kind 1 of
+ * xkp_basis_coeffs).  The polish starts from x0_C (info.guess_source = 3) when its FP64
+ * relative residual is <= gate and below x0_P's, else from x0_P (guess_source 1): the
+ * correction never starts the polish from a worse guess than the projection.  A projected
+ * system that is singular (XKP_ESINGULAR) keeps x_base uncorrected.  One persistent launch.
+ */
+xkp_status xkp_learned_correction_solve(xkp_ctx *ctx, int32_t n_targets,
+                                        const xkp_system *targets, int32_t n_bases,
+                                        const void *const *bases, const xkp_params *params,
+                                        const float *alpha, int32_t alpha_ld, double alpha_scale,
+                                        double gate, xkp_info *infos);
 
 /* kind 0: alpha[i][c] = v_c . x_i (FP64) for c < k of the basis bases[systems[i].basis_id], 0
  * for k <= c < m_out (1 <= m_out <= 64): the coordinates of systems[i].x in the seed subspace.

@@ -433,6 +433,29 @@ xkp_status xkp_learned_solve(xkp_ctx *ctx, int32_t n_targets, const xkp_system *
                              nullptr));
 }
 
+xkp_status xkp_learned_correction_solve(xkp_ctx *ctx, int32_t n_targets,
+                                        const xkp_system *targets, int32_t n_bases,
+                                        const void *const *bases, const xkp_params *params,
+                                        const float *alpha, int32_t alpha_ld, double alpha_scale,
+                                        double gate, xkp_info *infos) {
+    int nmax = 0, rmax = 0;
+    const Variant *v = nullptr;
+    xkp_status st = check_call(ctx, n_targets, targets, params, &nmax, &rmax, &v);
+    if (st != XKP_OK) return st;
+    if (params->mode == XKP_PROJ_NONE) return XKP_EINVAL;
+    if (n_targets > 0 && (!infos || !alpha || alpha_ld < 1 || n_bases < 1 || !bases))
+        return XKP_EINVAL;
+    if (!(gate >= 0.0) || !(alpha_scale == alpha_scale)) return XKP_EINVAL;
+    if (n_targets == 0) return XKP_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
+    const int grid = solve_grid(ctx, n_targets);
+    const int flags = xkp::kLearned | xkp::kCorrection | xkp::kTarget | xkp::kRegBasis;
+    return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), targets, n_targets,
+                             *params, flags, n_bases, bases, nullptr, infos, ctx->ws, ctx->L,
+                             nmax, ctx->queue, xkp::Learned{alpha, alpha_ld, alpha_scale, gate},
+                             nullptr));
+}
+
 xkp_status xkp_basis_coeffs(xkp_ctx *ctx, int32_t n_sys, const xkp_system *systems,
                             int32_t n_bases, const void *const *bases, int32_t m_out,
                             int32_t kind, double *alpha) {

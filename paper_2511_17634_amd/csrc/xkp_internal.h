@@ -36,8 +36,9 @@ enum GmresFlags {
     kLearned = 8,      // try the learned guess first; project only if it fails the gate
     kDcgs = 16,        // seeds: the kept cycle by DCGS2 (set by the launcher when the LDS fits)
     kRegBasis = 32,    // discarded cycles with the basis in registers where it fits
-    kPreProjected = 64 // targets projected by the projection launches (xkp_project.hip): x holds
-                       // x0, pre[i] the projection's status
+    kPreProjected = 64,   // targets projected by the projection launches (xkp_project.hip): x
+                          // holds x0, pre[i] the projection's status
+    kCorrection = 128     // with kLearned: the prediction corrects the projected guess
 };
 
 // Learned-guess inputs of a solve launch: target i's predicted residual coordinates at

@@ -1749,6 +1749,25 @@ __device__ __noinline__ void gmres_call(xkp_system s, xkp_params P, int flags, i
 // s.x.  Returns ||b - A x0|| / ||b|| in FP64 (0 when b = 0), or -1 when the target has no usable
 // basis or the least-squares problem is singular (s.x may then hold a partial guess; the caller
 // falls back).  LDS: the projection layout (matrix at the base, vectors after nregion).
+// ||b - A' x|| / ||b|| (FP64 operator; 0 when b = 0) of the iterate x whose rows the threads
+// hold in xr; vbuf is the zero-padded LDS vector copy (cleared pads).
+template <int R>
+__device__ __forceinline__ double guess_rel_residual(const xkp_system &s, const Coef &C,
+                                                    const OpConst &o, const double (&xr)[R],
+                                                    double *vbuf, BlockRed &br) {
+    const int n = s.H * s.H;
+    double w[R], b[R];
+    store_rows_lds<R>(vbuf, xr);
+    lds_barrier();
+    stencil_lds<R>(vbuf, C, o, w);
+    load_rows<R>(s.b, n, b);
+#pragma unroll
+    for (int q = 0; q < R; ++q) w[q] = b[q] - w[q];
+    double two[2] = {dot_rows<R>(w, w), dot_rows<R>(b, b)};
+    br.sum_multi<2>(two);
+    return two[1] > 0.0 ? sqrt(two[0]) / sqrt(two[1]) : 0.0;
+}
+
 template <int R>
 __device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const void *const *bases,
                                             xkp_params P0, const float *a, int ka, double scale,
@@ -1798,7 +1817,7 @@ __device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const vo
         lds_barrier();
         singular = pivl[kMMax - 1] != 0;
     }
-    double xr[R], w[R];
+    double xr[R];
     if (s.x0) {
         load_rows<R>(s.x0, n, xr);
     } else {
@@ -1817,17 +1836,45 @@ __device__ __noinline__ double learned_call(xkp_system s0, int n_bases, const vo
     for (int t = tid; t < nlds; t += kNT) lds[t] = 0.0;
     lds_barrier();
     store_rows<R>(s.x, n, xr);
-    store_rows_lds<R>(vbuf, xr);
-    lds_barrier();
-    stencil_lds<R>(vbuf, C, o, w);
-    load_rows<R>(s.b, n, xr);
-#pragma unroll
-    for (int q = 0; q < R; ++q) w[q] = xr[q] - w[q];
-    double two[2] = {dot_rows<R>(w, w), dot_rows<R>(xr, xr)};
-    br.sum_multi<2>(two);
+    const double rel = guess_rel_residual<R>(s, C, o, xr, vbuf, br);
     __syncthreads();   // the polish reads rows of x0 written by other threads, and reuses LDS
     if (singular) return -1.0;
-    return two[1] > 0.0 ? sqrt(two[0]) / sqrt(two[1]) : 0.0;
+    return rel;
+}
+
+
+
+// The projected guess in s.x: its rows copied to `stash` (device workspace) and its FP64
+// relative residual returned (the coefficients were built by the projection).
+template <int R>
+__device__ __noinline__ double stash_guess_call(xkp_system s0, Coef C0, double *stash, int nlds) {
+    const xkp_system s = uni(s0);
+    const Coef C = uni(C0);
+    stash = uni(stash);
+    nlds = uni(nlds);
+    const int n = s.H * s.H;
+    double *lds = xkp_dyn_lds;
+    double *vbuf = lds + (nlds - kNT * R) / 2;
+    BlockRed br{lds + nlds, 0};
+    for (int t = threadIdx.x; t < nlds + 2 * kRedSlots * kNW; t += kNT) lds[t] = 0.0;
+    lds_barrier();
+    double xr[R];
+    load_rows<R>(s.x, n, xr);
+    store_rows<R>(stash, n, xr);
+    const double rel = guess_rel_residual<R>(s, C, op_const(s), xr, vbuf, br);
+    __syncthreads();
+    return rel;
+}
+
+// s.x = the stashed rows (a rejected correction of the projected guess is undone).
+template <int R>
+__device__ __noinline__ void unstash_guess_call(xkp_system s0, const double *stash) {
+    const xkp_system s = uni(s0);
+    stash = uni(stash);
+    double xr[R];
+    load_rows<R>(stash, s.H * s.H, xr);
+    store_rows<R>(s.x, s.H * s.H, xr);
+    __syncthreads();   // the polish reads rows written by other threads
 }
 
 template <int R, bool PROJ>
@@ -1846,6 +1893,33 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
         if (pre0 != XKP_OK && pre0 != XKP_ESINGULAR) return;
         pre = pre0;
         flags |= kStartFromX;
+    } else if ((flags & kLearned) && (flags & kCorrection)) {
+        if constexpr (PROJ) {
+            // the projection first; then the network's correction of the projected coordinates,
+            // kept when its FP64 residual passes the gate and is below the projected guess's
+            pre = P.precision == XKP_MIXED
+                      ? project_call<R, true>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds,
+                                              nbuf, nregion)
+                      : project_call<R, false>(s, info, n_bases, bases, P, C, slot + Lw.w, nlds,
+                                               nbuf, nregion);
+            if (pre == XKP_EINVAL) return;
+            project = false;
+            flags |= kStartFromX;
+            if (pre == XKP_OK) {
+                double *stash = slot + Lw.w;
+                const double rel_p = stash_guess_call<R>(s, C, stash, nlds);
+                for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;
+                lds_barrier();
+                xkp_system sc = s;
+                sc.x0 = s.x;   // the correction starts from the projected guess
+                const double rel =
+                    learned_call<R>(sc, n_bases, bases, P, al, lg.ld, lg.scale, C, nlds, nregion);
+                if (rel >= 0.0 && rel <= lg.gate && rel < rel_p)
+                    gsrc = 3;
+                else
+                    unstash_guess_call<R>(s, stash);
+            }
+        }
     } else if (flags & kLearned) {
         // the network's guess, kept when its FP64 residual passes the gate
         for (int t = threadIdx.x; t < nlds; t += kNT) lds[t] = 0.0;

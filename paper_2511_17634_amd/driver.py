@@ -53,7 +53,9 @@ class Batch:
         """method: "project" (projection + polish), "plain" (GMRES from x_base) or "learned"
         (the network's guess behind the residual gate, projection as fallback; `learned` =
         dict(params=FP32 parameters of a network with m + 1 outputs, scale=output scale,
-        gate=residual gate), single 64x64 group of one channel).  with_seeds: also solve the
+        gate=residual gate, correction=False), single 64x64 group of one channel; with
+        correction=True the network corrects the projected guess instead, kept when it lowers
+        the guess's residual).  with_seeds: also solve the
         seeds with plain targets.  reorth: "auto" (two Gram-Schmidt passes only while a seed's
         basis is kept) or "always".  accumulate: per-source column count a of the image-cycle
         subspace expansion: the groups (one grid size, one channel) are consecutive blocks of
@@ -265,8 +267,10 @@ class Batch:
         if self.learned is not None:
             t = self.step_no % self.T
             self.net.forward(self.images, self.steps_all[t], self.alpha_l)
-            c.learned_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, self.alpha_l,
-                            self.m + 1, self.learned["scale"], self.learned["gate"], inf_t)
+            solve = (c.learned_correction_solve if self.learned.get("correction")
+                     else c.learned_solve)
+            solve(self.tgt_desc[par], self.N, self.S, bases, self.params, self.alpha_l,
+                  self.m + 1, self.learned["scale"], self.learned["gate"], inf_t)
         else:
             c.target_project_solve(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         if events is not None:

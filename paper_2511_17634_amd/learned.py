@@ -9,6 +9,10 @@ A_seed V_n = V_{n,k+1} Hbar_n, an error in zeta is (for targets close to the see
 the guess's relative residual, so the squared loss measures what the guess is judged by, and
 the solve recovers alpha by the Hessenberg least-squares problem.  zeta* is order one (its first
 entry is about ||b_t|| / ||b_seed||), so no further scaling is applied.
+
+The correction variant learns zeta* - zeta_P instead, zeta_P the coordinates of the target's
+projected guess on the same basis (xkp_learned_correction_solve adds the prediction to the
+projection and keeps it only where it lowers the guess's residual).
 """
 from __future__ import annotations
 
@@ -31,21 +35,39 @@ def init_params(k, rng):
     return np.concatenate(parts).astype(np.float32)
 
 
-def generate(seed_m0, target_m0, T, m, device=0):
+def generate(seed_m0, target_m0, T, m, device=0, with_projection=False):
     """Run the chain (seeds with kept bases, targets by plain GMRES to 1e-8) and collect
     zeta*[t][i] = Hbar_{t+1} V_{t+1}^T x*_{i,t+1} / beta_{t+1} (float64 device tensor
-    (T, N, m + 1))."""
+    (T, N, m + 1)).  with_projection: also the same coordinates of each target's
+    target-Galerkin guess x0_P on the same basis (the correction target is zeta* - zeta_P);
+    returns (zeta*, zeta_P, ok) then, else (zeta*, ok)."""
     import torch
     gr = Group(64, np.asarray(seed_m0).reshape(1, -1), np.asarray(target_m0).reshape(-1, 1, 4096))
     b = Batch([gr], T, m, method="plain", with_seeds=True, pipeline=False, device=device)
     alpha = torch.empty((T, b.N, m + 1), dtype=torch.float64, device=b.dev)
+    alpha_p = torch.empty_like(alpha) if with_projection else None
+    if with_projection:
+        # the projected guess of each target into a scratch iterate: the polish stops before
+        # its first step (tolerance 1e300)
+        scratch = torch.zeros_like(b.mt[0])
+        pdesc = [b._desc(b.tgt_sys, b.mt, b.bt, par, x_from=scratch) for par in (0, 1)]
+        pparams = xkp.Context.params(m, tol=1e300, mode=xkp.TARGET_GALERKIN)
+        pinf = b.ctx.new_infos(b.N)
+
+    def hook(par, bases, t):
+        b.ctx.basis_coeffs(b.tgt_desc[par], b.N, b.S, bases, m + 1, alpha[t], kind=1)
+        if with_projection:
+            b.ctx.target_project_solve(pdesc[par], b.N, b.S, bases, pparams, pinf)
+            b.ctx.basis_coeffs(pdesc[par], b.N, b.S, bases, m + 1, alpha_p[t], kind=1)
+
     b.reset()
     for t in range(T):
-        b.step(after_targets=lambda par, bases, t=t: b.ctx.basis_coeffs(
-            b.tgt_desc[par], b.N, b.S, bases, m + 1, alpha[t], kind=1))
+        b.step(after_targets=lambda par, bases, t=t: hook(par, bases, t))
     s_inf, t_inf = b.all_infos()
     ok = bool((s_inf["status"] == 0).all() and (t_inf["status"] == 0).all())
     torch.cuda.synchronize()
+    if with_projection:
+        return alpha, alpha_p, ok
     return alpha, ok
 
 
@@ -76,3 +98,44 @@ def train(net, images, alpha_star, epochs, batch, lr, seed=0, log=None):
         if log:
             log(f"epoch {ep}: mean loss {hist[-1]:.5f}")
     return hist
+
+
+def span_floor(b, picks, steps):
+    """The smallest relative residual the seed subspace allows each picked target of a
+    one-group chain b at the given timesteps, min_a ||b' - A' V a|| / ||b'|| (A', b' the
+    target's operator and right-hand side, V the seed's kept basis at that step): A'V formed by
+    the library's operator (xkp_apply, one system per basis column), the least-squares problem
+    solved on the GPU in FP64.  Runs one eager chain; returns {(t, i): floor}."""
+    import torch
+    H = b.groups[0].H
+    n = H * H
+    out = {}
+
+    def hook(par, bases, t):
+        if t not in steps:
+            return
+        torch.cuda.synchronize(b.dev)
+        for i in picks:
+            _, off, bid = b.tgt_sys[i]
+            j = par * b.S + bid
+            k = b.bases.header(j)["k"]
+            if k < 1:
+                continue
+            V = b.bases.V(j)
+            W = torch.empty((k, n), dtype=torch.float64, device=b.dev)
+            a = np.zeros(k, dtype=xkp.SYSTEM_DTYPE)
+            mt = b.mt[par].data_ptr() + 8 * off
+            bp = b.bt.data_ptr() + 8 * off
+            for c in range(k):
+                a[c] = (H, 0, b.dt, b.g, mt, 0, 0, bp, V[:, c].data_ptr(), W[c].data_ptr())
+            d = torch.from_numpy(a.view(np.uint8).copy()).to(b.dev)
+            b.ctx.apply(d, k)
+            rhs = b.bt[off:off + n]
+            sol = torch.linalg.lstsq(W.T, rhs[:, None]).solution
+            out[(t, i)] = float(torch.linalg.norm(rhs - W.T @ sol[:, 0]) / torch.linalg.norm(rhs))
+
+    b.reset()
+    for t in range(b.T):
+        b.step(after_targets=lambda par, bases, t=t: hook(par, bases, t))
+    torch.cuda.synchronize(b.dev)
+    return out

@@ -103,6 +103,7 @@ def load():
                                      ct.c_float, ct.c_float, ct.c_float]
         lib.xkp_learned_solve.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.POINTER(Params),
                                           P, ct.c_int32, ct.c_double, ct.c_double, P]
+        lib.xkp_learned_correction_solve.argtypes = lib.xkp_learned_solve.argtypes
         lib.xkp_basis_coeffs.argtypes = [P, ct.c_int32, P, ct.c_int32, P, ct.c_int32, ct.c_int32,
                                          P]
         lib.xkp_target_project_solve_noalloc.argtypes = [ct.c_int, P, ct.c_int32, P, ct.c_int32,
@@ -117,7 +118,8 @@ def load():
                   "xkp_learned_solve", "xkp_basis_coeffs", "xkp_ctx_set_launch",
                   "xkp_target_project_solve_noalloc", "xkp_ctx_set_seed_width",
                   "xkp_ctx_set_seed_wait", "xkp_ctx_set_projection_split",
-                  "xkp_ctx_set_timing", "xkp_ctx_last_timing"):
+                  "xkp_ctx_set_timing", "xkp_ctx_last_timing",
+                  "xkp_learned_correction_solve"):
             getattr(lib, f).restype = ct.c_int
         _lib = lib
     return _lib
@@ -343,6 +345,14 @@ class Context:
         _check(load().xkp_learned_solve(self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs),
                                         ct.byref(params), _ptr(alpha), alpha_ld, alpha_scale,
                                         gate, _ptr(infos)), "xkp_learned_solve")
+
+    def learned_correction_solve(self, systems, n_sys, n_bases, bases_ptrs, params, alpha,
+                                 alpha_ld, alpha_scale, gate, infos):
+        """Projection, then the predicted correction of its residual coordinates (times
+        alpha_scale), kept when its residual is <= gate and below the projected guess's."""
+        _check(load().xkp_learned_correction_solve(
+            self._h, n_sys, _ptr(systems), n_bases, _ptr(bases_ptrs), ct.byref(params),
+            _ptr(alpha), alpha_ld, alpha_scale, gate, _ptr(infos)), "xkp_learned_correction_solve")
 
     def basis_coeffs(self, systems, n_sys, n_bases, bases_ptrs, m_out, alpha, kind=0):
         """kind 0: alpha[i][c] = v_c . x_i on each system's seed basis; kind 1: the residual

@@ -1,6 +1,9 @@
 """GPU parity of the learned-guess solve path: subspace coordinates V^T x, the guess
 x0_L = x_base + V (scale alpha), the residual gate, and the fallback to the projection path (which
-must reproduce xkp_target_project_solve exactly)."""
+must reproduce xkp_target_project_solve exactly); the learned correction of the projection (a
+zero correction is the projection bit for bit, the exact correction gives V V^T x*, a
+correction is kept only where it lowers the guess's residual); the smallest residual the seed
+subspace allows; and the trained pipeline against the projection."""
 import numpy as np
 import pytest
 
@@ -131,14 +134,83 @@ def test_learned_guess_gate_and_fallback(X):
             assert i2[i]["guess_source"] == src
 
 
+def test_learned_correction_zero_exact_and_kept_only_when_better(X):
+    """xkp_learned_correction_solve: with a zero correction the guess is the projection's (not
+    kept: guess_source 1) and the call equals xkp_target_project_solve bit for bit; with the
+    exact correction (coordinates of x* minus those of the projected guess) the corrected guess
+    is V V^T x*, kept (guess_source 3) exactly where its FP64 residual is below the projected
+    guess's, and a gate of 0 keeps none."""
+    import torch
+    H, T, m, N = 64, 100, 40, 4
+    ctx, bases, d, specs, mts = setup(X, H, T, m, N)
+    k = bases.header(0)["k"]
+    V = cpu(bases.V(0))[:, :k]
+    P0 = X.Context.params(m, tol=1e300)
+    # the projected guesses and their coordinates
+    info_p = ctx.new_infos(N)
+    ctx.target_project_solve(d, N, 1, bases.ptrs, P0, info_p)
+    torch.cuda.synchronize()
+    ip = X.infos_to_numpy(info_p).copy()
+    xp = [cpu(s_.x).copy() for s_ in specs]
+    zp = torch.empty((N, 48), dtype=torch.float64, device=dev())
+    ctx.basis_coeffs(d, N, 1, bases.ptrs, 48, zp, kind=1)
+    # zero correction
+    zero = torch.zeros((N, 48), dtype=torch.float32, device=dev())
+    info = ctx.new_infos(N)
+    ctx.learned_correction_solve(d, N, 1, bases.ptrs, P0, zero, 48, 1.0, 1e300, info)
+    torch.cuda.synchronize()
+    i0 = X.infos_to_numpy(info)
+    assert np.all(i0["guess_source"] == 1)
+    for i in range(N):
+        assert np.array_equal(cpu(specs[i].x), xp[i])
+    assert np.array_equal(i0["guess_res"], ip["guess_res"])
+    # the exact correction: coordinates of x* minus those of x0_P (kind 1, FP64 on the GPU)
+    xstar = []
+    for i, mt in enumerate(mts):
+        At = oracle.Operator(H, 1.0 / T, 0.5, mt)
+        xstar.append(oracle.banded_solve(At, oracle.rhs(At, mt))[0])
+        specs[i].x.copy_(torch.from_numpy(xstar[-1]))
+    zs = torch.empty((N, 48), dtype=torch.float64, device=dev())
+    ctx.basis_coeffs(d, N, 1, bases.ptrs, 48, zs, kind=1)
+    corr = (zs - zp).to(torch.float32)
+    for gate, keep_any in ((1e300, True), (0.0, False)):
+        info = ctx.new_infos(N)
+        ctx.learned_correction_solve(d, N, 1, bases.ptrs, P0, corr, 48, 1.0, gate, info)
+        torch.cuda.synchronize()
+        ic = X.infos_to_numpy(info)
+        for i in range(N):
+            At = oracle.Operator(H, 1.0 / T, 0.5, mts[i])
+            bt = oracle.rhs(At, mts[i])
+            best = V @ (V.T @ xstar[i])
+            # kept exactly where it beats the projected guess (FP32 correction: rounding only)
+            better = oracle.residual(At, bt, best) < ip[i]["guess_res"] * (1 - 1e-6)
+            x0 = cpu(specs[i].x)
+            if keep_any and better:
+                assert ic[i]["guess_source"] == 3, i
+                assert np.abs(x0 - best).max() <= 1e-6 * np.abs(best).max(), i
+                assert ic[i]["guess_res"] < ip[i]["guess_res"]
+                assert abs(ic[i]["guess_res"] - oracle.residual(At, bt, x0)) <= \
+                    1e-9 * ic[i]["guess_res"]
+            elif not keep_any:
+                assert ic[i]["guess_source"] == 1 and np.array_equal(x0, xp[i]), i
+            else:
+                assert ic[i]["guess_res"] <= ip[i]["guess_res"], i
+    # the projection modes only: plain GMRES has nothing to correct
+    with pytest.raises(X.XkpError):
+        ctx.learned_correction_solve(d, N, 1, bases.ptrs, X.Context.params(m, mode="none"),
+                                     corr, 48, 1.0, 1e300, ctx.new_infos(N))
+
+
 def test_learned_pipeline_trains_and_falls_back(X):
     """The whole learned-guess pipeline at a small size (64x64, m = 40, T = 10): training data
     from the method's own chain, training on the GPU, then held-out targets solved with the
-    learned guess behind the gate.  What training gains is measured against the untrained
-    network (held-out guess residual), and what the learned guess gains over the method without
-    it against the projection chain: printed, with the gate keeping every result exact.  A gate
-    of 1e-6 rejects every learned guess here, and the chain then equals the projection chain
-    bit for bit."""
+    learned guess behind the gate, and with the learned correction of the projection.  What
+    training gains is asserted against the untrained network (held-out guess residual); what
+    the learned guess and the correction gain or lose against the projection (the method
+    without the network) is asserted and printed: guess residuals timestep by timestep, polish
+    iterations; the seed subspace's residual floor lies below every guess built from it.  A
+    gate of 1e-6 rejects every learned guess here, and the chain then equals the projection
+    chain bit for bit."""
     import torch
     from oracle import cnn
     from paper_2511_17634_amd import learned
@@ -182,12 +254,34 @@ def test_learned_pipeline_trains_and_falls_back(X):
             if gate == 1e300:
                 assert np.all(ti["guess_source"] == 2)
     tr, un = res[("trained", 1e300)], res[("untrained", 1e300)]
-    print(f"\nheld-out guess residual: trained {np.median(tr['guess_res']):.3g}, untrained "
-          f"{np.median(un['guess_res']):.3g}, projection {np.median(tp['guess_res']):.3g}; "
-          f"mean polish iterations: learned {tr['iters'].mean():.1f}, projection "
-          f"{tp['iters'].mean():.1f}; accepted at gate 1e-2: "
-          f"{(res[('trained', 1e-2)]['guess_source'] == 2).mean():.2f}")
     assert np.median(tr["guess_res"]) < 0.5 * np.median(un["guess_res"])
+    # the correction network: trained on the projected guess's coordinate error
+    alpha2, alpha_p, ok2 = learned.generate(s0, t0, T, m, with_projection=True)
+    assert ok2 and torch.equal(alpha2, alpha)
+    netc = X.Net(ctx, m + 1, 128, theta0)
+    histc = learned.train(netc, imgs, alpha - alpha_p, 6, 128, 2e-3)
+    assert histc[-1] < histc[0]
+    bc, tc = chain(method="learned",
+                   learned=dict(params=netc.params, scale=1.0, gate=1e300, correction=True))
+    assert np.all(np.isin(tc["guess_source"], (1, 3)))
+    # against the projection, the method without the network: both chains solve every step to
+    # 1e-8, so the guesses compare timestep by timestep.  The correction is kept only where it
+    # lowers the residual: never worse than the projection beyond the chains' 1e-8 differences
+    assert np.all(tc["guess_res"] <= tp["guess_res"] * (1 + 1e-6) + 1e-12)
+    assert tc["iters"].mean() <= tp["iters"].mean() + 0.2
+    # the seed subspace's floor on a sample: below every guess built from it
+    floor = learned.span_floor(bp, [0, 16], (0, 4, 9))
+    for (t, i), f in floor.items():
+        assert f <= tp["guess_res"][t, i] * (1 + 1e-9)
+        assert f <= tr["guess_res"][t, i] * (1 + 1e-9)
+        assert f <= tc["guess_res"][t, i] * (1 + 1e-9)
+    print(f"\nheld-out guess residual (median): trained {np.median(tr['guess_res']):.3g}, "
+          f"untrained {np.median(un['guess_res']):.3g}, correction "
+          f"{np.median(tc['guess_res']):.3g}, projection {np.median(tp['guess_res']):.3g}, "
+          f"subspace floor {np.median(list(floor.values())):.3g}; mean polish iterations: "
+          f"learned {tr['iters'].mean():.2f}, correction {tc['iters'].mean():.2f} (kept "
+          f"{(tc['guess_source'] == 3).mean():.2f}), projection {tp['iters'].mean():.2f}; "
+          f"accepted at gate 1e-2: {(res[('trained', 1e-2)]['guess_source'] == 2).mean():.2f}")
 
 
 def test_learned_chain_graph_replays_match_eager(X):
