@@ -257,7 +257,7 @@ def uneven_leg(args):
     for name, method in (("project", "project"), ("plain", "plain")):
         b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin",
                   reorth=args.reorth)
-        tu = None if args.no_tune else b.autotune()
+        tu = None if args.no_tune else tune(b, args)
         r = time_chain(b, args, args.uneven_steps, 1, graph)
         lm = target_call_ms(b)
         ro, rp, ph = target_rooflines(b, f"{b.N} systems of three sizes per launch", r,
@@ -304,7 +304,7 @@ def mixed_leg(args, orc=None):
                                ("plain_fp64", "plain", xkp.FP64)):
         b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec,
                   reorth=args.reorth)
-        tu = None if args.no_tune else b.autotune()
+        tu = None if args.no_tune else tune(b, args)
         r = time_chain(b, args, args.mixed_steps, 1, graph)
         lm = target_call_ms(b)
         mixed = prec == xkp.MIXED
@@ -326,7 +326,7 @@ def mixed_leg(args, orc=None):
                     "seed_waves": None if tu is None or b.seed_tuning is None
                     else b.seed_tuning.waves,
                     "mean_guess_residual": round(r["guess_res_mean"], 4),
-                    "seed_call_ms": sms,
+                    "seed_call_ms": sms, "seeds_redone": r["seeds_redone"],
                     "roofline": ro, **ph}
         if rp is not None:
             mx[name]["roofline_projection"] = rp
@@ -403,9 +403,9 @@ def learned_leg(args):
                                    correction=bool(kw.get("correction"))))
         b = Batch([Group(64, s0[None], e0[:, None])], T, m, reorth=args.reorth, **kw)
         if kw["method"] == "project" and not args.no_tune:
-            polish_m = b.autotune().polish_m
+            polish_m = tune(b, args).polish_m
         elif kw["method"] == "plain" and not args.no_tune:
-            b.autotune()
+            tune(b, args)
         r = time_chain(b, args, 1, 1, not args.eager)
         _, ti = b.all_infos()
         infos[name] = ti.copy()
@@ -494,7 +494,7 @@ def cycle_leg(args):
                          ("plain", groups, dict(method="plain"))):
         b = Batch(gr, T, m, reorth=args.reorth, **kw)
         if not args.no_tune:
-            b.autotune()
+            tune(b, args)
         r = time_chain(b, args, 1, 1, not args.eager)
         _, ti = b.all_infos()
         legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
@@ -535,7 +535,7 @@ def cluster_leg(args):
                      ("one_seed", [Group(H, imgs[0][None], imgs[1:][:, None])])):
         b = Batch(gr, T, m, reorth=args.reorth)
         if not args.no_tune:
-            b.autotune()
+            tune(b, args)
         r = time_chain(b, args, 1, 1, not args.eager)
         legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
                       "ms_per_chain": round(r["per_chain_s"] * 1e3, 2), "targets": b.N,
@@ -560,7 +560,7 @@ def picard_leg(args):
     for K in (2, 3):
         b = Chain(H, T, m, s0, t0, picard=K, reorth=args.reorth)
         if not args.no_tune:
-            b.autotune()
+            tune(b, args)
         r = time_chain(b, args, 1, 1, not args.eager)
         _, pt = b.picard_infos()
         ok = r["ok"] and bool((pt["status"] == 0).all() and (pt["res_true"] <= args.tol).all())
@@ -613,6 +613,15 @@ def epilogue_leg(args):
                          "bytes_per_launch": byts}}
 
 
+def tune(b, args):
+    """The library's autotuners on a driver Batch (see Batch.autotune); with --split off the
+    projection then stays inside the solve launch."""
+    t = b.autotune()
+    if args.split == "off":
+        b.ctx.set_projection_split(-1)
+    return t
+
+
 def time_chain(b, args, steps, warmup, graph=True, verify_all=True):
     """Time `steps` full chains (reset + T timesteps) of a driver Batch, replayed from one
     captured graph (or enqueued eagerly); then verify every solve: the kernels' own statuses and
@@ -634,22 +643,34 @@ def time_chain(b, args, steps, warmup, graph=True, verify_all=True):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     seed_inf, tgt_inf = b.all_infos()
-    ok = bool((tgt_inf["status"] == 0).all() and (tgt_inf["res_true"] <= args.tol).all())
+    checks = {"target status": bool((tgt_inf["status"] == 0).all()),
+              "target res_true": bool((tgt_inf["res_true"] <= args.tol).all())}
     if b.with_seeds:
-        ok = ok and bool((seed_inf["status"] == 0).all())
+        checks["seed status"] = bool((seed_inf["status"] == 0).all())
     if verify_all and b.K == 1:
         rel = b.verify_chain()
         _, tgt2 = b.all_infos()
         # the eager chain repeats the replayed one: same iteration counts
-        ok = ok and bool(np.array_equal(tgt2["iters"], tgt_inf["iters"]))
+        checks["eager = replay iterations"] = bool(np.array_equal(tgt2["iters"], tgt_inf["iters"]))
     else:
         rel = b.verify_last()[None]
-    ok = ok and bool((rel <= args.tol * (1 + 1e-6)).all())
+    checks["xkp_residual"] = bool((rel <= args.tol * (1 + 1e-6)).all())
+    ok = all(checks.values())
+    if not ok:
+        bad = [k for k, v in checks.items() if not v]
+        extra = ""
+        if b.with_seeds and not checks["seed status"]:
+            extra = f" seed statuses {np.unique(seed_inf['status']).tolist()}"
+        if not checks["target status"]:
+            extra += f" target statuses {np.unique(tgt_inf['status']).tolist()}"
+        print(f"# verification failed: {bad}{extra}", file=sys.stderr, flush=True)
     return {
         "elapsed": elapsed, "ok": ok, "per_chain_s": elapsed / steps,
         "iters_mean": float(tgt_inf["iters"].mean()),
         "restarts": tgt_inf["restarts"], "iters": tgt_inf["iters"], "infos": tgt_inf,
         "seed_iters_total": int(seed_inf["iters"].sum()) if b.with_seeds else 0,
+        # seeds whose spread-out solve gave up and one workgroup solved again
+        "seeds_redone": int((seed_inf["guess_source"] == 4).sum()) if b.with_seeds else 0,
         "guess_res_mean": float(np.mean(tgt_inf["guess_res"])),
         "max_res": float(max(tgt_inf["res_true"].max(), rel.max())),
         "verified_solves": int(rel.size),
@@ -873,6 +894,9 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=6,
                     help="targets of the one-core oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--split", choices=("auto", "off"), default="auto",
+                    help="projection placement: autotuned (inside the solve launch or in "
+                         "launches of its own), or always inside the solve launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -920,7 +944,7 @@ def main():
         ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m,
                    reorth=args.reorth, warm=warm)
         if not args.no_tune and not args.polish_m:
-            tunings[name] = (ch.autotune(), ch.seed_tuning)
+            tunings[name] = (tune(ch, args), ch.seed_tuning)
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name in ("project", "plain", "project_warm", "plain_warm"):
             launch[name] = target_call_ms(ch)
@@ -1000,6 +1024,7 @@ def main():
                          "plain_iters_mean": per_step_log(legs["plain"]["infos"])["iters_mean"]},
     }
     out["project"]["seed_iters_per_chain"] = legs["project"]["seed_iters_total"]
+    out["project"]["seeds_redone"] = legs["project"]["seeds_redone"]
     if "project_seed_galerkin" in legs:
         out["seed_galerkin"] = summary("project_seed_galerkin")
     if "project_warm" in legs and "plain_warm" in legs:

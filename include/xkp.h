@@ -134,7 +134,8 @@ typedef struct {
     double res_true;      /* final ||b - A x||_2 / ||b||_2 computed in FP64                  */
     double guess_res;     /* target: relative residual of the starting guess x0            */
     int32_t guess_source; /* target: 0 x_base, 1 projection onto the seed basis, 2 learned,
-                             3 projection corrected by the learned prediction                */
+                             3 projection corrected by the learned prediction; seed: 0, or 4
+                             when a spread-out solve gave up and one workgroup solved it again */
     int32_t pad;
 } xkp_info;
 
@@ -193,10 +194,12 @@ xkp_status xkp_ctx_set_launch(xkp_ctx *ctx, int32_t waves, int32_t wg_per_cu);
  * are exchanged through device memory, and each Arnoldi step takes two classical Gram-Schmidt
  * passes whose inner products are summed over the blocks in a fixed order (an orthonormal basis
  * to working precision, as the two modified passes of the one-workgroup solve give); results are
- * those of the one-workgroup solve to rounding.  The workgroups of a seed must be resident
- * together: each wait for the others gives up after a time limit (two seconds unless
- * xkp_ctx_set_seed_wait says otherwise) with XKP_EDEVICE for that seed (no hang; the other seeds
- * of the call and later calls are not affected).  Requires grids of at most 128 x 128 and
+ * those of the one-workgroup solve to rounding.  The exchange areas are uncached device memory
+ * (workgroups of one seed may sit on different XCDs), taken from a per-device pool that keeps
+ * them until the process ends.  The workgroups of a seed must be resident together: each wait
+ * for the others gives up after a time limit (100 ms unless xkp_ctx_set_seed_wait says
+ * otherwise; no hang), and a seed whose solve gave up is solved again in the same call by one
+ * workgroup (info.guess_source = 4), so every seed ends with the one-workgroup solve's result.  Requires grids of at most 128 x 128 and
  * max_m <= 64 (XKP_EUNSUPPORTED otherwise); allocates the exchange buffers (a setup call, like
  * xkp_ctx_create).  0 returns to one workgroup per seed.
  */
@@ -204,9 +207,9 @@ xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread);
 
 /*
  * The time after which a wait of a spread-out seed (xkp_ctx_set_seed_width) gives up, in
- * microseconds (0 .. 60e6; default 2e6).  0 gives up at the first wait whose data has not yet
- * arrived: the seed then reports XKP_EDEVICE, its basis header and info carrying that status.
- * XKP_EINVAL outside the range.
+ * microseconds (0 .. 60e6; default 1e5).  0 gives up at the first wait whose data has not yet
+ * arrived: the seed is then solved again by one workgroup in the same call (info.guess_source
+ * = 4).  XKP_EINVAL outside the range.
  */
 xkp_status xkp_ctx_set_seed_wait(xkp_ctx *ctx, int64_t microseconds);
 

@@ -88,6 +88,43 @@ int npad_for(int nmax) {
     return best;
 }
 
+// Exchange areas of spread-out seeds live in uncached device memory: workgroups of one seed on
+// different XCDs poll each other's units, and a line of ordinary (coarse-grained) memory held in
+// one XCD's L2 need not see another XCD's store.  Uncached memory once read by a kernel must not
+// be freed while the process runs (later allocations could then read wrong values), so released
+// areas go back to this per-device pool and are reused, never freed.
+struct XchBuf {
+    int device;
+    size_t bytes;
+    unsigned char *ptr;
+    bool used;
+};
+std::mutex g_xch_mu;
+std::vector<XchBuf> g_xch_pool;
+
+unsigned char *xch_acquire(int device, size_t bytes) {
+    std::lock_guard<std::mutex> g(g_xch_mu);
+    XchBuf *best = nullptr;
+    for (XchBuf &b : g_xch_pool)
+        if (!b.used && b.device == device && b.bytes >= bytes && (!best || b.bytes < best->bytes))
+            best = &b;
+    if (best) {
+        best->used = true;
+        return best->ptr;
+    }
+    void *p = nullptr;
+    if (hipExtMallocWithFlags(&p, bytes, hipDeviceMallocUncached) != hipSuccess || !p)
+        return nullptr;
+    g_xch_pool.push_back(XchBuf{device, bytes, (unsigned char *)p, true});
+    return (unsigned char *)p;
+}
+
+void xch_release(unsigned char *ptr) {
+    std::lock_guard<std::mutex> g(g_xch_mu);
+    for (XchBuf &b : g_xch_pool)
+        if (b.ptr == ptr) b.used = false;
+}
+
 // Host checks of a call's parameters against the restart and size limits of its workspace.
 xkp_status check_params(const xkp_params *P, int max_m, int max_n) {
     if (!P) return XKP_EINVAL;
@@ -186,7 +223,7 @@ xkp_status xkp_ctx_create(xkp_ctx **out, int device, void *hip_stream, int32_t m
     c->cus = cus;
     c->per_cu = choose(max_n)->solve_per_cu(max_n);
     c->variant = 0;
-    c->wide_limit = 200000000LL;   // two seconds
+    c->wide_limit = 10000000LL;   // 100 ms (a 128x128 seed takes about 2 ms)
     c->L = xkp::ws_layout(max_n, max_m, npad_for(max_n));
     if (hipMalloc((void **)&c->ws, sizeof(double) * c->L.stride * (size_t)c->slots) != hipSuccess) {
         delete c;
@@ -213,7 +250,7 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     hipError_t f = hipFree(ctx->ws);
     hipError_t q = hipFree(ctx->queue);
-    if (ctx->xch) hipFree(ctx->xch);
+    if (ctx->xch) xch_release(ctx->xch);
     if (ctx->pj_part) hipFree(ctx->pj_part);
     if (ctx->pj_alpha) hipFree(ctx->pj_alpha);
     if (ctx->pj_ctr) hipFree(ctx->pj_ctr);
@@ -255,11 +292,12 @@ xkp_status xkp_ctx_set_seed_width(xkp_ctx *ctx, int32_t rows_per_thread) {
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return XKP_EDEVICE;
-    if (ctx->xch) hipFree(ctx->xch);
+    if (ctx->xch) xch_release(ctx->xch);
     ctx->xch = nullptr;
     ctx->wide_R = 0;
     const size_t xs = xkp::wide::xch_bytes(gmax);
-    if (hipMalloc((void **)&ctx->xch, xs * cap) != hipSuccess) return XKP_ENOMEM;
+    ctx->xch = xch_acquire(ctx->device, xs * cap);
+    if (!ctx->xch) return XKP_ENOMEM;
     ctx->xch_stride = xs;
     ctx->wide_gmax = gmax;
     ctx->wide_cap = cap;
@@ -363,10 +401,18 @@ xkp_status xkp_seed_build(xkp_ctx *ctx, int32_t n_seeds, const xkp_system *seeds
     if (n_seeds == 0) return XKP_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return XKP_EDEVICE;
     if (ctx->wide_R > 0 && n_seeds <= ctx->wide_cap && params->reorth == XKP_REORTH_AUTO) {
-        // each seed over ceil(n / 256) workgroups; a wait gives up after ctx->wide_limit
-        return from_hip(xkp::wide::launch_wide_seed(ctx->stream, seeds, n_seeds, *params,
-                                                    bases, infos, ctx->xch, ctx->xch_stride,
-                                                    ctx->wide_gmax, nmax, ctx->wide_limit));
+        // each seed over ceil(n / 256) workgroups; a wait gives up after ctx->wide_limit, and a
+        // seed that gave up (XKP_EDEVICE) is solved again by one workgroup in a second launch
+        // that skips every other seed
+        hipError_t e = xkp::wide::launch_wide_seed(ctx->stream, seeds, n_seeds, *params, bases,
+                                                   infos, ctx->xch, ctx->xch_stride,
+                                                   ctx->wide_gmax, nmax, ctx->wide_limit);
+        if (e != hipSuccess) return XKP_EDEVICE;
+        const int grid = solve_grid(ctx, n_seeds);
+        return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
+                                 *params, xkp::kKeepBasis | xkp::kRedo, 0, nullptr, bases, infos,
+                                 ctx->ws, ctx->L, nmax, ctx->queue,
+                                 xkp::Learned{nullptr, 0, 0.0, 0.0}, nullptr));
     }
     const int grid = solve_grid(ctx, n_seeds);
     return from_hip(v->solve(ctx->stream, grid, rmax, v->lds_vec_len(nmax), seeds, n_seeds,
@@ -735,11 +781,47 @@ xkp_status xkp_autotune(xkp_ctx *ctx, int32_t n_targets, const xkp_system *targe
     xkp_tuning t_sp = t_in;
     st = run(&t_sp);
     if (st == XKP_OK && t_sp.ms_best < t_in.ms_best) {
-        t_sp.ms_default = t_in.ms_default;
-        t_sp.n_tried += t_in.n_tried;
-        t_sp.split = tiles;
-        *out = t_sp;
-        return XKP_OK;   // the split run left its variant and workgroup count in the context
+        // the two winners timed again, five calls each, alternating: the split stays only if
+        // it is still the faster
+        const int sp_w = ctx->per_cu, sp_v = ctx->variant;
+        auto timed = [&](int split, int w, int vi, int pm, float *ms) {
+            ctx->split = split;
+            ctx->per_cu = w;
+            ctx->variant = vi;
+            xkp_params P = *params;
+            P.polish_m = pm;
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess) return XKP_EDEVICE;
+            if (hipEventCreate(&e1) != hipSuccess) {
+                hipEventDestroy(e0);
+                return XKP_EDEVICE;
+            }
+            xkp_status r = xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases, &P,
+                                                    infos);
+            if (r == XKP_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) r = XKP_EDEVICE;
+            for (int q = 0; q < 5 && r == XKP_OK; ++q)
+                r = xkp_target_project_solve(ctx, n_targets, targets, n_bases, bases, &P, infos);
+            if (r == XKP_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                                hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+                r = XKP_EDEVICE;
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return r;
+        };
+        float ms_in = 0.f, ms_sp = 0.f;
+        st = timed(0, in_w, in_v, t_in.polish_m, &ms_in);
+        if (st == XKP_OK) st = timed(1, sp_w, sp_v, t_sp.polish_m, &ms_sp);
+        if (st != XKP_OK) return st;
+        if (ms_sp < ms_in) {
+            t_sp.ms_best = ms_sp / 5.f;
+            t_sp.ms_default = t_in.ms_default;
+            t_sp.n_tried += t_in.n_tried;
+            t_sp.split = tiles;
+            *out = t_sp;
+            return XKP_OK;   // the split winner's variant and workgroup count stay set
+        }
+        out->ms_best = ms_in / 5.f;
     }
     out->n_tried += st == XKP_OK ? t_sp.n_tried : 0;
     ctx->split = 0;

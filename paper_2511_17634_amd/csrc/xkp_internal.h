@@ -38,7 +38,9 @@ enum GmresFlags {
     kRegBasis = 32,    // discarded cycles with the basis in registers where it fits
     kPreProjected = 64,   // targets projected by the projection launches (xkp_project.hip): x
                           // holds x0, pre[i] the projection's status
-    kCorrection = 128     // with kLearned: the prediction corrects the projected guess
+    kCorrection = 128,    // with kLearned: the prediction corrects the projected guess
+    kRedo = 256           // seeds: solve only those whose info status is XKP_EDEVICE (a
+                          // spread-out solve gave up), skip the rest
 };
 
 // Learned-guess inputs of a solve launch: target i's predicted residual coordinates at

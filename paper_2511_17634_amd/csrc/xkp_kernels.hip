@@ -1885,7 +1885,8 @@ __device__ __forceinline__ void solve_one(const xkp_system &s, xkp_info *info,
                                           double *lds, int nlds, int nbuf, int nregion,
                                           const Learned &lg, const float *al, int pre0) {
     int pre = XKP_OK;
-    int gsrc = (flags & kTarget) ? 1 : 0;
+    // guess source: 1 targets, 4 a seed solved again after its spread-out solve gave up
+    int gsrc = (flags & kTarget) ? 1 : ((flags & kRedo) ? 4 : 0);
     bool project = PROJ;
     if (flags & kPreProjected) {
         // projected by the projection launches: x holds x0; no basis (XKP_EINVAL) was reported
@@ -1999,6 +2000,8 @@ __global__ __launch_bounds__(kNT) void solve_kernel(const xkp_system *__restrict
         if (si >= nsys) break;
         const xkp_system s = sys[si];
         xkp_info *info = infos + si;
+        if ((flags & kRedo) && __builtin_amdgcn_readfirstlane(info->status) != XKP_EDEVICE)
+            continue;
         if (!desc_ok(s, nmax) || P.m < 1 || P.m > kMMax || P.polish_m < 0 || P.polish_m > kMMax) {
             if (threadIdx.x == 0) info->status = XKP_EINVAL;
             continue;

@@ -151,9 +151,10 @@ def test_projected_chain_on_wide_seeds(X):
 
 def test_wide_seed_wait_gives_up_and_recovers(X):
     """A zero wait limit (xkp_ctx_set_seed_wait) makes every spread-out workgroup give up at the
-    first exchange whose data has not arrived: the launch ends, the seed reports XKP_EDEVICE in
-    its info and basis header, and the same context then solves the seed normally once the
-    limit is back (the exchange area is re-tagged at every launch)."""
+    first exchange whose data has not arrived: the launch ends and the same call solves the
+    seed again on one workgroup (guess_source 4), with the oracle's result; the same context
+    then solves the seed spread out once the limit is back (the exchange area is re-tagged at
+    every launch)."""
     import torch
     H, T, m = 128, 100, 40
     n = H * H
@@ -171,11 +172,14 @@ def test_wide_seed_wait_gives_up_and_recovers(X):
     ctx.seed_build(d, 1, bases.ptrs, P, info)
     torch.cuda.synchronize()
     inf = X.infos_to_numpy(info)[0]
-    assert inf["status"] == X.EDEVICE and bases.header(0)["status"] == X.EDEVICE
-    ctx.set_seed_wait(2000000)
+    assert inf["guess_source"] == 4 and bases.header(0)["status"] == X.OK
+    _check_seed(X, H, T, m, ms, cpu(b), cpu(x), inf, bases, 0)
+    ctx.set_seed_wait(100000)
     info = ctx.new_infos(1)
     ctx.seed_build(d, 1, bases.ptrs, P, info)
     torch.cuda.synchronize()
-    _check_seed(X, H, T, m, ms, cpu(b), cpu(x), X.infos_to_numpy(info)[0], bases, 0)
+    inf = X.infos_to_numpy(info)[0]
+    assert inf["guess_source"] == 0
+    _check_seed(X, H, T, m, ms, cpu(b), cpu(x), inf, bases, 0)
     with pytest.raises(X.XkpError):
         ctx.set_seed_wait(-1)
