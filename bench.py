@@ -40,8 +40,17 @@ HBM_PEAK_GBS = 8000.0
 # launch kind (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch averaged over the chain's target
 # launches), each scaled by what the same counter reads for a plain device copy of known size in
 # the same run (--copy-probe).  A record applies only to the kernel sources it was taken with
-# (digest) and the restart length it was taken at.
-TRAFFIC = {}
+# (digest), the restart length, workgroup size and projection placement it was taken at.
+TRAFFIC = {
+    # 64x64, 63 targets per launch: means over the last 100 polish (split projection) and plain
+    # launches; copy probe: 3 copies of 256 MiB read 131086.4 KiB and wrote 262144 KiB each
+    "c2_project": {"csrc_digest": "b6bf17eeea58a66e", "polish_m": 8, "waves": 4, "split": 0,
+                   "fetch_kib": 8307.28, "write_kib": 15157.00,
+                   "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c2_plain": {"csrc_digest": "b6bf17eeea58a66e", "polish_m": 6, "waves": 4, "split": -1,
+                 "fetch_kib": 8066.89, "write_kib": 15070.93,
+                 "fetch_scale": 1.99978, "write_scale": 1.0},
+}
 
 
 def csrc_digest():
@@ -62,6 +71,9 @@ def traffic_bytes(name, polish_m):
     there is none, the sources have changed or the restart length differs."""
     tr = TRAFFIC.get(name)
     if tr is None or csrc_digest() != tr["csrc_digest"] or tr["polish_m"] != polish_m:
+        return None
+    tu = TUNED.get(name)
+    if tu is not None and (tu["waves"] != tr["waves"] or (tu["split"] >= 0) != (tr["split"] >= 0)):
         return None
     return int(1024 * (tr["fetch_kib"] * tr["fetch_scale"]
                        + tr["write_kib"] * tr["write_scale"]))
@@ -257,7 +269,7 @@ def uneven_leg(args):
     for name, method in (("project", "project"), ("plain", "plain")):
         b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin",
                   reorth=args.reorth)
-        tu = None if args.no_tune else tune(b, args)
+        tu = None if args.no_tune else tune(b, args, f"uneven_{name}")
         r = time_chain(b, args, args.uneven_steps, 1, graph)
         lm = target_call_ms(b)
         ro, rp, ph = target_rooflines(b, f"{b.N} systems of three sizes per launch", r,
@@ -304,7 +316,7 @@ def mixed_leg(args, orc=None):
                                ("plain_fp64", "plain", xkp.FP64)):
         b = Chain(H3, cfg3.T, cfg3.m, s3, t3, method=method, precision=prec,
                   reorth=args.reorth)
-        tu = None if args.no_tune else tune(b, args)
+        tu = None if args.no_tune else tune(b, args, f"c3_{name}")
         r = time_chain(b, args, args.mixed_steps, 1, graph)
         lm = target_call_ms(b)
         mixed = prec == xkp.MIXED
@@ -403,9 +415,9 @@ def learned_leg(args):
                                    correction=bool(kw.get("correction"))))
         b = Batch([Group(64, s0[None], e0[:, None])], T, m, reorth=args.reorth, **kw)
         if kw["method"] == "project" and not args.no_tune:
-            polish_m = tune(b, args).polish_m
+            polish_m = tune(b, args, f"learned_{name}").polish_m
         elif kw["method"] == "plain" and not args.no_tune:
-            tune(b, args)
+            tune(b, args, f"learned_{name}")
         r = time_chain(b, args, 1, 1, not args.eager)
         _, ti = b.all_infos()
         infos[name] = ti.copy()
@@ -494,7 +506,7 @@ def cycle_leg(args):
                          ("plain", groups, dict(method="plain"))):
         b = Batch(gr, T, m, reorth=args.reorth, **kw)
         if not args.no_tune:
-            tune(b, args)
+            tune(b, args, f"cycle_{name}")
         r = time_chain(b, args, 1, 1, not args.eager)
         _, ti = b.all_infos()
         legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
@@ -535,7 +547,7 @@ def cluster_leg(args):
                      ("one_seed", [Group(H, imgs[0][None], imgs[1:][:, None])])):
         b = Batch(gr, T, m, reorth=args.reorth)
         if not args.no_tune:
-            tune(b, args)
+            tune(b, args, f"cluster_{name}")
         r = time_chain(b, args, 1, 1, not args.eager)
         legs[name] = {"value": round(b.N * T / r["per_chain_s"], 2),
                       "ms_per_chain": round(r["per_chain_s"] * 1e3, 2), "targets": b.N,
@@ -560,7 +572,7 @@ def picard_leg(args):
     for K in (2, 3):
         b = Chain(H, T, m, s0, t0, picard=K, reorth=args.reorth)
         if not args.no_tune:
-            tune(b, args)
+            tune(b, args, f"picard_K{K}")
         r = time_chain(b, args, 1, 1, not args.eager)
         _, pt = b.picard_infos()
         ok = r["ok"] and bool((pt["status"] == 0).all() and (pt["res_true"] <= args.tol).all())
@@ -613,12 +625,57 @@ def epilogue_leg(args):
                          "bytes_per_launch": byts}}
 
 
-def tune(b, args):
+# launch choices per leg (keys as in TRAFFIC): written by --tuning-out, applied by --tuning-from
+TUNED = {}
+FIXED_TUNING = {}
+
+
+def tuning_record(b, t):
+    """The launch choices a leg runs with: polish restart length, target launch shape and
+    projection placement, and the seed context's launch shape and seed width."""
+    ts = getattr(b, "seed_tuning", None)
+    return {"polish_m": int(b.params.polish_m), "waves": int(t.waves),
+            "wg_per_cu": int(t.wg_per_cu), "split": int(getattr(b.ctx, "split", -1)),
+            "seed_waves": None if ts is None else int(ts.waves),
+            "seed_wg_per_cu": None if ts is None else int(ts.wg_per_cu),
+            "seed_rows_per_thread": None if ts is None else int(ts.seed_rows)}
+
+
+def apply_tuning(b, rec):
+    """Set a leg's launch choices from a record of tuning_record instead of autotuning (runs
+    under a counter profiler, whose serialised dispatches would mislead the autotuners).
+    Returns the Tuning the autotuner would have."""
+    from paper_2511_17634_amd import xkp
+    b.params.polish_m = rec["polish_m"]
+    b.ctx.set_launch(rec["waves"], rec["wg_per_cu"])
+    b.ctx.set_projection_split(rec["split"])
+    b.seed_tuning = None
+    if rec["seed_waves"] is not None and b.with_seeds and b.ctx_seed is not b.ctx:
+        b.ctx_seed.set_launch(rec["seed_waves"], rec["seed_wg_per_cu"])
+        b.ctx_seed.set_seed_width(rec["seed_rows_per_thread"])
+        b.seed_tuning = xkp.Tuning(waves=rec["seed_waves"], wg_per_cu=rec["seed_wg_per_cu"],
+                                   seed_rows=rec["seed_rows_per_thread"])
+    return xkp.Tuning(polish_m=rec["polish_m"], wg_per_cu=rec["wg_per_cu"], waves=rec["waves"],
+                      split=rec["split"])
+
+
+def save_tuning(args):
+    if args.tuning_out:
+        with open(args.tuning_out, "w") as f:
+            json.dump(TUNED, f, indent=1)
+
+
+def tune(b, args, key):
     """The library's autotuners on a driver Batch (see Batch.autotune); with --split off the
-    projection then stays inside the solve launch."""
-    t = b.autotune()
-    if args.split == "off":
-        b.ctx.set_projection_split(-1)
+    projection then stays inside the solve launch.  With --tuning-from the leg `key` takes the
+    stored choices instead."""
+    if FIXED_TUNING:
+        t = apply_tuning(b, FIXED_TUNING[key])
+    else:
+        t = b.autotune()
+        if args.split == "off":
+            b.ctx.set_projection_split(-1)
+    TUNED[key] = tuning_record(b, t)
     return t
 
 
@@ -894,10 +951,18 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=6,
                     help="targets of the one-core oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--tuning-out", metavar="PATH",
+                    help="write every leg's launch choices (JSON) to PATH")
+    ap.add_argument("--tuning-from", metavar="PATH",
+                    help="take every leg's launch choices from a --tuning-out file instead of "
+                         "autotuning (for runs under a counter profiler)")
     ap.add_argument("--split", choices=("auto", "off"), default="auto",
                     help="projection placement: autotuned (inside the solve launch or in "
                          "launches of its own), or always inside the solve launch")
     args = ap.parse_args()
+    if args.tuning_from:
+        with open(args.tuning_from) as f:
+            FIXED_TUNING.update(json.load(f))
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
@@ -911,6 +976,7 @@ def main():
         rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
                "cycle": cycle_leg, "epilogue": epilogue_leg, "picard": picard_leg,
                "cluster": cluster_leg}[args.only](args)
+        save_tuning(args)
         print(json.dumps(rec), flush=True)
         return
     cfg, s0, t0 = build_c2()
@@ -944,7 +1010,7 @@ def main():
         ch = Chain(H, T, m, s0, t0, method=method, mode=mode, polish_m=args.polish_m,
                    reorth=args.reorth, warm=warm)
         if not args.no_tune and not args.polish_m:
-            tunings[name] = (tune(ch, args), ch.seed_tuning)
+            tunings[name] = (tune(ch, args, f"c2_{name}"), ch.seed_tuning)
         legs[name] = time_chain(ch, args, args.steps, args.warmup, graph)
         if name in ("project", "plain", "project_warm", "plain_warm"):
             launch[name] = target_call_ms(ch)
@@ -967,6 +1033,7 @@ def main():
 
     if "project" not in legs or "plain" not in legs:
         # a partial run (profiling): one line per leg, not the benchmark record
+        save_tuning(args)
         for k, v in legs.items():
             print(json.dumps({"leg": k, "ms_per_chain": round(v["per_chain_s"] * 1e3, 3),
                               "verified": v["ok"], "mean_iters": round(v["iters_mean"], 2)}))
@@ -1065,6 +1132,7 @@ def main():
             v["verified"] for v in out["cycle"]["legs"].values())
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
+    save_tuning(args)
     print(json.dumps(out), flush=True)
 
 

@@ -173,7 +173,9 @@ typedef struct xkp_ctx xkp_ctx;
 
 /* Create a context on `device` bound to `hip_stream` (a hipStream_t, or NULL for the null
  * stream).  Workspace for up to `max_batch` concurrently solved systems of at most max_n
- * unknowns and restart length max_m is allocated here; no later call allocates. */
+ * unknowns and restart length max_m is allocated here; no later solve call allocates (the
+ * setup calls xkp_ctx_set_seed_width and xkp_ctx_set_projection_split allocate their own
+ * buffers when first switched on). */
 xkp_status xkp_ctx_create(xkp_ctx **ctx, int device, void *hip_stream, int32_t max_n,
                           int32_t max_m, int32_t max_batch);
 xkp_status xkp_ctx_destroy(xkp_ctx *ctx);
@@ -231,7 +233,10 @@ xkp_status xkp_ctx_set_seed_wait(xkp_ctx *ctx, int64_t microseconds);
  * Statuses, basis_dim, guess_res and the iterate are those of the in-launch projection up to
  * rounding (the order of the row sums differs).  Calls stay free of allocation and host
  * synchronisation (graph-capturable).  The first call with max_tiles >= 0 allocates the partial
- * slots (at most 2048 of (max_m + 1)^2 doubles) and per-target buffers (a setup call);
+ * slots (at most 2048 of (max_m + 1)^2 doubles, in uncached device memory, since a target's
+ * tiles on different XCDs exchange them within one launch; like the spread-out seeds' exchange
+ * areas they return to a per-device pool on xkp_ctx_destroy and are never freed while the
+ * process runs) and per-target buffers (a setup call);
  * max_tiles = -1 returns to the projection inside the solve launch (the default).  XKP_EINVAL
  * for max_tiles < -1.
  */

@@ -88,11 +88,12 @@ int npad_for(int nmax) {
     return best;
 }
 
-// Exchange areas of spread-out seeds live in uncached device memory: workgroups of one seed on
-// different XCDs poll each other's units, and a line of ordinary (coarse-grained) memory held in
-// one XCD's L2 need not see another XCD's store.  Uncached memory once read by a kernel must not
-// be freed while the process runs (later allocations could then read wrong values), so released
-// areas go back to this per-device pool and are reused, never freed.
+// Exchange areas of spread-out seeds and the partial slots of split projections live in
+// uncached device memory: workgroups on different XCDs read each other's stores within one
+// launch, and a line of ordinary (coarse-grained) memory held in one XCD's L2 need not see
+// another XCD's store.  Uncached memory once read by a kernel must not be freed while the
+// process runs (later allocations could then read wrong values), so released areas go back to
+// this per-device pool and are reused, never freed.
 struct XchBuf {
     int device;
     size_t bytes;
@@ -251,7 +252,7 @@ xkp_status xkp_ctx_destroy(xkp_ctx *ctx) {
     hipError_t f = hipFree(ctx->ws);
     hipError_t q = hipFree(ctx->queue);
     if (ctx->xch) xch_release(ctx->xch);
-    if (ctx->pj_part) hipFree(ctx->pj_part);
+    if (ctx->pj_part) xch_release((unsigned char *)ctx->pj_part);
     if (ctx->pj_alpha) hipFree(ctx->pj_alpha);
     if (ctx->pj_ctr) hipFree(ctx->pj_ctr);
     if (ctx->pj_stat) hipFree(ctx->pj_stat);
@@ -356,21 +357,24 @@ xkp_status xkp_ctx_set_projection_split(xkp_ctx *ctx, int32_t max_tiles) {
     long slots = (long)ctx->max_batch * tiles;
     if (slots > 2048) slots = 2048;
     const int stride = xkp::proj::slot_doubles(ctx->max_m);
-    double *part = nullptr, *alpha = nullptr;
+    // the slots from the uncached pool: a target's last tile reads what tiles on other XCDs
+    // stored in the same launch
+    double *part = (double *)xch_acquire(ctx->device, sizeof(double) * stride * (size_t)slots);
+    double *alpha = nullptr;
     unsigned *ctr = nullptr;
     int *stat = nullptr;
-    if (hipMalloc((void **)&part, sizeof(double) * stride * (size_t)slots) != hipSuccess ||
+    if (!part ||
         hipMalloc((void **)&alpha, sizeof(double) * 64 * (size_t)ctx->max_batch) != hipSuccess ||
         hipMalloc((void **)&ctr, sizeof(unsigned) * (size_t)ctx->max_batch) != hipSuccess ||
         hipMalloc((void **)&stat, sizeof(int) * (size_t)ctx->max_batch) != hipSuccess) {
-        if (part) hipFree(part);
+        if (part) xch_release((unsigned char *)part);
         if (alpha) hipFree(alpha);
         if (ctr) hipFree(ctr);
         return XKP_ENOMEM;
     }
     if (hipMemset(ctr, 0, sizeof(unsigned) * (size_t)ctx->max_batch) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
-        hipFree(part);
+        xch_release((unsigned char *)part);
         hipFree(alpha);
         hipFree(ctr);
         hipFree(stat);

@@ -97,7 +97,8 @@ hipError_t launch_wide_seed(hipStream_t st, const xkp_system *sys, int nsys, xkp
 // tiles_cap row tiles (0: about one round of items on the cus compute units), then x0 written
 // to the targets' x; per target, the status (XKP_OK, XKP_ESINGULAR, XKP_EINVAL, -1 for a
 // rejected descriptor) goes to stat for the polish launch (kPreProjected).  part: slots partial
-// slots of slot_doubles(mmax) doubles; ctr: one zeroed counter per target; alpha: 64 per target.
+// slots of slot_doubles(mmax) doubles (uncached memory); ctr: one zeroed counter per target;
+// alpha: 64 per target.
 namespace proj {
 int slot_doubles(int mmax);
 int tiles_per_target(int nsys, int nmax, int slots, int tiles_cap, int cus);

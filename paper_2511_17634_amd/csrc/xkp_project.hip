@@ -450,9 +450,9 @@ __global__ __launch_bounds__(NT, 2) void gram_kernel(Args A) {
                 if (ka > 48) z_sweep<32>(J, 48, ka);
             }
         }
-        // the slot's device-coherent stores have completed once every thread's store counter
-        // is zero; then the target's last tile to arrive goes on and reads the slots with
-        // device-coherent loads
+        // the slot's device-coherent stores (uncached memory: they reach the memory side, not
+        // this XCD's L2) have completed once every thread's store counter is zero; then the
+        // target's last tile to arrive goes on and reads the slots with device-coherent loads
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tl.T > 1) {

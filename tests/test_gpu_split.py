@@ -226,3 +226,38 @@ def test_split_chain_matches_oracle_and_graph_replays(X):
         b.run()
         torch.cuda.synchronize()
         assert np.array_equal(cpu(b.state()[1]), ref_t)
+
+
+def test_split_repeated_calls_are_bitwise_equal(X):
+    """One context, two sets of 64 targets of 64 x 64 projected alternately six times over 8 tiles
+    per target (a target's tiles run on different XCDs, and every call reuses the same partial
+    slots): each call reproduces its set's first guesses bit for bit."""
+    import torch
+    T, m, H, N = 100, 40, 64, 64
+    n = H * H
+    ms, _ = blob_pair(H, seed=21)
+    bases = seed_basis(X, H, T, m, ms)
+    ctx = X.Context(n, m, N)
+    ctx.set_projection_split(8)
+    sets = []
+    for s in range(2):
+        specs = [X.SystemSpec(H, 1.0 / T, 0.5,
+                              t64(blob_pair(H, seed=21, jitter=0.5 + 0.02 * i + 0.3 * s)[1]),
+                              b=zeros(n), x=zeros(n)) for i in range(N)]
+        d = X.pack_systems(specs, dev())
+        ctx.build_rhs(d, N)
+        sets.append((specs, d))
+    P = X.Context.params(m, tol=1e300, batch_max_n=n)
+    first = [None, None]
+    for call in range(6):
+        specs, d = sets[call % 2]
+        info = ctx.new_infos(N)
+        ctx.target_project_solve(d, N, bases.count, bases.ptrs, P, info)
+        torch.cuda.synchronize()
+        xs = np.stack([cpu(s.x) for s in specs])
+        inf = X.infos_to_numpy(info)
+        assert np.all(inf["status"] == X.OK) and np.all(inf["basis_dim"] == bases.header(0)["k"])
+        if first[call % 2] is None:
+            first[call % 2] = xs
+        else:
+            assert np.array_equal(xs, first[call % 2]), call
