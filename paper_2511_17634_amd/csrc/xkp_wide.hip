@@ -9,23 +9,23 @@
 //   operator   w = A v_j on the owned rows; the neighbours H rows away come from the adjacent
 //              blocks' boundary rows (exchanged), the rest from the block's own LDS vector
 //   Gram-Schmidt  two classical passes (CGS2): pass k forms the block's share of V^T w (and of
-//              ||w||^2), the G shares are exchanged and summed in block order (the same order in
+//              ||w||^2), the G shares are exchanged and summed in a fixed order (the same in
 //              every workgroup, so every workgroup holds bitwise the same sums and takes the
 //              same decisions), w -= V h; ||w2||^2 = ||w1||^2 - ||h2||^2
 //   then       v_{j+1} = w2 / ||w2|| on the owned rows, its boundary rows exchanged for the next
-//              operator application; Givens rotations and the Hessenberg column computed
-//              identically by every workgroup
+//              operator application; the Givens rotations by the first wavefront of every
+//              workgroup, identically
 // i.e. three exchanges per step.  The basis, Hessenberg matrix, header, solution and info are
 // those of the single-workgroup seed solve (restarted GMRES from x0, first cycle kept); the two
 // classical passes give an orthonormal basis to working precision as two modified passes do.
 //
-// An exchange: every thread publishes its values with device-coherent stores and waits for them
-// to complete, workgroup barrier, then one thread adds 1 to the seed's arrival counter and waits
-// until G arrivals of this round are counted; readers use device-coherent loads.  Exchange
-// buffers alternate between rounds.  Every wait is bounded in time: a workgroup whose partners
-// do not arrive (they must all be resident at once) gives up, and the seed gets XKP_EDEVICE.
-// A seed's workgroups share one XCD (ids congruent mod 8) when G <= 32, so that their exchanges
-// stay in one L2; larger seeds spread over the XCDs.
+// An exchange round: each workgroup publishes its values as tagged units (below) in the seed's
+// exchange area (uncached device memory, so that workgroups on different XCDs see each other's
+// stores) and polls the units it needs until they carry the round's tag.  Every wait is bounded
+// in time: a workgroup whose partners do not arrive (they must all be resident at once) gives
+// up, the seed gets XKP_EDEVICE, and the caller solves it again on one workgroup.  A seed's
+// workgroups share one XCD (ids congruent mod 8) when G <= 32; larger seeds spread over the
+// XCDs.
 #define XKP_NT 256
 #define XKP_VARIANT wdev
 #include "xkp_device.h"
@@ -43,16 +43,23 @@ constexpr int NT = 256, NW = NT / 64;
 constexpr int HM = 128;                    // largest grid side (halo rows on each side)
 constexpr int kMM = 64;                    // largest restart length
 constexpr int kWV = kMM + 4;               // values of one exchange (j + 2 <= kMM + 1)
+constexpr int kSeg = 4;                    // threads (block segments) per reduced value
 
-// Per-seed exchange area: two rounds of per-workgroup value slots, then two rounds of
+// Per-seed exchange area: four rounds of per-workgroup value slots, then two rounds of
 // per-workgroup boundary rows (low H rows, high H rows).  Every published double is a 16-byte
 // unit {low word, tag, high word, tag} written with one store: a reader that sees both tags
 // equal to the round it waits for has the value (no separate flag, no counter), and a launch
 // starts by setting every tag to 0xFFFFFFFF, a round no solve reaches.
+// Reuse of a slot: a round that exchanges only boundary rows ties a workgroup to its two
+// neighbours, not to all, and up to two such rounds follow each other (the last step's row
+// exchange, then the new x's), so a workgroup may publish values up to three rounds after a
+// round whose values a distant workgroup is still reading: value slots rotate over four rounds.
+// Boundary rows are read by the neighbours only, which have finished the previous round before
+// a workgroup can start the next one, so two rounds suffice there.
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kAux = 16;   // cache policy sc1: device-coherent store / load
 __host__ __device__ inline size_t xch_units(int gmax) {
-    return 2 * (size_t)gmax * kWV + 2 * (size_t)gmax * 2 * HM;
+    return 4 * (size_t)gmax * kWV + 2 * (size_t)gmax * 2 * HM;
 }
 size_t xch_bytes(int gmax) { return (16 * xch_units(gmax) + 255) & ~(size_t)255; }
 int rows_per_block() { return NT; }
@@ -63,13 +70,13 @@ struct Wide {
     unsigned round;
     long long limit;
     int *abort_lds;
-    double *red, *tot;   // LDS
+    double *red, *tot, *seg;   // LDS
 
     __device__ __forceinline__ unsigned part_unit(unsigned rnd, int gg, int v) const {
-        return (unsigned)(((size_t)(rnd & 1) * gmax + gg) * kWV + v);
+        return (unsigned)(((size_t)(rnd & 3) * gmax + gg) * kWV + v);
     }
     __device__ __forceinline__ unsigned bnd_unit(unsigned rnd, int gg, int side, int t) const {
-        return (unsigned)(2 * (size_t)gmax * kWV + (((size_t)(rnd & 1) * gmax + gg) * 2 + side) * HM + t);
+        return (unsigned)(4 * (size_t)gmax * kWV + (((size_t)(rnd & 1) * gmax + gg) * 2 + side) * HM + t);
     }
     __device__ __forceinline__ void put(unsigned unit, double v) const {
         const unsigned lo = __double2loint(v), hi = __double2hiint(v);
@@ -111,26 +118,33 @@ struct Wide {
         return *abort_lds == 0;
     }
     // The workgroup's share of nv values, already summed per wave in red[v * NW + wave], is
-    // published; then tot[v] = the sums over the G blocks in block order (the G shares loaded
-    // sixteen at a time).  Callers may publish other units of this round before calling.
+    // published; then tot[v] = the sums over the G blocks: kSeg threads per value each load one
+    // segment of ceil(G / kSeg) consecutive blocks' shares at once (up to 16) and add them in
+    // block order, and the segment sums are added as a fixed tree, the same in every workgroup.
+    // Callers may publish other units of this round before calling.
     __device__ __forceinline__ bool reduce(int nv) {
         __syncthreads();
         const unsigned rnd = round;
         for (int v = threadIdx.x; v < nv; v += NT) put(part_unit(rnd, g, v), tree_sum<NW>(red + v * NW));
-        for (int v = threadIdx.x; v < nv; v += NT) {
+        const int L = (G + kSeg - 1) / kSeg;
+        for (int idx = threadIdx.x; idx < nv * kSeg; idx += NT) {
+            const int v = idx / kSeg, g0 = (idx - v * kSeg) * L;
+            const int g1 = g0 + L < G ? g0 + L : G;
             double t = 0.0;
-            for (int g0 = 0; g0 < G; g0 += 16) {
+            for (int gb = g0; gb < g1; gb += 16) {
                 u32x4_t sh[16];
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    sh[e] = g0 + e < G ? load(part_unit(rnd, g0 + e, v)) : u32x4_t{0, 0, 0, 0};
+                    sh[e] = gb + e < g1 ? load(part_unit(rnd, gb + e, v)) : u32x4_t{0, 0, 0, 0};
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    if (g0 + e < G && wait(part_unit(rnd, g0 + e, v), rnd, sh[e]))
+                    if (gb + e < g1 && wait(part_unit(rnd, gb + e, v), rnd, sh[e]))
                         t += value(sh[e]);
             }
-            tot[v] = t;
+            seg[idx] = t;
         }
+        __syncthreads();
+        for (int v = threadIdx.x; v < nv; v += NT) tot[v] = tree_sum<kSeg>(seg + v * kSeg);
         return end_round();
     }
 };
@@ -151,12 +165,30 @@ __device__ __forceinline__ void wave_put4(double a, double b, double c, double d
     }
 }
 
+// w - sum_{c <= j} h[c] V[c NT] (this thread's row of columns 0..j, LDS), subtracted in column
+// order, four columns' loads at a time.
+__device__ __forceinline__ double sub_cols(double w, int j, const double *h, const double *V) {
+    int c = 0;
+    for (; c + 3 <= j; c += 4) {
+        const double v0 = V[c * NT], v1 = V[(c + 1) * NT], v2 = V[(c + 2) * NT];
+        const double v3 = V[(c + 3) * NT];
+        const double h0 = h[c], h1 = h[c + 1], h2 = h[c + 2], h3 = h[c + 3];
+        w -= h0 * v0;
+        w -= h1 * v1;
+        w -= h2 * v2;
+        w -= h3 * v3;
+    }
+    for (; c <= j; ++c) w -= h[c] * V[c * NT];
+    return w;
+}
+
 // LDS layout (doubles), mmax = the largest cycle length of the call:
 //   Vl    (mmax + 1) x NT: the block's rows of the cycle's basis vectors, column-major
 //   vbuf  NT + 2 HM: the operator's input, owned rows at HM + t, halos around them
-//   red   kWV x NW, tot kWV, Rp mmax (mmax + 1) / 2, cs, sn, yv mmax, gv mmax + 1, flags
+//   red   kWV x NW, tot kWV, seg kWV x kSeg, Rp mmax (mmax + 1) / 2, cs, sn, yv mmax,
+//   gv mmax + 1, flags
 __host__ __device__ inline size_t lds_doubles(int mmax) {
-    return (size_t)(mmax + 1) * NT + NT + 2 * HM + kWV * NW + kWV +
+    return (size_t)(mmax + 1) * NT + NT + 2 * HM + kWV * NW + kWV + kWV * kSeg +
            (size_t)mmax * (mmax + 1) / 2 + 4 * (size_t)mmax + 1 + 2;
 }
 
@@ -197,7 +229,8 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     double *vbuf = Vl + (size_t)(mmax + 1) * NT;
     double *red = vbuf + NT + 2 * HM;
     double *tot = red + kWV * NW;
-    double *Rp = tot + kWV;
+    double *seg = tot + kWV;
+    double *Rp = seg + kWV * kSeg;
     double *cs = Rp + (size_t)mmax * (mmax + 1) / 2, *sn = cs + mmax, *yv = sn + mmax;
     double *gv = yv + mmax;
     int *flags = (int *)(gv + mmax + 1);
@@ -207,7 +240,7 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     __syncthreads();
     unsigned char *xs = xch + (size_t)si * xch_stride;
     Wide X{__builtin_amdgcn_make_buffer_rsrc(xs, (short)0, (int)xch_stride, 0x00020000), gmax,
-           G, g, 0u, limit, flags, red, tot};
+           G, g, 0u, limit, flags, red, tot, seg};
 
     // this thread's row p = g NT + tid; rows at or past n (last block) are zero throughout
     const int base = g * NT, p = base + tid;
@@ -347,16 +380,13 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                 ++iters;
                 if (!(alive = pass(j, w))) break;
                 const double wn0 = sqrt(tot[j + 1]);
-                for (int c = 0; c <= j; ++c) w -= tot[c] * Vl[c * NT + tid];
+                w = sub_cols(w, j, tot, Vl + tid);
                 // pass 1's coefficients wait in yv while pass 2 reuses tot
                 for (int c = tid; c <= j; c += NT) yv[c] = tot[c];
                 if (!(alive = pass(j, w))) break;
                 double c2 = 0.0;
-                for (int c = 0; c <= j; ++c) {
-                    const double hc = tot[c];
-                    c2 += hc * hc;
-                    w -= hc * Vl[c * NT + tid];
-                }
+                for (int c = 0; c <= j; ++c) c2 += tot[c] * tot[c];
+                w = sub_cols(w, j, tot, Vl + tid);
                 const double hn = sqrt(fmax(tot[j + 1] - c2, 0.0));
                 const bool brk = !(hn > 1e-14 * wn0);
                 const double rhn = brk ? 0.0 : 1.0 / hn;
@@ -375,27 +405,32 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                         for (int rr = tid; rr <= j + 1; rr += NT)
                             Hb[(size_t)j * (m + 1) + rr] = rr <= j ? yv[rr] + tot[rr] : hn;
                 }
-                // Givens rotations of column j (every thread holds the same values)
-                double t = yv[0] + tot[0];
-                for (int i = 1; i <= j; ++i) {
-                    const double hi = yv[i] + tot[i];
-                    const double c = cs[i - 1], sv = sn[i - 1];
-                    const double rrv = c * t + sv * hi;
-                    t = -sv * t + c * hi;
-                    if (tid == 0) Rp[(j * (j + 1)) / 2 + i - 1] = rrv;
+                // Givens rotations of column j by the first wavefront: lane i holds entry i of
+                // the column and rotation i, the chain reads them with readlane, and lane i
+                // keeps rotated entry i; the others take the new rotation from the LDS
+                if (tid < 64) {
+                    const double hl = tid <= j ? yv[tid] + tot[tid] : 0.0;
+                    const double cl = tid < j ? cs[tid] : 0.0, sl = tid < j ? sn[tid] : 0.0;
+                    double t = readlane_d(hl, 0), rl = 0.0;
+                    for (int i = 1; i <= j; ++i) {
+                        const double c = readlane_d(cl, i - 1), sv = readlane_d(sl, i - 1);
+                        const double hi = readlane_d(hl, i);
+                        const double rrv = c * t + sv * hi;
+                        t = -sv * t + c * hi;
+                        if (tid == i - 1) rl = rrv;
+                    }
+                    if (tid < j) Rp[(j * (j + 1)) / 2 + tid] = rl;
+                    if (tid == 0) {
+                        const double den = sqrt(t * t + hn * hn);
+                        const double rden = 1.0 / den;
+                        Rp[(j * (j + 1)) / 2 + j] = den;
+                        cs[j] = t * rden;
+                        sn[j] = hn * rden;
+                        gv[j] = t * rden * gcur;
+                    }
                 }
-                const double den = sqrt(t * t + hn * hn);
-                const double rden = 1.0 / den;
-                const double cj = t * rden, sj = hn * rden;
-                // every thread has read yv, cs and sn before they change
                 __syncthreads();
-                if (tid == 0) {
-                    Rp[(j * (j + 1)) / 2 + j] = den;
-                    cs[j] = cj;
-                    sn[j] = sj;
-                    gv[j] = cj * gcur;
-                }
-                gcur = -sj * gcur;
+                gcur = -sn[j] * gcur;
                 kk = j + 1;
                 // v_{j+1}'s boundary rows to the neighbours, theirs into the halos
                 if (!(alive = exchange_row(w))) break;

@@ -76,6 +76,8 @@ def test_wide_seed_matches_oracle(X, H, m, R):
     T = 100 if H != 28 else 50
     bases, inf, out = _seeds(X, [H], T, m, R)
     H_, ms, b, x = out[0]
+    # the spread-out solve itself, not the one-workgroup solve that follows a give-up
+    assert inf[0]["guess_source"] == 0
     _check_seed(X, H, T, m, ms, b, x, inf[0], bases, 0)
 
 
@@ -86,6 +88,7 @@ def test_wide_seed_equals_one_workgroup_seed(X):
     b1, i1, o1 = _seeds(X, Hs, T, m, 0)
     b2, i2, o2 = _seeds(X, Hs, T, m, 1)
     assert np.array_equal(i1["status"], i2["status"]) and np.all(i2["status"] == X.OK)
+    assert np.all(i2["guess_source"] == 0)
     assert np.abs(i1["iters"].astype(int) - i2["iters"].astype(int)).max() <= 1
     for k in range(3):
         kk = min(b1.header(k)["k"], b2.header(k)["k"])
