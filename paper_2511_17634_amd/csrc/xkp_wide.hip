@@ -165,20 +165,72 @@ __device__ __forceinline__ void wave_put4(double a, double b, double c, double d
     }
 }
 
+// Sums over the workgroup's rows of 16 values d[0..16) at once (values v0 + i, those < nv
+// kept): a butterfly inside each 16-lane row (lane partners 1, 2, 4, 8 apart; at each level a
+// lane keeps the half of its values picked by its own lane bit and adds the partner's copy of
+// it) leaves lane r of the row with value bitreverse4(r) summed over the row; two lane permutes
+// add the wave's four rows, and lanes 0..15 write the wave's sums to red[v * NW + wave].
+__device__ __forceinline__ double bperm_d(double v, int src_lane) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void wave_put16(double (&d)[16], double *red, int v0, int nv) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double keep = b0 ? d[i + 8] : d[i], send = b0 ? d[i] : d[i + 8];
+        d[i] = keep + dpp_d<0xB1>(send);   // quad_perm [1,0,3,2]: partner lane ^ 1
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = b1 ? d[i + 4] : d[i], send = b1 ? d[i] : d[i + 4];
+        d[i] = keep + dpp_d<0x4E>(send);   // quad_perm [2,3,0,1]: partner lane ^ 2
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = b2 ? d[i + 2] : d[i], send = b2 ? d[i] : d[i + 2];
+        d[i] = keep + dpp_d<0x124>(send);  // row_ror 4: a partner whose lane bit 2 differs
+    }
+    double s;
+    {
+        const double keep = b3 ? d[1] : d[0], send = b3 ? d[0] : d[1];
+        s = keep + dpp_d<0x128>(send);     // row_ror 8: partner lane ^ 8
+    }
+    s += bperm_d(s, lane ^ 16);
+    s += bperm_d(s, lane ^ 32);
+    const int v = v0 + ((lane & 1) << 3 | (lane & 2) << 1 | (lane & 4) >> 1 | (lane & 8) >> 3);
+    if (lane < 16 && v < nv) red[v * NW + wave] = s;
+}
+
 // w - sum_{c <= j} h[c] V[c NT] (this thread's row of columns 0..j, LDS), subtracted in column
-// order, four columns' loads at a time.
-__device__ __forceinline__ double sub_cols(double w, int j, const double *h, const double *V) {
+// order, four columns' loads at a time; with SQ also c2 += h[c]^2 in the same order.
+template <bool SQ>
+__device__ __forceinline__ double sub_cols(double w, int j, const double *h, const double *V,
+                                           double &c2) {
     int c = 0;
     for (; c + 3 <= j; c += 4) {
         const double v0 = V[c * NT], v1 = V[(c + 1) * NT], v2 = V[(c + 2) * NT];
         const double v3 = V[(c + 3) * NT];
         const double h0 = h[c], h1 = h[c + 1], h2 = h[c + 2], h3 = h[c + 3];
+        if (SQ) {
+            c2 += h0 * h0;
+            c2 += h1 * h1;
+            c2 += h2 * h2;
+            c2 += h3 * h3;
+        }
         w -= h0 * v0;
         w -= h1 * v1;
         w -= h2 * v2;
         w -= h3 * v3;
     }
-    for (; c <= j; ++c) w -= h[c] * V[c * NT];
+    for (; c <= j; ++c) {
+        const double hc = h[c];
+        if (SQ) c2 += hc * hc;
+        w -= hc * V[c * NT];
+    }
     return w;
 }
 
@@ -295,14 +347,14 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
     // one classical pass over columns 0..j: the block's shares of V^T w and ||w||^2, summed
     // over the blocks into tot[0..j+1]
     auto pass = [&](int j, double w) -> bool {
-        for (int c0 = 0; c0 <= j + 1; c0 += 4) {
-            double d[4];
+        for (int c0 = 0; c0 <= j + 1; c0 += 16) {
+            double d[16];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 16; ++e) {
                 const int c = c0 + e;
                 d[e] = c <= j ? Vl[c * NT + tid] * w : (c == j + 1 ? w * w : 0.0);
             }
-            wave_put4(d[0], d[1], d[2], d[3], red, c0, j + 2);
+            wave_put16(d, red, c0, j + 2);
         }
         return X.reduce(j + 2);
     };
@@ -380,13 +432,12 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                 ++iters;
                 if (!(alive = pass(j, w))) break;
                 const double wn0 = sqrt(tot[j + 1]);
-                w = sub_cols(w, j, tot, Vl + tid);
+                double c2 = 0.0;
+                w = sub_cols<false>(w, j, tot, Vl + tid, c2);
                 // pass 1's coefficients wait in yv while pass 2 reuses tot
                 for (int c = tid; c <= j; c += NT) yv[c] = tot[c];
                 if (!(alive = pass(j, w))) break;
-                double c2 = 0.0;
-                for (int c = 0; c <= j; ++c) c2 += tot[c] * tot[c];
-                w = sub_cols(w, j, tot, Vl + tid);
+                w = sub_cols<true>(w, j, tot, Vl + tid, c2);
                 const double hn = sqrt(fmax(tot[j + 1] - c2, 0.0));
                 const bool brk = !(hn > 1e-14 * wn0);
                 const double rhn = brk ? 0.0 : 1.0 / hn;
@@ -412,6 +463,7 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                     const double hl = tid <= j ? yv[tid] + tot[tid] : 0.0;
                     const double cl = tid < j ? cs[tid] : 0.0, sl = tid < j ? sn[tid] : 0.0;
                     double t = readlane_d(hl, 0), rl = 0.0;
+#pragma unroll 4
                     for (int i = 1; i <= j; ++i) {
                         const double c = readlane_d(cl, i - 1), sv = readlane_d(sl, i - 1);
                         const double hi = readlane_d(hl, i);
