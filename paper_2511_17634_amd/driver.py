@@ -338,7 +338,8 @@ class Batch:
         over the candidates of xkp_autotune on its real inputs; the chosen polish restart length
         goes into the params, the workgroup count into the context.  With a seed context of
         its own (pipelined chains), the seed call of that timestep is tuned too
-        (xkp_autotune_seeds; the result is in `self.seed_tuning`).  Resets the chain."""
+        (xkp_autotune_seeds; the result is in `self.seed_tuning`), and a spread-out seed width
+        is kept only if the pipelined chain steps are faster with it.  Resets the chain."""
         import torch
         self.reset()
         for _ in range(steps):
@@ -360,9 +361,42 @@ class Batch:
         torch.cuda.synchronize(self.dev)
         t = self.ctx.autotune(self.tgt_desc[par], self.N, self.S, bases, self.params, inf_t)
         self.params.polish_m = t.polish_m
+        if self.seed_tuning is not None and self.seed_tuning.seed_rows == 1:
+            # the seed call was timed alone; beside the target launches (projection launches
+            # that fill the chip) a seed spread over workgroups must wait until all of them are
+            # resident, so the width whose chain steps run faster is kept
+            self.seed_tuning.seed_rows = self._pick_seed_width()
         self.reset()
         torch.cuda.synchronize(self.dev)
         return t
+
+    def _chain_ms(self):
+        """Host time of one replay of the whole chain, captured now and replayed once before."""
+        import time
+        import torch
+        self.capture()
+        self.replay()
+        self._join()
+        torch.cuda.synchronize(self.dev)
+        t0 = time.perf_counter()
+        self.replay()
+        self._join()
+        torch.cuda.synchronize(self.dev)
+        self.graph = None
+        return (time.perf_counter() - t0) * 1e3
+
+    def _pick_seed_width(self, reps=2):
+        """Seed width (1: spread over workgroups, 0: one workgroup per seed) whose replayed
+        chain is faster, the better of `reps` alternating timings each; sets it in the seed
+        context and returns it."""
+        best = {0: float("inf"), 1: float("inf")}
+        for _ in range(reps):
+            for w in (1, 0):
+                self.ctx_seed.set_seed_width(w)
+                best[w] = min(best[w], self._chain_ms())
+        w = 1 if best[1] < best[0] else 0
+        self.ctx_seed.set_seed_width(w)
+        return w
 
     def ctx_seed_rows(self):
         """1 if the seed context spreads each seed over several workgroups, else 0."""
