@@ -1021,11 +1021,16 @@ def main():
             legs[name]["seed_ms"] = {"alone": round(seed_call_ms(ch, True), 4),
                                      "beside_targets": round(seed_call_ms(ch, False), 4)}
             if name == "project":
-                # the same seed call on one workgroup, for scale
+                # the same seed call on one workgroup and spread over ceil(n / 256) workgroups,
+                # alone and beside the target calls, whichever width the chain runs with
                 rows = ch.ctx_seed_rows()
-                ch.ctx_seed.set_seed_width(0)
-                legs[name]["seed_ms"]["one_workgroup_alone"] = round(seed_call_ms(ch, True), 4)
+                for w, key in ((0, "one_workgroup"), (1, "spread")):
+                    ch.ctx_seed.set_seed_width(w)
+                    legs[name]["seed_ms"][f"{key}_alone"] = round(seed_call_ms(ch, True), 4)
+                    legs[name]["seed_ms"][f"{key}_beside_targets"] = round(
+                        seed_call_ms(ch, False), 4)
                 ch.ctx_seed.set_seed_width(rows)
+                legs[name]["seed_ms"]["width_used"] = "spread" if rows else "one_workgroup"
         print(f"# {name}: {legs[name]['per_chain_s'] * 1e3:.1f} ms/chain, ok={legs[name]['ok']}, "
               f"mean iters {legs[name]['iters_mean']:.1f}, polish_m {legs[name]['polish_m']}",
               file=sys.stderr, flush=True)

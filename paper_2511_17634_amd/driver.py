@@ -109,6 +109,10 @@ class Batch:
         self.bt = torch.empty_like(self.m0[1])
         ns = [H * H for H, _, _ in self.seed_sys]
         self.bases = xkp.Bases(2 * self.S, ns * 2, m, device=device)
+        # a seed spread over workgroups (256 rows each) runs beside the previous target call
+        # only where its workgroups and one per target fit the chip's compute units together
+        self.seed_blocks = sum((n + 255) // 256 for n in ns)
+        self.cus = torch.cuda.get_device_properties(self.dev).multi_processor_count
         self.dt = 1.0 / T
         mode_id = xkp.NONE if method == "plain" else xkp.MODES[mode]
         self.learned = None
@@ -241,9 +245,10 @@ class Batch:
             cs = self.ctx_seed
             if self.pipeline and self.step_no >= 2:
                 self.s_seed.wait_event(self.ev_tgt[par])   # targets n-2 done with these bases
-            if self.pipeline and self.step_no >= 1 and self.ctx_seed_rows() > 0:
-                # a seed spread over several workgroups needs them resident together: it runs
-                # after the previous target call rather than beside it
+            if (self.pipeline and self.step_no >= 1 and self.ctx_seed_rows() > 0
+                    and self.N + self.seed_blocks > self.cus):
+                # a seed spread over several workgroups needs them resident together: beside a
+                # target call that fills the chip it would wait for it anyway, so it runs after
                 self.s_seed.wait_event(self.ev_tgt[1 - par])
             cs.build_rhs(self.seed_desc[par], self.S)
             if seed_events is not None:
