@@ -70,6 +70,48 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// A double from lane src_lane (ds_bpermute: a lane permute, no LDS memory is touched).
+__device__ __forceinline__ double bperm_d(double v, int src_lane) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Sums over the 64 lanes of 16 values at once (d[i] per lane, overwritten): a butterfly inside
+// each 16-lane row halves the values per level (partners 1, 2, 4 and 8 apart: a lane keeps the
+// half of its values picked by its own lane bit and adds the partner's copy of that half), then
+// the four rows are added.  Lane r < 16 returns the wave's sum of value bfly_index(r) (the
+// bit-reversed r); every value is formed in a fixed order, so results do not depend on
+// scheduling.
+__device__ __forceinline__ int bfly_index(int lane) {
+    return (lane & 1) << 3 | (lane & 2) << 1 | (lane & 4) >> 1 | (lane & 8) >> 3;
+}
+
+__device__ __forceinline__ double wave_bfly16(double (&d)[16]) {
+    const int lane = threadIdx.x & 63;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double keep = b0 ? d[i + 8] : d[i], send = b0 ? d[i] : d[i + 8];
+        d[i] = keep + dpp_d<0xB1>(send);   // quad_perm [1,0,3,2]: partner lane ^ 1
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = b1 ? d[i + 4] : d[i], send = b1 ? d[i] : d[i + 4];
+        d[i] = keep + dpp_d<0x4E>(send);   // quad_perm [2,3,0,1]: partner lane ^ 2
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = b2 ? d[i + 2] : d[i], send = b2 ? d[i] : d[i + 2];
+        d[i] = keep + dpp_d<0x124>(send);  // row_ror 4: a partner whose lane bit 2 differs
+    }
+    const double keep = b3 ? d[1] : d[0], send = b3 ? d[0] : d[1];
+    double s = keep + dpp_d<0x128>(send);  // row_ror 8: partner lane ^ 8
+    s += bperm_d(s, lane ^ 16);
+    s += bperm_d(s, lane ^ 32);
+    return s;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp_d<0xB1>(v));
     v = fmax(v, dpp_d<0x4E>(v));

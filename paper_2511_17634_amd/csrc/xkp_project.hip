@@ -552,10 +552,39 @@ __global__ __launch_bounds__(NT) void x0_kernel(Args A) {
         const double *al = A.alpha + (size_t)t * KMX;
         const int row0 = j * tl.RT;
         const int row1 = row0 + tl.RT < n ? row0 + tl.RT : n;
-        for (int p = row0 + threadIdx.x; p < row1; p += NT) {
-            double x = s.x0 ? s.x0[p] : 0.0;
-            for (int c = 0; c < k; ++c) x += al[c] * V[(size_t)c * ldv + p];
-            s.x[p] = x;
+        // four rows per thread and four columns at a time: sixteen loads in flight, each row's
+        // sum still taken column by column
+        for (int p0 = row0 + threadIdx.x; p0 < row1; p0 += 4 * NT) {
+            double x[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + r * NT;
+                x[r] = (p < row1 && s.x0) ? s.x0[p] : 0.0;
+            }
+            for (int c = 0; c < k; c += 4) {
+                double a[4], v[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    a[q] = c + q < k ? al[c + q] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = p0 + r * NT;
+                        v[q][r] = (c + q < k && p < row1) ? V[(size_t)(c + q) * ldv + p] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (c + q < k) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) x[r] += a[q] * v[q][r];
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int p = p0 + r * NT;
+                if (p < row1) s.x[p] = x[r];
+            }
         }
     }
 }

@@ -165,43 +165,12 @@ __device__ __forceinline__ void wave_put4(double a, double b, double c, double d
     }
 }
 
-// Sums over the workgroup's rows of 16 values d[0..16) at once (values v0 + i, those < nv
-// kept): a butterfly inside each 16-lane row (lane partners 1, 2, 4, 8 apart; at each level a
-// lane keeps the half of its values picked by its own lane bit and adds the partner's copy of
-// it) leaves lane r of the row with value bitreverse4(r) summed over the row; two lane permutes
-// add the wave's four rows, and lanes 0..15 write the wave's sums to red[v * NW + wave].
-__device__ __forceinline__ double bperm_d(double v, int src_lane) {
-    const int lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2loint(v));
-    const int hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, __double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-
+// The wave's sums of 16 values d[0..16) at once (values v0 + i, those < nv kept;
+// wave_bfly16), lanes 0..15 writing them to red[v * NW + wave].
 __device__ __forceinline__ void wave_put16(double (&d)[16], double *red, int v0, int nv) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const double keep = b0 ? d[i + 8] : d[i], send = b0 ? d[i] : d[i + 8];
-        d[i] = keep + dpp_d<0xB1>(send);   // quad_perm [1,0,3,2]: partner lane ^ 1
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double keep = b1 ? d[i + 4] : d[i], send = b1 ? d[i] : d[i + 4];
-        d[i] = keep + dpp_d<0x4E>(send);   // quad_perm [2,3,0,1]: partner lane ^ 2
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const double keep = b2 ? d[i + 2] : d[i], send = b2 ? d[i] : d[i + 2];
-        d[i] = keep + dpp_d<0x124>(send);  // row_ror 4: a partner whose lane bit 2 differs
-    }
-    double s;
-    {
-        const double keep = b3 ? d[1] : d[0], send = b3 ? d[0] : d[1];
-        s = keep + dpp_d<0x128>(send);     // row_ror 8: partner lane ^ 8
-    }
-    s += bperm_d(s, lane ^ 16);
-    s += bperm_d(s, lane ^ 32);
-    const int v = v0 + ((lane & 1) << 3 | (lane & 2) << 1 | (lane & 4) >> 1 | (lane & 8) >> 3);
+    const double s = wave_bfly16(d);
+    const int v = v0 + bfly_index(lane);
     if (lane < 16 && v < nv) red[v * NW + wave] = s;
 }
 
