@@ -165,6 +165,7 @@ struct BlockRed {
 struct OpConst {
     int n, H;
     double cd, a, c8, inv2h;
+    float invH;   // 1/H rounded to FP32: grid row of p as (int)((p + 0.5) invH), exact here
 };
 
 __device__ __forceinline__ OpConst op_const(const xkp_system &s) {
@@ -177,6 +178,7 @@ __device__ __forceinline__ OpConst op_const(const xkp_system &s) {
     o.a = g2 / (2.0 * h * h);
     o.c8 = g2 / (8.0 * h * h);
     o.inv2h = 1.0 / (2.0 * h);
+    o.invH = 1.0f / (float)s.H;
     return o;
 }
 
@@ -186,10 +188,10 @@ __device__ __forceinline__ bool desc_ok(const xkp_system &s, int nmax) {
            s.x != nullptr && s.dt > 0.0;
 }
 
-// The four neighbour coefficients of row p < n (Section 2.3: the lagged-density drift terms
-// and the drift field f, zero where the neighbour lies outside the grid).
-__device__ __forceinline__ void row_coeffs(const xkp_system &s, const OpConst &o, int p,
-                                           double &cE, double &cW, double &cN, double &cS) {
+// The antisymmetric parts ex, ey of row p < n's neighbour coefficients (Section 2.3: the
+// lagged-density drift terms and the drift field f; m~ and f zero outside the grid).
+__device__ __forceinline__ void row_drift(const xkp_system &s, const OpConst &o, int p,
+                                          double &ex, double &ey) {
     const int H = o.H;
     const double *__restrict__ mt = s.mt;
     const int i = p / H, j = p - (p / H) * H;
@@ -199,12 +201,29 @@ __device__ __forceinline__ void row_coeffs(const xkp_system &s, const OpConst &o
     const double mS = (j > 0) ? mt[p - 1] : 0.0;
     const double fxp = s.fx ? s.fx[p] : 0.0;
     const double fyp = s.fy ? s.fy[p] : 0.0;
-    const double ex = fxp * o.inv2h - o.c8 * (mE - mW);
-    const double ey = fyp * o.inv2h - o.c8 * (mN - mS);
-    cE = (i + 1 < H) ? -o.a + ex : 0.0;
-    cW = (i > 0) ? -o.a - ex : 0.0;
-    cN = (j + 1 < H) ? -o.a + ey : 0.0;
-    cS = (j > 0) ? -o.a - ey : 0.0;
+    ex = fxp * o.inv2h - o.c8 * (mE - mW);
+    ey = fyp * o.inv2h - o.c8 * (mN - mS);
+}
+
+// The four neighbour coefficients of row p from its ex, ey: -a +- ex (east, west) and -a +- ey
+// (north, south), zero where the neighbour lies outside the grid and for rows p >= n.
+__device__ __forceinline__ void coeffs_of(const OpConst &o, int p, double ex, double ey,
+                                          double &cE, double &cW, double &cN, double &cS) {
+    const int H = o.H;
+    const int i = (int)(((float)p + 0.5f) * o.invH), j = p - i * H;
+    const bool in = p < o.n;
+    cE = (in && i + 1 < H) ? -o.a + ex : 0.0;
+    cW = (in && i > 0) ? -o.a - ex : 0.0;
+    cN = (in && j + 1 < H) ? -o.a + ey : 0.0;
+    cS = (in && j > 0) ? -o.a - ey : 0.0;
+}
+
+// The four neighbour coefficients of row p < n.
+__device__ __forceinline__ void row_coeffs(const xkp_system &s, const OpConst &o, int p,
+                                           double &cE, double &cW, double &cN, double &cS) {
+    double ex, ey;
+    row_drift(s, o, p, ex, ey);
+    coeffs_of(o, p, ex, ey, cE, cW, cN, cS);
 }
 
 // BF16 bits of a double: rounded to FP32, then to the nearest BF16 (ties to even); finite

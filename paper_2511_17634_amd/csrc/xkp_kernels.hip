@@ -257,26 +257,42 @@ template <> struct Depth<32> { static constexpr int value = XKP_DEPTH32; };
 //   C_west  = -g^2/(2h^2) - f_x/(2h) + g^2/(8h^2) (m~_{i+1,j} - m~_{i-1,j})
 //   C_north = -g^2/(2h^2) + f_y/(2h) - g^2/(8h^2) (m~_{i,j+1} - m~_{i,j-1})
 //   C_south = -g^2/(2h^2) - f_y/(2h) + g^2/(8h^2) (m~_{i,j+1} - m~_{i,j-1})
-// (m~ and f zero outside the grid).  A coefficient whose neighbour lies outside the grid is stored
-// as zero, and rows n <= p < npad are zero, so the stencil needs no boundary branches.  C_diag is
-// the same for every row and stays a scalar.
+// (m~ and f zero outside the grid).  Systems of up to 4096 unknowns (whose workspace stays in the
+// caches) keep the four coefficients: a coefficient whose neighbour lies outside the grid is
+// stored as zero, and rows n <= p < npad are zero, so the stencil needs no boundary branches.
+// Larger systems, whose launches stream from HBM, keep only the antisymmetric parts ex, ey (in
+// the E and W arrays, zero for rows p >= n) and the stencil forms the four coefficients from
+// them (coeffs_of): 16 bytes of coefficients per row and operator application instead of 32.
+// Mixed precision keeps the four coefficients rounded to FP32 in both cases.  C_diag is the same
+// for every row and stays a scalar.
 struct Coef {
     double *E, *W, *N, *S;
     float *E32, *W32, *N32, *S32;   // FP32 copies (mixed precision)
 };
+
+// Whether systems of the row class RMAX keep ex, ey instead of the four coefficients.
+template <int RMAX>
+constexpr bool kDriftCoef = RMAX * kNT > 4096;
 
 template <int RMAX>
 __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &C, bool mixed) {
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) {
         const int p = row_of(k);
-        double cE = 0.0, cW = 0.0, cN = 0.0, cS = 0.0;
-        if (p < o.n) row_coeffs(s, o, p, cE, cW, cN, cS);
+        double ex = 0.0, ey = 0.0;
+        if (p < o.n) row_drift(s, o, p, ex, ey);
+        double cE, cW, cN, cS;
+        coeffs_of(o, p, ex, ey, cE, cW, cN, cS);
         const unsigned off = (unsigned)p * 8u;
-        bst(mkbuf(C.E, kNT * RMAX), off, cE);
-        bst(mkbuf(C.W, kNT * RMAX), off, cW);
-        bst(mkbuf(C.N, kNT * RMAX), off, cN);
-        bst(mkbuf(C.S, kNT * RMAX), off, cS);
+        if constexpr (kDriftCoef<RMAX>) {
+            bst(mkbuf(C.E, kNT * RMAX), off, ex);
+            bst(mkbuf(C.W, kNT * RMAX), off, ey);
+        } else {
+            bst(mkbuf(C.E, kNT * RMAX), off, cE);
+            bst(mkbuf(C.W, kNT * RMAX), off, cW);
+            bst(mkbuf(C.N, kNT * RMAX), off, cN);
+            bst(mkbuf(C.S, kNT * RMAX), off, cS);
+        }
         if (mixed) {
             const unsigned o4 = (unsigned)p * 4u;
             bstf(mkbuf32(C.E32, kNT * RMAX), o4, (float)cE);
@@ -304,8 +320,23 @@ __device__ __forceinline__ void stencil_lds(const double *u, const Coef &C, cons
         // rows q[0], q[1] of the pair; q[-1] and q[2] are their south and north neighbours
         const unsigned so = row_soff(k);
         const double *q = uc + k * kNT;
-        const double2_t cE = bld2(bE, lo, so), cW = bld2(bW, lo, so);
-        const double2_t cN = bld2(bN, lo, so), cS = bld2(bS, lo, so);
+        double2_t cE, cW, cN, cS;
+        if constexpr (kDriftCoef<RMAX>) {
+            const double2_t ex = bld2(bE, lo, so), ey = bld2(bW, lo, so);
+            const int p = row_of(k);
+            double e0, w0, n0, s0, e1, w1, n1, s1;
+            coeffs_of(o, p, ex[0], ey[0], e0, w0, n0, s0);
+            coeffs_of(o, p + 1, ex[1], ey[1], e1, w1, n1, s1);
+            cE = double2_t{e0, e1};
+            cW = double2_t{w0, w1};
+            cN = double2_t{n0, n1};
+            cS = double2_t{s0, s1};
+        } else {
+            cE = bld2(bE, lo, so);
+            cW = bld2(bW, lo, so);
+            cN = bld2(bN, lo, so);
+            cS = bld2(bS, lo, so);
+        }
         const double2_t u0 = *(const double2_t *)q;
         w[k] = o.cd * u0[0] + cE[0] * q[H] + cW[0] * q[-H] + cN[0] * u0[1] + cS[0] * q[-1];
         w[k + 1] = o.cd * u0[1] + cE[1] * q[H + 1] + cW[1] * q[1 - H] + cN[1] * q[2] + cS[1] * u0[0];
@@ -1543,10 +1574,15 @@ __device__ __forceinline__ int project_one(const xkp_system &s, xkp_info *info, 
                     const rsrc_t bN = mkbuf(C.N, kNT * RMAX), bS = mkbuf(C.S, kNT * RMAX);
 #pragma unroll
                     for (int q = 0; q < RMAX; ++q) {
-                        cEr[q] = bld(bE, row_off(q));
-                        cWr[q] = bld(bW, row_off(q));
-                        cNr[q] = bld(bN, row_off(q));
-                        cSr[q] = bld(bS, row_off(q));
+                        if constexpr (kDriftCoef<RMAX>) {
+                            coeffs_of(o, row_of(q), bld(bE, row_off(q)), bld(bW, row_off(q)),
+                                      cEr[q], cWr[q], cNr[q], cSr[q]);
+                        } else {
+                            cEr[q] = bld(bE, row_off(q));
+                            cWr[q] = bld(bW, row_off(q));
+                            cNr[q] = bld(bN, row_off(q));
+                            cSr[q] = bld(bS, row_off(q));
+                        }
                     }
                 }
                 const int H = o.H;
