@@ -42,14 +42,25 @@ HBM_PEAK_GBS = 8000.0
 # the same run (--copy-probe).  A record applies only to the kernel sources it was taken with
 # (digest), the restart length, workgroup size and projection placement it was taken at.
 TRAFFIC = {
-    # 64x64, 63 targets per launch: means over the last 100 polish (split projection) and plain
-    # launches; copy probe: 3 copies of 256 MiB read 131086.4 KiB and wrote 262144 KiB each
-    "c2_project": {"csrc_digest": "b6bf17eeea58a66e", "polish_m": 8, "waves": 4, "split": 0,
-                   "fetch_kib": 8307.28, "write_kib": 15157.00,
-                   "fetch_scale": 1.99978, "write_scale": 1.0},
-    "c2_plain": {"csrc_digest": "b6bf17eeea58a66e", "polish_m": 6, "waves": 4, "split": -1,
-                 "fetch_kib": 8066.89, "write_kib": 15070.93,
-                 "fetch_scale": 1.99978, "write_scale": 1.0},
+    # means over the last 100 dispatches of each launch kind in counter runs of this file with
+    # the launch choices of an unprofiled run (--tuning-from); copy probe: three 256 MiB copies
+    # read about 131086 KiB (FETCH_SIZE) and wrote 262144 KiB (WRITE_SIZE) each
+    "c2_project": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 8, "waves": 4, "split": 0,
+        "fetch_kib": 8311.22, "write_kib": 15195.13, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c2_plain": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 6, "waves": 4, "split": -1,
+        "fetch_kib": 8073.39, "write_kib": 15309.84, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c3_project_mixed": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 11947511.12, "write_kib": 2567722.09, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_project_fp64": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 16, "split": 0,
+        "fetch_kib": 16504383.40, "write_kib": 5065763.88, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_mixed": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 7880076.12, "write_kib": 1672486.40, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_fp64": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 16, "split": -1,
+        "fetch_kib": 12541608.81, "write_kib": 3936739.75, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "uneven_project": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 8, "split": 0,
+        "fetch_kib": 73167228.42, "write_kib": 21209354.67, "fetch_scale": 1.99977, "write_scale": 1.0},
+    "uneven_plain": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 10, "waves": 8, "split": -1,
+        "fetch_kib": 57584625.60, "write_kib": 17149257.42, "fetch_scale": 1.99977, "write_scale": 1.0},
 }
 
 
@@ -448,10 +459,13 @@ def learned_leg(args):
             "guess_better_frac": round(float((ti["guess_res"] < tp["guess_res"]).mean()), 4)}
     keys = sorted(floor)
     fl = np.array([floor[q] for q in keys])
+    fin = fl[np.isfinite(fl)]
     at = lambda inf: np.array([inf["guess_res"][t, i] for t, i in keys])
     sample = {"targets": len({i for _, i in keys}), "timesteps": sorted({t + 1 for t, _ in keys}),
-              "median_floor": float(f"{np.median(fl):.4g}"),
-              "min_floor": float(f"{fl.min():.4g}"),
+              # a least-squares solve that returned a non-finite value is left out and counted
+              "median_floor": float(f"{np.median(fin):.4g}") if fin.size else None,
+              "min_floor": float(f"{fin.min():.4g}") if fin.size else None,
+              "non_finite_floors": int(fl.size - fin.size),
               "median_projection": float(f"{np.median(at(tp)):.4g}"),
               "median_learned": float(f"{np.median(at(infos['learned_gate_inf'])):.4g}"),
               "median_correction": float(f"{np.median(at(infos['learned_correction'])):.4g}"),
@@ -657,6 +671,17 @@ def apply_tuning(b, rec):
                                    seed_rows=rec["seed_rows_per_thread"])
     return xkp.Tuning(polish_m=rec["polish_m"], wg_per_cu=rec["wg_per_cu"], waves=rec["waves"],
                       split=rec["split"])
+
+
+def finite(o):
+    """The record with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(o, float):
+        return o if np.isfinite(o) else None
+    if isinstance(o, dict):
+        return {k: finite(v) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [finite(v) for v in o]
+    return o
 
 
 def save_tuning(args):
@@ -972,12 +997,22 @@ def main():
     from paper_2511_17634_amd.driver import Batch, Chain
 
     xkp.load()
+    if args.copy_probe:
+        # a device copy of known size, the scale of the HBM counters of a --pmc run
+        import torch
+        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"# copy probe: 3 copies of {args.copy_probe} MiB", file=sys.stderr, flush=True)
+        del src, dst
     if args.only:
         rec = {"uneven": uneven_leg, "mixed": mixed_leg, "learned": learned_leg,
                "cycle": cycle_leg, "epilogue": epilogue_leg, "picard": picard_leg,
                "cluster": cluster_leg}[args.only](args)
         save_tuning(args)
-        print(json.dumps(rec), flush=True)
+        print(json.dumps(finite(rec)), flush=True)
         return
     cfg, s0, t0 = build_c2()
     H, T, m = cfg.groups[0].H, cfg.T, cfg.m
@@ -989,15 +1024,6 @@ def main():
         cfg3, s3, t3 = build_c3()
         orc = OracleRecord(cfg3.groups[0].H, cfg3.T, cfg3.m, s3, t3, [0, 127, 254])
 
-    if args.copy_probe:
-        import torch
-        src = torch.ones(args.copy_probe << 17, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"# copy probe: 3 copies of {args.copy_probe} MiB", file=sys.stderr, flush=True)
-        del src, dst
     wanted = args.legs.split(",")
     legs, tunings, launch, roofs = {}, {}, {}, {}
     for name, method, mode, warm in (("project", "project", "target_galerkin", False),
@@ -1138,7 +1164,7 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     save_tuning(args)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite(out)), flush=True)
 
 
 if __name__ == "__main__":
