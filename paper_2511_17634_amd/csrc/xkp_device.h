@@ -218,6 +218,20 @@ __device__ __forceinline__ void coeffs_of(const OpConst &o, int p, double ex, do
     cS = (in && j > 0) ? -o.a - ey : 0.0;
 }
 
+// The same in FP32 from FP32 parts (the mixed-precision operator): -a +- ex, -a +- ey formed in
+// FP32, zero where the neighbour lies outside the grid and for rows p >= n.
+__device__ __forceinline__ void coeffs_of_f32(const OpConst &o, int p, float ex, float ey,
+                                              float &cE, float &cW, float &cN, float &cS) {
+    const int H = o.H;
+    const int i = (int)(((float)p + 0.5f) * o.invH), j = p - i * H;
+    const bool in = p < o.n;
+    const float a = (float)o.a;
+    cE = (in && i + 1 < H) ? -a + ex : 0.0f;
+    cW = (in && i > 0) ? -a - ex : 0.0f;
+    cN = (in && j + 1 < H) ? -a + ey : 0.0f;
+    cS = (in && j > 0) ? -a - ey : 0.0f;
+}
+
 // The four neighbour coefficients of row p < n.
 __device__ __forceinline__ void row_coeffs(const xkp_system &s, const OpConst &o, int p,
                                            double &cE, double &cW, double &cN, double &cS) {

@@ -263,8 +263,9 @@ template <> struct Depth<32> { static constexpr int value = XKP_DEPTH32; };
 // Larger systems, whose launches stream from HBM, keep only the antisymmetric parts ex, ey (in
 // the E and W arrays, zero for rows p >= n) and the stencil forms the four coefficients from
 // them (coeffs_of): 16 bytes of coefficients per row and operator application instead of 32.
-// Mixed precision keeps the four coefficients rounded to FP32 in both cases.  C_diag is the same
-// for every row and stays a scalar.
+// Mixed precision keeps FP32 copies the same way: the four coefficients rounded to FP32, or the
+// two parts rounded to FP32 with the coefficients formed in FP32 (coeffs_of_f32; 8 bytes per
+// row instead of 16).  C_diag is the same for every row and stays a scalar.
 struct Coef {
     double *E, *W, *N, *S;
     float *E32, *W32, *N32, *S32;   // FP32 copies (mixed precision)
@@ -295,10 +296,15 @@ __device__ void build_coeffs(const xkp_system &s, const OpConst &o, const Coef &
         }
         if (mixed) {
             const unsigned o4 = (unsigned)p * 4u;
-            bstf(mkbuf32(C.E32, kNT * RMAX), o4, (float)cE);
-            bstf(mkbuf32(C.W32, kNT * RMAX), o4, (float)cW);
-            bstf(mkbuf32(C.N32, kNT * RMAX), o4, (float)cN);
-            bstf(mkbuf32(C.S32, kNT * RMAX), o4, (float)cS);
+            if constexpr (kDriftCoef<RMAX>) {
+                bstf(mkbuf32(C.E32, kNT * RMAX), o4, (float)ex);
+                bstf(mkbuf32(C.W32, kNT * RMAX), o4, (float)ey);
+            } else {
+                bstf(mkbuf32(C.E32, kNT * RMAX), o4, (float)cE);
+                bstf(mkbuf32(C.W32, kNT * RMAX), o4, (float)cW);
+                bstf(mkbuf32(C.N32, kNT * RMAX), o4, (float)cN);
+                bstf(mkbuf32(C.S32, kNT * RMAX), o4, (float)cS);
+            }
         }
     }
 }
@@ -362,8 +368,23 @@ __device__ __forceinline__ void stencil_lds_f32(const double *u, const Coef &C, 
     for (int k = 0; k < RMAX; k += 2) {
         const unsigned so = (unsigned)(k * kNT * 4);
         const double *q = uc + k * kNT;
-        const f32x2_t cE = bldf2(bE, lo, so), cW = bldf2(bW, lo, so);
-        const f32x2_t cN = bldf2(bN, lo, so), cS = bldf2(bS, lo, so);
+        f32x2_t cE, cW, cN, cS;
+        if constexpr (kDriftCoef<RMAX>) {
+            const f32x2_t ex = bldf2(bE, lo, so), ey = bldf2(bW, lo, so);
+            const int p = row_of(k);
+            float e0, w0, n0, s0, e1, w1, n1, s1;
+            coeffs_of_f32(o, p, ex[0], ey[0], e0, w0, n0, s0);
+            coeffs_of_f32(o, p + 1, ex[1], ey[1], e1, w1, n1, s1);
+            cE = f32x2_t{e0, e1};
+            cW = f32x2_t{w0, w1};
+            cN = f32x2_t{n0, n1};
+            cS = f32x2_t{s0, s1};
+        } else {
+            cE = bldf2(bE, lo, so);
+            cW = bldf2(bW, lo, so);
+            cN = bldf2(bN, lo, so);
+            cS = bldf2(bS, lo, so);
+        }
         const double2_t u0 = *(const double2_t *)q;
         const float y0 = cd * (float)u0[0] + cE[0] * (float)q[H] + cW[0] * (float)q[-H]
                          + cN[0] * (float)u0[1] + cS[0] * (float)q[-1];
