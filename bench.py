@@ -45,22 +45,22 @@ TRAFFIC = {
     # means over the last 100 dispatches of each launch kind in counter runs of this file with
     # the launch choices of an unprofiled run (--tuning-from); copy probe: three 256 MiB copies
     # read about 131086 KiB (FETCH_SIZE) and wrote 262144 KiB (WRITE_SIZE) each
-    "c2_project": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 8, "waves": 4, "split": 0,
-        "fetch_kib": 8311.22, "write_kib": 15195.13, "fetch_scale": 1.99978, "write_scale": 1.0},
-    "c2_plain": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 6, "waves": 4, "split": -1,
-        "fetch_kib": 8073.39, "write_kib": 15309.84, "fetch_scale": 1.99978, "write_scale": 1.0},
-    "c3_project_mixed": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 15, "waves": 8, "split": -1,
-        "fetch_kib": 11947511.12, "write_kib": 2567722.09, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_project_fp64": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 16, "split": 0,
-        "fetch_kib": 16504383.40, "write_kib": 5065763.88, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_plain_mixed": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 15, "waves": 8, "split": -1,
-        "fetch_kib": 7880076.12, "write_kib": 1672486.40, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_plain_fp64": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 16, "split": -1,
-        "fetch_kib": 12541608.81, "write_kib": 3936739.75, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "uneven_project": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 9, "waves": 8, "split": 0,
-        "fetch_kib": 73167228.42, "write_kib": 21209354.67, "fetch_scale": 1.99977, "write_scale": 1.0},
-    "uneven_plain": {"csrc_digest": "e982fb18325d5ed2", "polish_m": 10, "waves": 8, "split": -1,
-        "fetch_kib": 57584625.60, "write_kib": 17149257.42, "fetch_scale": 1.99977, "write_scale": 1.0},
+    "c2_project": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 8, "waves": 4, "split": 0,
+        "fetch_kib": 8311.13, "write_kib": 14945.80, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c2_plain": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 6, "waves": 4, "split": -1,
+        "fetch_kib": 8073.15, "write_kib": 15512.80, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c3_project_mixed": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 9602830.23, "write_kib": 2493549.81, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_project_fp64": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 9, "waves": 16, "split": 0,
+        "fetch_kib": 16503574.91, "write_kib": 5065191.69, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_mixed": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 6675219.96, "write_kib": 1634448.85, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_fp64": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 9, "waves": 16, "split": -1,
+        "fetch_kib": 12545842.12, "write_kib": 3936306.55, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "uneven_project": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 10, "waves": 8, "split": 0,
+        "fetch_kib": 73164216.60, "write_kib": 21209961.82, "fetch_scale": 1.99977, "write_scale": 1.0},
+    "uneven_plain": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 10, "waves": 8, "split": -1,
+        "fetch_kib": 57582500.60, "write_kib": 17149764.39, "fetch_scale": 1.99977, "write_scale": 1.0},
 }
 
 
