@@ -989,8 +989,8 @@ def main():
         with open(args.tuning_from) as f:
             FIXED_TUNING.update(json.load(f))
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path is "
+              "built and measured on one GPU only)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2511_17634_amd import xkp
