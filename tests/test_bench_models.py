@@ -112,3 +112,18 @@ def test_polish_bytes_and_projection_roofline_by_hand():
     assert rp["bound"] == "mfma" and rp["peak"] == 78.6 and rp["unit"] == "TFLOP/s"
     assert rp["achieved"] == round(fl / 2e-5 / 1e12, 3) and rp["flops_per_launch"] == int(fl)
     assert bench.projection_roofline("p", [n] * 3, inf, 2e-5, mixed=True)["peak"] == 2500.0
+
+
+def test_paper_context_ratios():
+    """The paper's Table 4 reductions are quoted as given, and this run's ratios follow from the
+    record: projection over plain GMRES, and the oracle's projection against its banded LU."""
+    import bench
+    out = {"value": 150.0, "plain_gmres": {"value": 300.0},
+           "cpu_baseline": {"per_system_ms_one_core": {"banded_lu_ms": 10.0,
+                                                       "projection_polish_ms": 7.5}}}
+    ctx = bench.paper_context(out)
+    assert ctx["reduction"] == {"32x32": 0.158, "64x64": 0.298, "128x128": 0.437}
+    assert ctx["this_run"]["gpu_projection_over_plain_gmres"] == 0.5
+    assert ctx["this_run"]["cpu_oracle_projection_vs_banded_lu_reduction"] == 0.25
+    assert "cpu_oracle_projection_vs_banded_lu_reduction" not in bench.paper_context(
+        {"value": 1.0, "plain_gmres": {"value": 2.0}})["this_run"]
