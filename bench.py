@@ -712,8 +712,8 @@ def save_tuning(args):
 def tune(b, args, key):
     """The library's autotuners on a driver Batch (see Batch.autotune); with --split off the
     projection then stays inside the solve launch.  With --tuning-from the leg `key` takes the
-    stored choices instead."""
-    if FIXED_TUNING:
+    stored choices instead (a leg the file does not hold is tuned as usual)."""
+    if key in FIXED_TUNING:
         t = apply_tuning(b, FIXED_TUNING[key])
     else:
         t = b.autotune()

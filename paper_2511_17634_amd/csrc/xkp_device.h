@@ -288,17 +288,25 @@ __device__ inline bool lsq_hessenberg_wave(double *A, int lda, int kk, double *z
     return false;
 }
 
-// LU with partial pivoting of the kk x kk row-major LDS matrix A (leading dimension lda,
-// kk <= KM) by one wavefront, lane r holding row r in registers.  Per column the pivot is the
-// largest remaining |A[r][c]| (lowest lane on ties); rows are not moved: the pivot lane writes
-// its row's remaining entries to rowbuf (LDS, KM doubles, 16-byte aligned), every lane reads
-// them back as broadcasts and updates its row in place.  zr is lane r's right-hand side entry;
-// the solution goes to out[0..kk) in LDS.  A pivot <= 1e-13 max|A| reports singular (true).
-// The column loops are unrolled to KM, so every register index is a constant.
+// LU with partial pivoting of the kk x kk row-major LDS matrix A (leading dimension lda >= KM,
+// even; A 16-byte aligned; kk <= KM, KM a multiple of 8) by one wavefront, lane r holding row r
+// in registers.  Per column the pivot is the largest remaining |A[r][c]| (lowest lane on ties);
+// rows are not moved.  The registers hold the columns from the current one on: after each
+// elimination step every row shifts down by one register, so the column loop is a plain loop
+// and the code stays small (one wave runs this once per system, from a cold instruction cache;
+// a fully unrolled column loop spent much of its time fetching instructions).  The pivot lane of
+// column c stores its row (columns c, c+1, ...) over row c of A and its right-hand side entry
+// in zbuf[c] (LDS, kk doubles); every lane reads them back as broadcasts.  Stores, reads and
+// updates go in chunks of 8 registers, and chunks wholly past the last column are skipped
+// (they hold zeros and stay so).  Back substitution then runs on the stored rows.  zr is lane
+// r's right-hand side entry; the solution goes to out[0..kk) in LDS.  A pivot <= 1e-13 max|A|
+// reports singular (true).  A is overwritten.
 template <int KM>
-__device__ __forceinline__ bool lu_regs(const double *A, int lda, int kk, double zr, double *out,
-                                        double *rowbuf) {
+__device__ __forceinline__ bool lu_regs(double *A, int lda, int kk, double zr, double *out,
+                                        double *zbuf) {
     typedef double d2_t __attribute__((ext_vector_type(2)));
+    constexpr int CH = 8;
+    static_assert(KM % CH == 0, "whole chunks");
     const int r = threadIdx.x & 63;
     kk = __builtin_amdgcn_readfirstlane(kk);
     double a[KM];
@@ -310,50 +318,58 @@ __device__ __forceinline__ bool lu_regs(const double *A, int lda, int kk, double
     }
     const double amax = wave_max(rowmax);
     if (!(amax > 0.0)) return true;
+    wave_lds_sync();   // every row read before pivot rows are stored over A
     bool active = r < kk;
-    int pc = KM;          // the column this lane's row is the pivot of
-    double rp = 0.0;      // the reciprocal of that pivot
-    int pl_of = 0;        // lane c: the pivot lane of column c
+#pragma unroll 1
+    for (int c = 0; c < kk; ++c) {
+        const double v = active ? fabs(a[0]) : -1.0;
+        const double vmax = wave_max(v);
+        if (!(vmax > 1e-13 * amax)) return true;
+        const int pl = __ffsll((unsigned long long)__ballot(active && v == vmax)) - 1;
+        // registers [0, live) hold columns c..kk-1; a chunk starting at q0 <= live still sets
+        // register q0 - 1, so it runs (its stored entries past the last column are zeros)
+        const int live = kk - c;
+        double *U = A + c * lda;
+        if (r == pl) {
 #pragma unroll
-    for (int c = 0; c < KM; ++c) {
-        if (c < kk) {
-            const double v = active ? fabs(a[c]) : -1.0;
-            const double vmax = wave_max(v);
-            if (!(vmax > 1e-13 * amax)) return true;
-            const int pl = __ffsll((unsigned long long)__ballot(active && v == vmax)) - 1;
-            if (r == c) pl_of = pl;
-            if (r == pl) {
+            for (int q0 = 0; q0 < KM; q0 += CH)
+                if (q0 <= live) {
 #pragma unroll
-                for (int q = c & ~1; q < KM; q += 2) *(d2_t *)(rowbuf + q) = d2_t{a[q], a[q + 1]};
-            }
-            wave_lds_sync();
-            const double piv = rowbuf[c];
-            if (r == pl) {
-                active = false;
-                pc = c;
-                rp = 1.0 / piv;
-            }
-            const double l = active ? a[c] / piv : 0.0;
-#pragma unroll
-            for (int q = (c + 1) & ~1; q < KM; q += 2) {
-                const d2_t u = *(const d2_t *)(rowbuf + q);
-                if (q > c) a[q] -= l * u[0];
-                a[q + 1] -= l * u[1];
-            }
-            zr -= l * readlane_d(zr, pl);
-            wave_lds_sync();   // read before the next pivot row is written
+                    for (int q = q0; q < q0 + CH; q += 2) *(d2_t *)(U + q) = d2_t{a[q], a[q + 1]};
+                }
+            zbuf[c] = zr;
+            active = false;
         }
-    }
-    // back substitution on the pivot rows, last column first
+        wave_lds_sync();
+        const double l = active ? a[0] / U[0] : 0.0;
+        // column c + q of the row minus l times the pivot row's, into register q - 1
 #pragma unroll
-    for (int c = KM - 1; c >= 0; --c) {
-        if (c < kk) {
-            const int pl = __builtin_amdgcn_readlane(pl_of, c);
-            const double xc = readlane_d(zr, pl) * readlane_d(rp, pl);
-            if (pc < c) zr -= a[c] * xc;
-            if (r == 0) out[c] = xc;
-        }
+        for (int q0 = 0; q0 < KM; q0 += CH)
+            if (q0 <= live) {
+#pragma unroll
+                for (int q = q0; q < q0 + CH; q += 2) {
+                    const d2_t u = *(const d2_t *)(U + q);
+                    if (q > 0) a[q - 1] = a[q] - l * u[0];
+                    a[q] = a[q + 1] - l * u[1];
+                }
+            }
+        a[KM - 1] = 0.0;
+        zr -= l * zbuf[c];
     }
+    // back substitution on the stored pivot rows, last column first: lane r holds pivot row
+    // r's right-hand side entry and the reciprocal of its pivot; row r's entry of column c is
+    // A[r * lda + c - r]
+    const double rp = r < kk ? 1.0 / A[r * lda] : 0.0;
+    double zb = r < kk ? zbuf[r] : 0.0;
+    double unext = r < kk - 1 ? A[r * lda + (kk - 1 - r)] : 0.0;
+#pragma unroll 1
+    for (int c = kk - 1; c >= 0; --c) {
+        const double u = unext;
+        unext = r < c - 1 ? A[r * lda + (c - 1 - r)] : 0.0;
+        const double xc = readlane_d(zb, c) * readlane_d(rp, c);
+        if (r < c) zb -= u * xc;
+    }
+    if (r < kk) out[r] = zb * rp;
     wave_lds_sync();
     return false;
 }

@@ -467,8 +467,8 @@ __global__ __launch_bounds__(NT, 2) void gram_kernel(Args A) {
         }
         // the target's slots summed in tile order into the LDS matrix (row-major, LDA)
         double *Ap = proj_lds;
-        double *rowbuf = Ap + (KMX + 1) * LDA;   // the LU's pivot row (16-byte aligned)
-        double *zl = rowbuf + KMX;
+        double *zbuf = Ap + (KMX + 1) * LDA;   // the LU's stored right-hand side entries
+        double *zl = zbuf + KMX;
         double *al = zl + KMX + 1;
         const int nc = k + 1;
         const int first = A.tpt > 1 ? t * A.tpt : slot;
@@ -516,10 +516,10 @@ __global__ __launch_bounds__(NT, 2) void gram_kernel(Args A) {
         } else if (wave == 0) {
             // the Galerkin modes: the right-hand side z is column k
             const double zr = lane < k ? Ap[lane * LDA + k] : 0.0;
-            if (k <= 16) singular = lu_regs<16>(Ap, LDA, k, zr, al, rowbuf);
-            else if (k <= 32) singular = lu_regs<32>(Ap, LDA, k, zr, al, rowbuf);
-            else if (k <= 48) singular = lu_regs<48>(Ap, LDA, k, zr, al, rowbuf);
-            else singular = lu_regs<64>(Ap, LDA, k, zr, al, rowbuf);
+            if (k <= 16) singular = lu_regs<16>(Ap, LDA, k, zr, al, zbuf);
+            else if (k <= 32) singular = lu_regs<32>(Ap, LDA, k, zr, al, zbuf);
+            else if (k <= 48) singular = lu_regs<48>(Ap, LDA, k, zr, al, zbuf);
+            else singular = lu_regs<64>(Ap, LDA, k, zr, al, zbuf);
         }
         if (wave == 0) {
             if (!singular && lane < k) A.alpha[(size_t)t * KMX + lane] = al[lane];
