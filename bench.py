@@ -45,22 +45,22 @@ TRAFFIC = {
     # means over the last 100 dispatches of each launch kind in counter runs of this file with
     # the launch choices of an unprofiled run (--tuning-from); copy probe: three 256 MiB copies
     # read about 131086 KiB (FETCH_SIZE) and wrote 262144 KiB (WRITE_SIZE) each
-    "c2_project": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 8, "waves": 4, "split": 0,
-        "fetch_kib": 8311.13, "write_kib": 14945.80, "fetch_scale": 1.99978, "write_scale": 1.0},
-    "c2_plain": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 6, "waves": 4, "split": -1,
-        "fetch_kib": 8073.15, "write_kib": 15512.80, "fetch_scale": 1.99978, "write_scale": 1.0},
-    "c3_project_mixed": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 15, "waves": 8, "split": -1,
-        "fetch_kib": 9602830.23, "write_kib": 2493549.81, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_project_fp64": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 9, "waves": 16, "split": 0,
-        "fetch_kib": 16503574.91, "write_kib": 5065191.69, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_plain_mixed": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 15, "waves": 8, "split": -1,
-        "fetch_kib": 6675219.96, "write_kib": 1634448.85, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "c3_plain_fp64": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 9, "waves": 16, "split": -1,
-        "fetch_kib": 12545842.12, "write_kib": 3936306.55, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "uneven_project": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 10, "waves": 8, "split": 0,
-        "fetch_kib": 73164216.60, "write_kib": 21209961.82, "fetch_scale": 1.99977, "write_scale": 1.0},
-    "uneven_plain": {"csrc_digest": "4688c388c2ff48d9", "polish_m": 10, "waves": 8, "split": -1,
-        "fetch_kib": 57582500.60, "write_kib": 17149764.39, "fetch_scale": 1.99977, "write_scale": 1.0},
+    "c2_project": {"csrc_digest": "b82947a142d54c38", "polish_m": 8, "waves": 4, "split": 0,
+        "fetch_kib": 8312.19, "write_kib": 15314.77, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c2_plain": {"csrc_digest": "b82947a142d54c38", "polish_m": 6, "waves": 4, "split": -1,
+        "fetch_kib": 8074.26, "write_kib": 15234.25, "fetch_scale": 1.99978, "write_scale": 1.0},
+    "c3_project_mixed": {"csrc_digest": "b82947a142d54c38", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 9600652.47, "write_kib": 2493507.40, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_project_fp64": {"csrc_digest": "b82947a142d54c38", "polish_m": 9, "waves": 16, "split": 0,
+        "fetch_kib": 16500537.72, "write_kib": 5064994.66, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_mixed": {"csrc_digest": "b82947a142d54c38", "polish_m": 15, "waves": 8, "split": -1,
+        "fetch_kib": 6675145.78, "write_kib": 1634356.40, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "c3_plain_fp64": {"csrc_digest": "b82947a142d54c38", "polish_m": 9, "waves": 16, "split": -1,
+        "fetch_kib": 12545493.88, "write_kib": 3936355.23, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "uneven_project": {"csrc_digest": "b82947a142d54c38", "polish_m": 10, "waves": 8, "split": 0,
+        "fetch_kib": 73163708.50, "write_kib": 21209936.27, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "uneven_plain": {"csrc_digest": "b82947a142d54c38", "polish_m": 10, "waves": 8, "split": -1,
+        "fetch_kib": 57586063.90, "write_kib": 17149819.58, "fetch_scale": 1.9998, "write_scale": 1.0},
 }
 
 
