@@ -57,10 +57,11 @@ TRAFFIC = {
         "fetch_kib": 6675145.78, "write_kib": 1634356.40, "fetch_scale": 1.9998, "write_scale": 1.0},
     "c3_plain_fp64": {"csrc_digest": "b82947a142d54c38", "polish_m": 9, "waves": 16, "split": -1,
         "fetch_kib": 12545493.88, "write_kib": 3936355.23, "fetch_scale": 1.9998, "write_scale": 1.0},
-    "uneven_project": {"csrc_digest": "b82947a142d54c38", "polish_m": 10, "waves": 8, "split": 0,
-        "fetch_kib": 73163708.50, "write_kib": 21209936.27, "fetch_scale": 1.9998, "write_scale": 1.0},
+    "uneven_project": {"csrc_digest": "b82947a142d54c38", "polish_m": 9, "waves": 8, "split": 0,
+        "m": 30, "fetch_kib": 74526416.47, "write_kib": 22978637.78, "fetch_scale": 1.9998,
+        "write_scale": 1.0},
     "uneven_plain": {"csrc_digest": "b82947a142d54c38", "polish_m": 10, "waves": 8, "split": -1,
-        "fetch_kib": 57586063.90, "write_kib": 17149819.58, "fetch_scale": 1.9998, "write_scale": 1.0},
+        "fetch_kib": 57597886.69, "write_kib": 17150009.10, "fetch_scale": 1.9998, "write_scale": 1.0},
 }
 
 
@@ -79,12 +80,14 @@ def csrc_digest():
 
 def traffic_bytes(name, polish_m):
     """HBM bytes per launch of the launch kind `name` from its stored counter record, or None if
-    there is none, the sources have changed or the restart length differs."""
+    there is none, the sources have changed, or the restart length, launch shape, projection
+    placement or (where the record has one) the seeds' basis dimension m differs."""
     tr = TRAFFIC.get(name)
     if tr is None or csrc_digest() != tr["csrc_digest"] or tr["polish_m"] != polish_m:
         return None
     tu = TUNED.get(name)
-    if tu is not None and (tu["waves"] != tr["waves"] or (tu["split"] >= 0) != (tr["split"] >= 0)):
+    if tu is not None and (tu["waves"] != tr["waves"] or (tu["split"] >= 0) != (tr["split"] >= 0)
+                           or tu.get("m", tr.get("m")) != tr.get("m")):
         return None
     return int(1024 * (tr["fetch_kib"] * tr["fetch_scale"]
                        + tr["write_kib"] * tr["write_scale"]))
@@ -271,22 +274,57 @@ def err_vs_oracle(rec_gpu, rec_o):
     return (num / den).max(axis=0), num.max(axis=0)
 
 
+def pick_uneven_m(args, cfg4, groups):
+    """The seeds' basis dimension m of the projected uneven batch, which the workload leaves
+    open: each candidate (--uneven-m) is autotuned, then its first --m-probe-steps timesteps
+    are timed eagerly after one untimed step; the fastest is kept.  Returns (m, {m: ms per
+    timestep})."""
+    import torch
+    from paper_2511_17634_amd.driver import Batch
+    cands = [int(v) for v in args.uneven_m.split(",") if v.strip()]
+    fixed = FIXED_TUNING.get("uneven_project", {}).get("m")
+    if fixed is not None or len(cands) == 1 or args.no_tune:
+        return (int(fixed) if fixed is not None else (cands[0] if len(cands) == 1 else cfg4.m)), {}
+    ms = {}
+    for m in cands:
+        b = Batch(groups, cfg4.T, m, method="project", mode="target_galerkin",
+                  reorth=args.reorth)
+        b.autotune(cache=args.tuning_cache)
+        b.reset()
+        b.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.m_probe_steps):
+            b.step()
+        torch.cuda.synchronize()
+        ms[m] = round((time.perf_counter() - t0) * 1e3 / args.m_probe_steps, 3)
+        del b
+    best = min(ms, key=ms.get)
+    print(f"# uneven m probe (ms per timestep): {ms}, m = {best}", file=sys.stderr, flush=True)
+    return best, ms
+
+
 def uneven_leg(args):
     """Uneven batch: 32x32 / 64x64 / 128x128 x 3 channels, one launch per timestep."""
     from paper_2511_17634_amd.driver import Batch
     graph = not args.eager
     cfg4, groups = build_c4()
+    m_proj, m_probe = pick_uneven_m(args, cfg4, groups)
     un = {}
     for name, method in (("project", "project"), ("plain", "plain")):
-        b = Batch(groups, cfg4.T, cfg4.m, method=method, mode="target_galerkin",
+        m = m_proj if method == "project" else cfg4.m
+        b = Batch(groups, cfg4.T, m, method=method, mode="target_galerkin",
                   reorth=args.reorth)
         tu = None if args.no_tune else tune(b, args, f"uneven_{name}")
+        if method == "project" and f"uneven_{name}" in TUNED:
+            TUNED[f"uneven_{name}"]["m"] = m
         r = time_chain(b, args, args.uneven_steps, 1, graph)
         lm = target_call_ms(b)
         ro, rp, ph = target_rooflines(b, f"{b.N} systems of three sizes per launch", r,
                                       method == "project", lm,
                                       traffic_key=f"uneven_{name}")
         un[name] = {"value": round(b.N * cfg4.T / r["per_chain_s"], 2),
+                    "m": m,
                     "ms_per_chain": round(r["per_chain_s"] * 1e3, 2),
                     "target_phase_value": round(b.N * cfg4.T / (sum(lm) / 1e3), 2),
                     "mean_iters": round(r["iters_mean"], 2), "verified": r["ok"],
@@ -304,8 +342,8 @@ def uneven_leg(args):
               file=sys.stderr, flush=True)
         del b
     return {"workload": cfg4.name, "targets": sum(g.N * g.C for g in groups),
-            "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": cfg4.m,
-            "unit": "target systems/s", **un}
+            "seeds": sum(g.C for g in groups), "timesteps": cfg4.T, "m": m_proj,
+            "m_probe_ms_per_step": m_probe, "unit": "target systems/s", **un}
 
 
 def mixed_leg(args, orc=None):
@@ -642,35 +680,20 @@ def epilogue_leg(args):
 # launch choices per leg (keys as in TRAFFIC): written by --tuning-out, applied by --tuning-from
 TUNED = {}
 FIXED_TUNING = {}
+# legs whose launch choices came from / were added to the --tuning-cache file
+CACHE_HITS, CACHE_MISSES = [], []
 
 
 def tuning_record(b, t):
-    """The launch choices a leg runs with: polish restart length, target launch shape and
-    projection placement, and the seed context's launch shape and seed width."""
-    ts = getattr(b, "seed_tuning", None)
-    return {"polish_m": int(b.params.polish_m), "waves": int(t.waves),
-            "wg_per_cu": int(t.wg_per_cu), "split": int(getattr(b.ctx, "split", -1)),
-            "seed_waves": None if ts is None else int(ts.waves),
-            "seed_wg_per_cu": None if ts is None else int(ts.wg_per_cu),
-            "seed_rows_per_thread": None if ts is None else int(ts.seed_rows)}
+    """The launch choices a leg runs with (Batch.tuning_record)."""
+    return b.tuning_record(t)
 
 
 def apply_tuning(b, rec):
     """Set a leg's launch choices from a record of tuning_record instead of autotuning (runs
     under a counter profiler, whose serialised dispatches would mislead the autotuners).
     Returns the Tuning the autotuner would have."""
-    from paper_2511_17634_amd import xkp
-    b.params.polish_m = rec["polish_m"]
-    b.ctx.set_launch(rec["waves"], rec["wg_per_cu"])
-    b.ctx.set_projection_split(rec["split"])
-    b.seed_tuning = None
-    if rec["seed_waves"] is not None and b.with_seeds and b.ctx_seed is not b.ctx:
-        b.ctx_seed.set_launch(rec["seed_waves"], rec["seed_wg_per_cu"])
-        b.ctx_seed.set_seed_width(rec["seed_rows_per_thread"])
-        b.seed_tuning = xkp.Tuning(waves=rec["seed_waves"], wg_per_cu=rec["seed_wg_per_cu"],
-                                   seed_rows=rec["seed_rows_per_thread"])
-    return xkp.Tuning(polish_m=rec["polish_m"], wg_per_cu=rec["wg_per_cu"], waves=rec["waves"],
-                      split=rec["split"])
+    return b.apply_tuning(rec)
 
 
 def paper_context(out):
@@ -716,7 +739,8 @@ def tune(b, args, key):
     if key in FIXED_TUNING:
         t = apply_tuning(b, FIXED_TUNING[key])
     else:
-        t = b.autotune()
+        t = b.autotune(cache=args.tuning_cache)
+        (CACHE_HITS if b.tuned_from_cache else CACHE_MISSES).append(key)
         if args.split == "off":
             b.ctx.set_projection_split(-1)
     TUNED[key] = tuning_record(b, t)
@@ -1000,6 +1024,14 @@ def main():
     ap.add_argument("--tuning-from", metavar="PATH",
                     help="take every leg's launch choices from a --tuning-out file instead of "
                          "autotuning (for runs under a counter profiler)")
+    ap.add_argument("--tuning-cache", metavar="PATH",
+                    help="launch choices cached by device and workload (JSON): a leg found "
+                         "there is not autotuned, a leg that is not is autotuned and added")
+    ap.add_argument("--uneven-m", default="30,40,60",
+                    help="candidates of the seeds' basis dimension m for the projected uneven "
+                         "batch (one value: no probe)")
+    ap.add_argument("--m-probe-steps", type=int, default=10,
+                    help="timesteps timed per m candidate")
     ap.add_argument("--split", choices=("auto", "off"), default="auto",
                     help="projection placement: autotuned (inside the solve launch or in "
                          "launches of its own), or always inside the solve launch")
@@ -1183,6 +1215,9 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(H, T, m, s0, t0, args.cpu_targets, args.cpu_steps)
     out["paper_context"] = paper_context(out)
+    if args.tuning_cache:
+        out["tuning_cache"] = {"path": args.tuning_cache, "hits": CACHE_HITS,
+                               "tuned_and_added": CACHE_MISSES}
     save_tuning(args)
     print(json.dumps(finite(out)), flush=True)
 

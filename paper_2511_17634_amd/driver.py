@@ -15,9 +15,50 @@ out largest grid first, the order in which the work queue hands them out.
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 
 from . import xkp
+
+# fields of a cached launch-choice record (Batch.tuning_record)
+TUNING_FIELDS = ("polish_m", "waves", "wg_per_cu", "split", "seed_waves", "seed_wg_per_cu",
+                 "seed_rows_per_thread")
+
+
+def load_tuning_cache(path):
+    """Launch-choice records by key from a JSON cache file ({} if it does not exist); records
+    that lack a field are left out."""
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except FileNotFoundError:
+        return {}
+    if not isinstance(data, dict):
+        raise ValueError(f"tuning cache {path}: not a JSON object")
+    return {k: v for k, v in data.items()
+            if isinstance(v, dict) and all(f in v for f in TUNING_FIELDS)}
+
+
+def store_tuning_cache(path, key, rec):
+    """Adds (or replaces) one record in the JSON cache file; the file is rewritten through a
+    temporary file and a rename, so a reader never sees it half written."""
+    missing = [f for f in TUNING_FIELDS if f not in rec]
+    if missing:
+        raise ValueError(f"tuning record lacks {missing}")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        if not isinstance(data, dict):
+            data = {}
+    except (FileNotFoundError, json.JSONDecodeError):
+        data = {}
+    data[key] = {f: rec[f] for f in TUNING_FIELDS}
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 class Group:
@@ -144,6 +185,12 @@ class Batch:
                                          precision=precision, mode=mode_id,
                                          batch_max_n=self.nmax, polish_m=polish_m,
                                          reorth=reorth)
+        self.config = dict(m=m, precision=int(precision), method=method,
+                           mode=mode if method != "plain" else "none", reorth=reorth,
+                           pipeline=bool(self.pipeline), picard=int(picard),
+                           accumulate=self.acc)
+        self.tuned_from_cache = False
+        self.seed_tuning = None
         self.warm = warm
         self.K = int(picard)
         assert self.K >= 1
@@ -338,13 +385,72 @@ class Batch:
 
     # -- tuning and results -----------------------------------------------------------------
 
-    def autotune(self, steps=2):
+    def autotune(self, steps=2, cache=None):
         """Advance `steps` timesteps eagerly, then time the target call of the next timestep
         over the candidates of xkp_autotune on its real inputs; the chosen polish restart length
         goes into the params, the workgroup count into the context.  With a seed context of
         its own (pipelined chains), the seed call of that timestep is tuned too
         (xkp_autotune_seeds; the result is in `self.seed_tuning`), and a spread-out seed width
-        is kept only if the pipelined chain steps are faster with it.  Resets the chain."""
+        is kept only if the pipelined chain steps are faster with it.  Resets the chain.
+
+        cache: path of a JSON file of launch choices keyed by `tuning_key()` (device, grid
+        sizes and system counts, m, precision, method).  A hit applies the stored choices
+        without timing anything (`tuned_from_cache` is then True); a miss tunes and adds the
+        choices to the file."""
+        import torch
+        key = self.tuning_key() if cache is not None else None
+        if key is not None:
+            rec = load_tuning_cache(cache).get(key)
+            if rec is not None:
+                t = self.apply_tuning(rec)
+                self.tuned_from_cache = True
+                return t
+        self.tuned_from_cache = False
+        t = self._autotune(steps)
+        if key is not None:
+            store_tuning_cache(cache, key, self.tuning_record(t))
+        return t
+
+    def tuning_key(self):
+        """Cache key of this batch's launch choices: the device's architecture and compute
+        units, every group's grid side, channels and targets, and the solver configuration."""
+        import torch
+        p = torch.cuda.get_device_properties(self.dev)
+        arch = getattr(p, "gcnArchName", "") or p.name
+        shape = "+".join(f"{gr.H}x{gr.C}x{gr.N}" for gr in self.groups)
+        c = self.config
+        return (f"{arch}/cu{p.multi_processor_count}/{shape}/m{c['m']}/prec{c['precision']}/"
+                f"{c['method']}/{c['mode']}/{c['reorth']}/"
+                f"{'pipe' if c['pipeline'] else 'serial'}/K{c['picard']}/acc{c['accumulate']}")
+
+    def tuning_record(self, t):
+        """The launch choices the batch runs with (JSON-able): polish restart length, target
+        launch shape and projection placement, the seed context's launch shape and seed
+        width."""
+        ts = self.seed_tuning
+        return {"polish_m": int(self.params.polish_m), "waves": int(t.waves),
+                "wg_per_cu": int(t.wg_per_cu), "split": int(getattr(self.ctx, "split", -1)),
+                "seed_waves": None if ts is None else int(ts.waves),
+                "seed_wg_per_cu": None if ts is None else int(ts.wg_per_cu),
+                "seed_rows_per_thread": None if ts is None else int(ts.seed_rows)}
+
+    def apply_tuning(self, rec):
+        """Set the launch choices of a `tuning_record` instead of timing candidates; returns
+        the Tuning the autotuner would have."""
+        self.params.polish_m = rec["polish_m"]
+        self.ctx.set_launch(rec["waves"], rec["wg_per_cu"])
+        self.ctx.set_projection_split(rec["split"])
+        self.seed_tuning = None
+        if rec.get("seed_waves") is not None and self.with_seeds and self.ctx_seed is not self.ctx:
+            self.ctx_seed.set_launch(rec["seed_waves"], rec["seed_wg_per_cu"])
+            self.ctx_seed.set_seed_width(rec["seed_rows_per_thread"])
+            self.seed_tuning = xkp.Tuning(waves=rec["seed_waves"],
+                                          wg_per_cu=rec["seed_wg_per_cu"],
+                                          seed_rows=rec["seed_rows_per_thread"])
+        return xkp.Tuning(polish_m=rec["polish_m"], wg_per_cu=rec["wg_per_cu"],
+                          waves=rec["waves"], split=rec["split"])
+
+    def _autotune(self, steps):
         import torch
         self.reset()
         for _ in range(steps):

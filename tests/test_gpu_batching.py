@@ -298,6 +298,35 @@ def test_seed_autotune_keeps_results(X):
     assert np.all(b.verify_last() <= 1e-8 * (1 + 1e-6))
 
 
+def test_autotune_cache_reuses_choices(X, tmp_path):
+    """Batch.autotune with a cache file: the first call tunes and stores the choices under the
+    batch's key, a second batch of the same workload takes them from the file without timing,
+    with the same launch choices, and its chain still verifies; a batch of another m is a miss."""
+    import json
+    T, m = 6, 20
+    path = str(tmp_path / "tuning.json")
+    b1, _ = uneven_batch(T, m)
+    t1 = b1.autotune(steps=2, cache=path)
+    assert not b1.tuned_from_cache
+    rec1 = b1.tuning_record(t1)
+    data = json.load(open(path))
+    assert list(data) == [b1.tuning_key()] and data[b1.tuning_key()] == rec1
+    del b1
+    b2, _ = uneven_batch(T, m)
+    t2 = b2.autotune(steps=2, cache=path)
+    assert b2.tuned_from_cache and b2.tuning_record(t2) == rec1
+    assert t2.n_tried == 0 and b2.params.polish_m == rec1["polish_m"]
+    b2.run()
+    s_inf, t_inf = b2.all_infos()
+    assert np.all(s_inf["status"] == X.OK) and np.all(t_inf["status"] == X.OK)
+    assert np.all(b2.verify_last() <= 1e-8 * (1 + 1e-6))
+    del b2
+    b3, _ = uneven_batch(T, 16)
+    assert b3.tuning_key() not in data
+    b3.autotune(steps=2, cache=path)
+    assert not b3.tuned_from_cache and len(json.load(open(path))) == 2
+
+
 def test_uneven_mixed_precision_chain(X):
     """Mixed precision over an uneven two-size, two-channel batch: every solve meets the FP64
     tolerance and the states stay within the chain bound of the FP64 oracle."""
