@@ -97,6 +97,29 @@ def test_traffic_only_for_the_sources_it_was_taken_with(monkeypatch):
     assert bench.traffic_bytes("probe", 10) is None
 
 
+def test_traffic_only_for_the_launch_choices_it_was_taken_with(monkeypatch):
+    """A counter record applies only to the workgroup size, projection placement and (where it
+    has one) seed basis dimension m that the leg runs with."""
+    rec = {"csrc_digest": bench.csrc_digest(), "fetch_kib": 1.0, "write_kib": 2.0,
+           "fetch_scale": 2.0, "write_scale": 1.0, "polish_m": 9, "waves": 8, "split": 0, "m": 30}
+    monkeypatch.setitem(bench.TRAFFIC, "probe", rec)
+    tuned = {"polish_m": 9, "waves": 8, "wg_per_cu": 1, "split": 0, "seed_waves": 8,
+             "seed_wg_per_cu": 1, "seed_rows_per_thread": 0, "m": 30}
+    monkeypatch.setitem(bench.TUNED, "probe", dict(tuned))
+    assert bench.traffic_bytes("probe", 9) == 1024 * 4
+    for k, v in (("m", 40), ("waves", 4), ("split", -1)):
+        monkeypatch.setitem(bench.TUNED, "probe", {**tuned, k: v})
+        assert bench.traffic_bytes("probe", 9) is None, k
+    # any non-negative split is the same placement (launches of their own)
+    monkeypatch.setitem(bench.TUNED, "probe", {**tuned, "split": 7})
+    assert bench.traffic_bytes("probe", 9) == 1024 * 4
+    # a leg without an m of its own matches a record without one
+    rec2 = {k: v for k, v in rec.items() if k != "m"}
+    monkeypatch.setitem(bench.TRAFFIC, "probe", rec2)
+    monkeypatch.setitem(bench.TUNED, "probe", {k: v for k, v in tuned.items() if k != "m"})
+    assert bench.traffic_bytes("probe", 9) == 1024 * 4
+
+
 def test_polish_bytes_and_projection_roofline_by_hand():
     """The polish launch after the projection launches: GMRES bytes plus x0 and b read (16 n)
     per target; the projection launches against the FP64 (or BF16) matrix-core peak."""
