@@ -425,9 +425,14 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                         for (int rr = tid; rr <= j + 1; rr += NT)
                             Hb[(size_t)j * (m + 1) + rr] = rr <= j ? yv[rr] + tot[rr] : hn;
                 }
-                // Givens rotations of column j by the first wavefront: lane i holds entry i of
-                // the column and rotation i, the chain reads them with readlane, and lane i
-                // keeps rotated entry i; the others take the new rotation from the LDS
+                // v_{j+1}'s boundary rows to the neighbours first (every thread has read the
+                // LDS vector in this step's operator application, before the reductions), then
+                // the Givens rotations of column j by the first wavefront while those rows travel:
+                // lane i holds entry i of the column and rotation i, the chain reads them with
+                // readlane, and lane i keeps rotated entry i; the others take the new rotation
+                // from the LDS after the round
+                vbuf[HM + tid] = w;
+                publish_bnd(w);
                 if (tid < 64) {
                     const double hl = tid <= j ? yv[tid] + tot[tid] : 0.0;
                     const double cl = tid < j ? cs[tid] : 0.0, sl = tid < j ? sn[tid] : 0.0;
@@ -450,11 +455,12 @@ __global__ __launch_bounds__(NT) void wide_seed_kernel(const xkp_system *__restr
                         gv[j] = t * rden * gcur;
                     }
                 }
-                __syncthreads();
+                // the neighbours' rows into the halos; the round's barrier also publishes the
+                // rotation to every thread
+                get_halo();
+                if (!(alive = X.end_round())) break;
                 gcur = -sn[j] * gcur;
                 kk = j + 1;
-                // v_{j+1}'s boundary rows to the neighbours, theirs into the halos
-                if (!(alive = exchange_row(w))) break;
                 if (fabs(gcur) <= P.tol * bnorm || brk) break;
             }
             if (!alive) break;
