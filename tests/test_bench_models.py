@@ -150,3 +150,18 @@ def test_paper_context_ratios():
     assert ctx["this_run"]["cpu_oracle_projection_vs_banded_lu_reduction"] == 0.25
     assert "cpu_oracle_projection_vs_banded_lu_reduction" not in bench.paper_context(
         {"value": 1.0, "plain_gmres": {"value": 2.0}})["this_run"]
+
+
+def test_uneven_m_probe_is_skipped_where_m_is_given(monkeypatch):
+    """pick_uneven_m times candidates only when several are given, the leg is autotuned and no
+    stored record fixes m: a stored m wins, a single candidate is taken as is, and without
+    autotuning the workload's own m stays."""
+    from types import SimpleNamespace
+    cfg = SimpleNamespace(m=40)
+    args = SimpleNamespace(uneven_m="30,40,60", no_tune=False, m_probe_steps=10,
+                           tuning_cache=None, reorth="auto")
+    monkeypatch.setitem(bench.FIXED_TUNING, "uneven_project", {"m": 60})
+    assert bench.pick_uneven_m(args, cfg, []) == (60, {})
+    monkeypatch.delitem(bench.FIXED_TUNING, "uneven_project")
+    assert bench.pick_uneven_m(SimpleNamespace(**{**vars(args), "uneven_m": "30"}), cfg, []) == (30, {})
+    assert bench.pick_uneven_m(SimpleNamespace(**{**vars(args), "no_tune": True}), cfg, []) == (40, {})
